@@ -1,0 +1,233 @@
+/*
+ * egosgm.h — C ABI of the MI355X (gfx950) library for dense disparity
+ * estimation in an ego-motion reduced search space (Fućek, Marković, Cvišić,
+ * Petrović: "Dense Disparity Estimation in Ego-motion Reduced Search Space").
+ *
+ * The method (Sec. 2) runs, per stereo frame k:
+ *   disparity prediction  D^{k|k-1}, P^{k|k-1} from D^{k-1}, P^{k-1} and the
+ *                         ego-motion (Sec. 2.1-2.2)          -> warp_disparity
+ *   search windows        [d^{k|k-1} +- 3 sqrt(p^{k|k-1})] (Sec. 2.3)
+ *                                                 -> sgm_windows_from_prediction
+ *   stereo matching       census + 8-path SGM over those windows, matching
+ *                         uncertainty (Sec. 2.3, Eq. 9), left-right check
+ *                         (Sec. 2.4.1)               -> sgm_reduced / sgm_full
+ *   disparity update      pixel-wise Kalman filter (Sec. 2.4, Eq. 10-12)
+ *                                                             -> kalman_update
+ *
+ * General rules for every entry point:
+ *  - Buffer arguments are DEVICE pointers (HIP device memory, e.g. the data
+ *    of torch tensors on the GPU) unless the argument says "host".  The
+ *    caller owns every buffer; the library never allocates, frees or keeps
+ *    caller-visible memory and keeps no state between calls.
+ *  - Images and maps are row-major, pixel p = y*w + x.  Images are uint8
+ *    with a row pitch in bytes (pitch >= w); every map is dense (pitch = w).
+ *  - Every call is asynchronous on `stream` (a hipStream_t; NULL is the
+ *    null stream): it only enqueues work.  Results are ready once the
+ *    stream has been synchronised.  Calls on one stream run in order.
+ *  - Return value: EGOSGM_OK, or a negative egosgm_status.  Arguments are
+ *    validated on the host before anything is enqueued; on an error nothing
+ *    is enqueued (EDEVICE: a launch failed; earlier launches of the same call
+ *    may have been enqueued).  Nothing is printed, nothing throws.
+ *  - Device-side contents that cannot be checked without a copy (window
+ *    bounds, offsets) are documented preconditions.
+ *  - Invalid disparities are -1 in int16 maps and -1.0f in float maps; the
+ *    variance of an invalid pixel is 0 and is never read.
+ */
+#ifndef EGOSGM_H
+#define EGOSGM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EGOSGM_ABI_VERSION 1
+
+/* Largest disparity range and the census window (9 wide, 7 tall: 62 bits). */
+#define EGOSGM_MAX_DISP 256
+#define EGOSGM_CENSUS_BITS 62
+
+typedef enum egosgm_status {
+    EGOSGM_OK = 0,
+    EGOSGM_EINVAL = -1,      /* a pointer, size or parameter is out of range   */
+    EGOSGM_EWORKSPACE = -2,  /* the workspace is NULL or smaller than required */
+    EGOSGM_EDEVICE = -3,     /* a HIP launch or copy failed                    */
+    EGOSGM_EUNSUPPORTED = -4 /* valid request this build does not implement    */
+} egosgm_status;
+
+/* Matcher parameters.  The paper fixes none of them (it names a [3x3]
+ * matching window and S_max = 10 for it, Sec. 2.3.1); the values used for
+ * the street sequences are D = 128, P1 = 10, P2 = 120, S_max = 80, lr_tol = 1. */
+typedef struct egosgm_sgm_params {
+    int32_t max_disp; /* D: disparities 0..D-1, 1 <= D <= 256                  */
+    int32_t p1;       /* penalty for a disparity change of 1, 0 <= p1 <= p2    */
+    int32_t p2;       /* penalty for larger changes, p2 <= 255 - 62 = 193      */
+    int32_t s_max;    /* uncertainty threshold of Eq. 9, >= 0                  */
+    int32_t lr_tol;   /* left-right tolerance in pixels; < 0 disables the check */
+} egosgm_sgm_params;
+
+/* Optional intermediate outputs for inspection (each member nullable; the
+ * struct pointer itself may be NULL).  "slots" is the ragged volume: pixel p
+ * owns entries offsets[p] .. offsets[p+1]-1, entry offsets[p] + (d - lo[p])
+ * holds disparity d; the full range is the case offsets[p] = p*D. */
+typedef struct egosgm_debug {
+    uint64_t* census_left;  /* w*h census codes of the left image            */
+    uint64_t* census_right; /* w*h census codes of the right image           */
+    uint8_t* cost;          /* slots: matching cost C(p,d), 0..62            */
+    uint8_t* paths;         /* 8 x slots: path costs L_r(p,d), direction-major */
+    uint16_t* agg;          /* slots: aggregated cost S(p,d) = sum_r L_r     */
+    int16_t* wta_raw;       /* w*h: winner-takes-all disparity before the LR check */
+} egosgm_debug;
+
+int egosgm_abi_version(void);
+const char* egosgm_status_string(int status);
+
+/* ------------------------------------------------------------------ census
+ * 9x7 census transform (the matching cost of the matcher; the paper names
+ * only its [3x3] matching window, Sec. 2.3.1).  Bit k of out[p] is set when
+ * the k-th neighbour, visited row by row (dy = -3..3 outer, dx = -4..4
+ * inner, centre skipped, coordinates clamped into the image), is darker than
+ * the centre.  Bits 62 and 63 are zero.
+ *   img: w x h uint8, row pitch `pitch` bytes.  out: w*h uint64.          */
+int egosgm_census(const uint8_t* img, int w, int h, int pitch, uint64_t* out, void* stream);
+
+/* ------------------------------------------------------------------ SGM
+ * Workspace bytes for sgm_full / sgm_reduced on a w x h pair with disparity
+ * range max_disp (sized for the full range; a reduced call never needs more).
+ * Returns 0 for out-of-range arguments. */
+size_t egosgm_sgm_workspace_bytes(int w, int h, int max_disp);
+
+/* Full-range semi-global matching (Sec. 2.3 with no prediction: the first
+ * frame and the pixels rejected in the previous frame search the whole
+ * range, Sec. 2.4.1 and Sec. 3).
+ *   cost  C(p,d) = popcount(cL(x,y) ^ cR(x-d,y)), or 62 where x-d < 0;
+ *   paths L_r(p,d) = C + min(L_r(p-r,d), L_r(p-r,d+-1)+P1, m+P2) - m,
+ *         m = min_k L_r(p-r,k), for the 8 directions r (Sec. 2.3: "eight-path
+ *         configuration"; the recurrence of Hirschmüller 2008);
+ *   S(p,d) = sum_r L_r(p,d);  d* = smallest argmin_d S(p,d);
+ *   disp_sub = d* + (a-c)/(2(a-2b+c)) with a,b,c = S(d*-1), S(d*), S(d*+1)
+ *         when d* is inside the window and a-2b+c > 0, else d*;
+ *   var_meas = n_l + n_r, the neighbours counted on each side of d* while the
+ *         running sum of S(d*+-j) - S(d*) stays below s_max (Eq. 9);
+ *   disp_right(x') = smallest argmin_d S(x'+d, d) over the left pixels whose
+ *         window holds d, or -1;
+ *   LR check: d* is kept when x-d* >= 0, disp_right(x-d*) is valid and
+ *         |d* - disp_right(x-d*)| <= lr_tol; rejected pixels are written as
+ *         -1 / -1.0f / 0.
+ * Inputs: left, right (w x h uint8, pitch).  Outputs (w*h each): disp_wta
+ * int16, disp_sub float, var_meas float, disp_right int16 (nullable).
+ * workspace: device memory of at least egosgm_sgm_workspace_bytes(w,h,D). */
+int sgm_full(const uint8_t* left, const uint8_t* right, int w, int h, int pitch,
+             const egosgm_sgm_params* params, int16_t* disp_wta, float* disp_sub,
+             float* var_meas, int16_t* disp_right, const egosgm_debug* debug,
+             void* workspace, size_t workspace_bytes, void* stream);
+
+/* Workspace bytes for sgm_windows_from_prediction on a w x h map. */
+size_t egosgm_windows_workspace_bytes(int w, int h);
+
+/* Per-pixel search windows from the predicted map (Sec. 2.3: the interval
+ * [d +- 3 sqrt(p)] around the prediction; pixels without a usable prediction
+ * search the whole range, Sec. 2.4.1):
+ *   a prediction is usable when d_pred >= 0 (and <= 65536) and, when the
+ *   radius comes from the variance, p_pred >= 0;
+ *   centre c = floorf(d_pred + 0.5f); radius r = r_fixed if r_fixed >= 0,
+ *   else ceilf(k_sigma * sqrtf(p_pred)), both in float32; r clamped to
+ *   [r_min, r_max]; lo = max(0, c-r), hi = min(D-1, c+r); an unusable
+ *   prediction or an empty interval gives [0, D-1].
+ *   offsets[p] = sum of (hi-lo+1) over the pixels before p, offsets[w*h] =
+ *   the total (w*h+1 entries).
+ * d_pred, p_pred: w*h float (p_pred may be NULL when r_fixed >= 0).
+ * lo, hi: w*h int16.  workspace: egosgm_windows_workspace_bytes(w,h). */
+int sgm_windows_from_prediction(const float* d_pred, const float* p_pred, int w, int h,
+                                float k_sigma, int r_fixed, int r_min, int r_max,
+                                int max_disp, int16_t* lo, int16_t* hi, uint32_t* offsets,
+                                void* workspace, size_t workspace_bytes, void* stream);
+
+/* Reduced-range semi-global matching (Sec. 2.3): sgm_full restricted to the
+ * per-pixel windows [lo[p], hi[p]]; predecessor entries outside the
+ * predecessor's window count as +infinity and m is the minimum over that
+ * window (with every window [0, D-1] this is exactly sgm_full).
+ * lo, hi, offsets: as written by sgm_windows_from_prediction; preconditions
+ * (not checked): 0 <= lo <= hi < D, offsets[0] = 0, offsets[p+1]-offsets[p] =
+ * hi-lo+1.  Other arguments as sgm_full; debug volumes hold offsets[w*h]
+ * entries (paths: 8 blocks of w*h*D entries, the first offsets[w*h] of each
+ * filled). */
+int sgm_reduced(const uint8_t* left, const uint8_t* right, int w, int h, int pitch,
+                const int16_t* lo, const int16_t* hi, const uint32_t* offsets,
+                const egosgm_sgm_params* params, int16_t* disp_wta, float* disp_sub,
+                float* var_meas, int16_t* disp_right, const egosgm_debug* debug,
+                void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------ warp
+ * Disparity-space motion matrix H = Gamma T Gamma^-1 (Eq. 1 and 4) with the
+ * principal point added to Gamma (the paper's Gamma is cx = cy = 0):
+ * Gamma = [[f,0,cx,0],[0,f,cy,0],[0,0,0,f b],[0,0,1,0]], T = [R t; 0 1].
+ * R (row-major 3x3) and t (metres) map previous-frame camera coordinates to
+ * the current frame, M^k = R M^{k-1} + t as in Eq. 2 (so driving forward by
+ * 1 m is t = (0,0,-1)).  Computed in double on the host and rounded once to
+ * float: H (host, 16 floats, row-major).  Host only; enqueues nothing. */
+int egosgm_warp_matrix(const double* R, const double* t, double f, double cx, double cy,
+                       double baseline, float* H);
+
+/* Disparity prediction (Sec. 2.2): every source pixel with d > 0 moves to
+ * omega* = H (x, y, d, 1) (Eq. 3), normalised by its fourth component; its
+ * variance is predicted as Phi^2 p + q with Phi = d'/d (Eq. 5-6).
+ * Which source lands where, and which wins a collision, is decided in
+ * float32 with H rounded to float32, in this order:
+ * omega_i = ((H_i0 x + H_i1 y) + H_i2 d) + H_i3, x' = omega_0/omega_3,
+ * y' = omega_1/omega_3, d' = d/omega_3; the target pixel is
+ * (floorf(x'+0.5f), floorf(y'+0.5f)); sources with omega_3 <= 0 or a target
+ * outside the image are dropped.  Collisions keep the largest d' (Sec. 2.2.2:
+ * the nearest surface), then the smaller source pixel index; the result does
+ * not depend on thread order.  The kept values, d' and (d'/d)^2 p + q, are
+ * then evaluated in double with the double H and rounded once to float.
+ * Targets that receive nothing are invalid (-1.0f, variance 0).
+ * d_prev, p_prev: w*h float; R, t: host (see egosgm_warp_matrix); q > 0.
+ * d_pred, p_pred: w*h float (must not alias d_prev / p_prev).  zbuf: w*h
+ * uint64 scratch owned by the caller (contents on entry are ignored, on
+ * return undefined). */
+int warp_disparity(const float* d_prev, const float* p_prev, int w, int h,
+                   const double* R, const double* t, double f, double cx, double cy,
+                   double baseline, float q, float* d_pred, float* p_pred, uint64_t* zbuf,
+                   void* stream);
+
+/* ------------------------------------------------------------------ update
+ * Pixel-wise Kalman update (Sec. 2.4, Eq. 10-12), float32 in this order:
+ *   K = p/(p + r); d = d_pred + K (z - d_pred); p = (1 - K) p_pred.
+ * A prediction is usable when d_pred >= 0 and p_pred > 0; a measurement is
+ * valid when z >= 0 and r >= 0.  Prediction only: invalid (-1, 0) unless
+ * keep_unmeasured, then (d_pred, p_pred); measurement only: (z, r) (the first
+ * frame); neither: (-1, 0).
+ * d_pred, p_pred, d_meas (z), r_meas (r): n floats; d_out, p_out: n floats
+ * (may alias d_pred / p_pred element for element). */
+int kalman_update(const float* d_pred, const float* p_pred, const float* d_meas,
+                  const float* r_meas, int n, int keep_unmeasured, float* d_out, float* p_out,
+                  void* stream);
+
+/* ------------------------------------------------------------------ timing
+ * Opt-in profiling aid (the one piece of state the library keeps): while
+ * enabled, each stage the library enqueues is bracketed by a pair of HIP
+ * events recorded on the caller's stream.  egosgm_timing_read waits for the
+ * recorded events, adds the elapsed milliseconds and launch counts per stage
+ * into ms[] / count[] (n_stages entries, see egosgm_stage), and forgets them.
+ * Not thread-safe with concurrent callers on several host threads. */
+typedef enum egosgm_stage {
+    EGOSGM_STAGE_CENSUS = 0,  /* census of a pair (one kernel)                   */
+    EGOSGM_STAGE_WINDOWS = 1, /* windows: row scan + offsets (two kernels)       */
+    EGOSGM_STAGE_COST = 2,    /* matching cost per search slot (one kernel)      */
+    EGOSGM_STAGE_PATHS = 3,   /* 8-path aggregation (one kernel)                 */
+    EGOSGM_STAGE_SELECT = 4,  /* WTA/subpixel/uncertainty/right map, LR (two kernels) */
+    EGOSGM_STAGE_WARP = 5,    /* z-buffer clear, scatter, decode (three kernels) */
+    EGOSGM_STAGE_KALMAN = 6,  /* Kalman update (one kernel)                      */
+    EGOSGM_STAGE_COUNT = 7
+} egosgm_stage;
+
+int egosgm_timing_enable(int on);
+int egosgm_timing_read(double* ms, int* count, int n_stages);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EGOSGM_H */

@@ -399,42 +399,40 @@ int orc_warp_matrix(const double* R, const double* t, double f, double cx, doubl
     return 0;
 }
 
-static uint32_t f2u(float v) { uint32_t u; memcpy(&u, &v, 4); return u; }
-
 /* Disparity prediction (Sec. 2.2).  Each source pixel with d > 0 is moved by
  * omega* = H omega (Eq. 3) and normalised by its fourth component; its
  * variance is predicted as Phi^2 p + q with Phi = d'/d (Eq. 5-6).  The
  * predicted pixel is (x', y') rounded half up.  On collisions the largest d'
- * is kept (Sec. 2.2.2); equal d' keep the smaller p'.  Sources whose fourth
- * component is not positive or whose target leaves the image are dropped.
+ * is kept (Sec. 2.2.2); the paper is silent on equal d', which keep the
+ * source with the smaller pixel index.  Sources whose fourth component is
+ * not positive or whose target leaves the image are dropped.
  *
  * Which source wins each target is an integer decision taken from floating
  * point, so it is taken in float32 with H rounded to float32 and this exact
  * evaluation order: omega_i = ((H_i0 x + H_i1 y) + H_i2 d) + H_i3,
- * x' = omega_0/omega_3, y' = omega_1/omega_3, d' = d/omega_3, Phi = d'/d,
- * p' = (Phi Phi) p + q.  The values written for the winner are then
- * evaluated in double with the double H. */
+ * x' = omega_0/omega_3, y' = omega_1/omega_3, d' = d/omega_3.  The values
+ * written for the winner, d' = omega_2/omega_3 and p' = Phi^2 p + q, are
+ * then evaluated in double with the double H.  d_key_f32 (nullable) gets the
+ * float32 d' the z-buffer compared. */
 int orc_warp(const float* d_prev, const float* p_prev, int w, int h,
              const double* R, const double* t, double f, double cx, double cy,
              double b, double q, double* d_pred, double* p_pred,
-             int32_t* winner, float* d_pred_f32, float* p_pred_f32) {
+             int32_t* winner, float* d_key_f32) {
     if (!d_prev || !p_prev || !d_pred || !p_pred || w <= 0 || h <= 0) return -1;
     if (!(q > 0.0)) return -1;
     double Hd[16];
     if (orc_warp_matrix(R, t, f, cx, cy, b, Hd)) return -1;
     float Hf[16];
     for (int i = 0; i < 16; ++i) Hf[i] = (float)Hd[i];
-    const float qf = (float)q;
     const size_t n = (size_t)w * (size_t)h;
-    uint64_t* key = malloc(n * sizeof(uint64_t));
+    float* best = malloc(n * sizeof(float));
     int32_t* src = malloc(n * sizeof(int32_t));
-    if (!key || !src) { free(key); free(src); return -2; }
-    for (size_t i = 0; i < n; ++i) { key[i] = ~(uint64_t)0; src[i] = -1; }
+    if (!best || !src) { free(best); free(src); return -2; }
+    for (size_t i = 0; i < n; ++i) { best[i] = 0.0f; src[i] = -1; }
 
     for (int y = 0; y < h; ++y)
         for (int x = 0; x < w; ++x) {
             const float d = d_prev[y * w + x];
-            const float p = p_prev[y * w + x];
             if (!(d > 0.0f)) continue;
             const float xf = (float)x, yf = (float)y;
             const float o0 = ((Hf[0] * xf + Hf[1] * yf) + Hf[2] * d) + Hf[3];
@@ -442,14 +440,13 @@ int orc_warp(const float* d_prev, const float* p_prev, int w, int h,
             const float o3 = ((Hf[12] * xf + Hf[13] * yf) + Hf[14] * d) + Hf[15];
             if (!(o3 > 0.0f)) continue;
             const float xp = o0 / o3, yp = o1 / o3, dp = d / o3;
-            const float phi = dp / d;
-            const float pp = (phi * phi) * p + qf;
             const float vx = xp + 0.5f, vy = yp + 0.5f;
             if (!(vx >= 0.0f) || !(vx < (float)w) || !(vy >= 0.0f) || !(vy < (float)h)) continue;
             const int xi = (int)floorf(vx), yi = (int)floorf(vy);
-            const uint64_t k = ((uint64_t)(0xFFFFFFFFu - f2u(dp)) << 32) | (uint64_t)f2u(pp);
             const size_t tgt = (size_t)yi * (size_t)w + (size_t)xi;
-            if (k < key[tgt]) { key[tgt] = k; src[tgt] = y * w + x; }
+            /* sources are visited in increasing index, so a strict > keeps
+             * the smaller index on equal d' */
+            if (src[tgt] < 0 || dp > best[tgt]) { best[tgt] = dp; src[tgt] = y * w + x; }
         }
 
     for (size_t i = 0; i < n; ++i) {
@@ -457,8 +454,7 @@ int orc_warp(const float* d_prev, const float* p_prev, int w, int h,
         if (src[i] < 0) {
             d_pred[i] = -1.0;
             p_pred[i] = 0.0;
-            if (d_pred_f32) d_pred_f32[i] = -1.0f;
-            if (p_pred_f32) p_pred_f32[i] = 0.0f;
+            if (d_key_f32) d_key_f32[i] = -1.0f;
             continue;
         }
         const int sx = src[i] % w, sy = src[i] / w;
@@ -471,12 +467,9 @@ int orc_warp(const float* d_prev, const float* p_prev, int w, int h,
         const double phi = dn / d;
         d_pred[i] = dn;
         p_pred[i] = phi * phi * p + q;
-        const uint32_t hiw = (uint32_t)(key[i] >> 32), low = (uint32_t)key[i];
-        const uint32_t db = 0xFFFFFFFFu - hiw;
-        if (d_pred_f32) memcpy(&d_pred_f32[i], &db, 4);
-        if (p_pred_f32) memcpy(&p_pred_f32[i], &low, 4);
+        if (d_key_f32) d_key_f32[i] = best[i];
     }
-    free(key);
+    free(best);
     free(src);
     return 0;
 }

@@ -83,14 +83,15 @@ int orc_sgm(const uint8_t* left, const uint8_t* right, int w, int h, int max_dis
 int orc_warp_matrix(const double* R, const double* t, double f, double cx, double cy,
                     double b, double* H);
 
-/* Disparity-map warp with z-buffer.  Target pixel and z-order are decided
- * in float32 with H rounded to float32; the kept disparity and variance are
- * then evaluated in double for the winning source.  winner (nullable) gets
- * the source pixel index or -1. */
+/* Disparity-map warp with z-buffer.  Target pixel and z-order (largest d',
+ * then smallest source index) are decided in float32 with H rounded to
+ * float32; the kept disparity and variance are then evaluated in double for
+ * the winning source.  winner (nullable) gets the source pixel index or -1;
+ * d_key_f32 (nullable) the float32 d' that won. */
 int orc_warp(const float* d_prev, const float* p_prev, int w, int h,
              const double* R, const double* t, double f, double cx, double cy,
              double b, double q, double* d_pred, double* p_pred,
-             int32_t* winner, float* d_pred_f32, float* p_pred_f32);
+             int32_t* winner, float* d_key_f32);
 
 /* Pixel-wise Kalman update in double. */
 int orc_kalman(const float* d_pred, const float* p_pred, const float* z,

@@ -168,20 +168,18 @@ def warp_matrix(R, t, f, cx, cy, b):
 
 def warp(d_prev, p_prev, R, t, f, cx, cy, b, q):
     """Returns dict d_pred/p_pred (float64 values), winner (int32 source
-    index or -1) and d_pred_f32/p_pred_f32 (the float32 values of the
-    winner that the z-buffer compared)."""
+    index or -1) and d_key_f32 (the float32 d' the z-buffer compared)."""
     d_prev = np.ascontiguousarray(d_prev, dtype=np.float32)
     p_prev = np.ascontiguousarray(p_prev, dtype=np.float32)
     h, w = d_prev.shape
     R = np.ascontiguousarray(R, dtype=np.float64).ravel()
     t = np.ascontiguousarray(t, dtype=np.float64).ravel()
     out = dict(d_pred=np.zeros((h, w)), p_pred=np.zeros((h, w)),
-               winner=np.zeros((h, w), np.int32), d_pred_f32=np.zeros((h, w), np.float32),
-               p_pred_f32=np.zeros((h, w), np.float32))
+               winner=np.zeros((h, w), np.int32), d_key_f32=np.zeros((h, w), np.float32))
     _check(lib().orc_warp(_p(d_prev), _p(p_prev), w, h, _p(R), _p(t), C.c_double(f),
                           C.c_double(cx), C.c_double(cy), C.c_double(b), C.c_double(q),
                           _p(out["d_pred"]), _p(out["p_pred"]), _p(out["winner"]),
-                          _p(out["d_pred_f32"]), _p(out["p_pred_f32"])), "warp")
+                          _p(out["d_key_f32"])), "warp")
     return out
 
 

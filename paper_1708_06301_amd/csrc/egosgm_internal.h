@@ -1,0 +1,62 @@
+// Internal interface between the C ABI (egosgm_api.hip) and the kernels
+// (egosgm_kernels.hip).  Not installed, not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace egosgm {
+
+constexpr int kCensusBits = 62;
+constexpr int kMaxDisp = 256;
+constexpr int kNumPaths = 8;
+
+// Views of the search windows: either the full range (lo = 0, hi = D-1,
+// offset = p*D) or the ragged arrays of sgm_windows_from_prediction.
+struct Windows {
+    const int16_t* lo;       // nullptr: full range
+    const int16_t* hi;
+    const uint32_t* off;     // w*h+1 entries
+    int max_disp;
+};
+
+struct SgmLaunch {
+    const uint64_t* census_l;
+    const uint64_t* census_r;
+    int w, h;
+    Windows win;
+    int p1, p2, s_max, lr_tol;
+    uint8_t* cost;           // matching cost per search slot
+    uint32_t* key_r;         // w*h right-map keys (S << 9 | d), cleared by the census pass
+    uint8_t* vol;            // 8 path volumes, direction-major
+    size_t vol_stride;       // entries per direction block (w*h*D)
+    int16_t* disp_wta;
+    float* disp_sub;
+    float* var_meas;
+    int16_t* disp_right;     // nullable
+    uint16_t* agg;           // nullable (debug)
+    int16_t* wta_raw;        // nullable (debug)
+};
+
+hipError_t launch_census(const uint8_t* img, int w, int h, int pitch, uint64_t* out,
+                         hipStream_t s);
+hipError_t launch_census_pair(const uint8_t* left, const uint8_t* right, int w, int h,
+                              int pitch, uint64_t* out_l, uint64_t* out_r, uint32_t* clear,
+                              hipStream_t s);
+hipError_t launch_sgm_cost(const SgmLaunch& a, hipStream_t s);
+hipError_t launch_sgm_paths(const SgmLaunch& a, hipStream_t s);
+hipError_t launch_sgm_select(const SgmLaunch& a, hipStream_t s);
+hipError_t launch_copy_slots(const SgmLaunch& a, const uint8_t* src, uint8_t* dst, hipStream_t s);
+hipError_t launch_windows(const float* d_pred, const float* p_pred, int w, int h,
+                          float k_sigma, int r_fixed, int r_min, int r_max, int max_disp,
+                          int16_t* lo, int16_t* hi, uint32_t* off, uint32_t* row_tot,
+                          hipStream_t s);
+hipError_t launch_warp(const float* d_prev, const float* p_prev, int w, int h, const float* H,
+                       const double* Hd, double q, float* d_pred, float* p_pred,
+                       unsigned long long* zbuf, hipStream_t s);
+hipError_t launch_kalman(const float* d_pred, const float* p_pred, const float* z,
+                         const float* r, int n, int keep, float* d_out, float* p_out,
+                         hipStream_t s);
+
+}  // namespace egosgm

@@ -1,0 +1,883 @@
+// HIP kernels for gfx950 (CDNA4, wave64): census, search windows, 8-path
+// semi-global matching over ragged per-pixel windows, its epilogue (WTA,
+// subpixel, uncertainty, right map, left-right check), the disparity-space
+// warp with a z-buffer, and the pixel-wise Kalman update.
+//
+// Floating-point steps whose results decide integers (warp target pixel and
+// z-order, window centre and radius) must round exactly as written: this file
+// is compiled with contraction off (the pragma below repeats it), and with
+// correctly rounded float32 division and square root.  HIP's __fsqrt_rn is
+// not used on purpose: without OCML_BASIC_ROUNDED_OPERATIONS it maps to the
+// approximate native square root.
+#include "egosgm_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace egosgm {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kInf = 0x3fff;
+
+// ------------------------------------------------------------------ census
+constexpr int kCtW = 64;          // output tile width  (one wave per row)
+constexpr int kCtH = kBlock / kCtW;  // output tile height
+constexpr int kHaloX = 4, kHaloY = 3;
+
+__global__ __launch_bounds__(kBlock) void census_kernel(const uint8_t* __restrict__ img0,
+                                                        const uint8_t* __restrict__ img1,
+                                                        int w, int h, int pitch,
+                                                        uint64_t* __restrict__ out0,
+                                                        uint64_t* __restrict__ out1,
+                                                        uint32_t* __restrict__ clear) {
+    const uint8_t* img = blockIdx.z ? img1 : img0;
+    uint64_t* out = blockIdx.z ? out1 : out0;
+    constexpr int TW = kCtW + 2 * kHaloX, TH = kCtH + 2 * kHaloY;
+    __shared__ uint8_t tile[TH][TW];
+    const int x0 = blockIdx.x * kCtW, y0 = blockIdx.y * kCtH;
+    for (int i = threadIdx.x; i < TW * TH; i += kBlock) {
+        const int ty = i / TW, tx = i - ty * TW;
+        const int gx = min(max(x0 + tx - kHaloX, 0), w - 1);
+        const int gy = min(max(y0 + ty - kHaloY, 0), h - 1);
+        tile[ty][tx] = img[(size_t)gy * pitch + gx];
+    }
+    __syncthreads();
+    const int lx = threadIdx.x % kCtW, ly = threadIdx.x / kCtW;
+    const int x = x0 + lx, y = y0 + ly;
+    if (x >= w || y >= h) return;
+    const int c = tile[ly + kHaloY][lx + kHaloX];
+    uint64_t code = 0;
+    int k = 0;
+#pragma unroll
+    for (int dy = 0; dy < 2 * kHaloY + 1; ++dy) {
+#pragma unroll
+        for (int dx = 0; dx < 2 * kHaloX + 1; ++dx) {
+            if (dy == kHaloY && dx == kHaloX) continue;
+            code |= (uint64_t)(tile[ly + dy][lx + dx] < c) << k;
+            ++k;
+        }
+    }
+    out[(size_t)y * w + x] = code;
+    if (clear && blockIdx.z == 0) clear[(size_t)y * w + x] = 0xffffffffu;
+}
+
+// ------------------------------------------------------------------ windows
+__device__ inline void window_from_prediction(float d, const float* p_pred, int p, float k_sigma,
+                                              int r_fixed, int r_min, int r_max, int D,
+                                              int& lo, int& hi) {
+    lo = 0;
+    hi = D - 1;
+    bool usable = d >= 0.0f && d <= 65536.0f;
+    int r = r_fixed;
+    if (usable && r_fixed < 0) {
+        const float pv = p_pred[p];
+        if (!(pv >= 0.0f)) {
+            usable = false;
+        } else {
+            const float rf = ceilf(k_sigma * sqrtf(pv));
+            r = rf >= (float)r_max ? r_max : (rf <= (float)r_min ? r_min : (int)rf);
+        }
+    }
+    if (usable) {
+        r = min(max(r, r_min), r_max);
+        const int c = (int)floorf(d + 0.5f);
+        const int l2 = max(0, c - r), u2 = min(D - 1, c + r);
+        if (l2 <= u2) {
+            lo = l2;
+            hi = u2;
+        }
+    }
+}
+
+// Block-wide exclusive scan of one value per thread; returns the block total.
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t& excl, uint32_t* ws) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) ws[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) {
+        const uint32_t s = ws[i];
+        if (i < wave) before += s;
+        total += s;
+    }
+    __syncthreads();
+    excl = before + inc - v;
+    return total;
+}
+
+__global__ __launch_bounds__(kBlock) void windows_row_kernel(
+    const float* __restrict__ d_pred, const float* __restrict__ p_pred, int w, float k_sigma,
+    int r_fixed, int r_min, int r_max, int D, int16_t* __restrict__ lo, int16_t* __restrict__ hi,
+    uint32_t* __restrict__ off, uint32_t* __restrict__ row_tot) {
+    __shared__ uint32_t ws[kBlock / 64];
+    const int y = blockIdx.x;
+    uint32_t running = 0;
+    for (int base = 0; base < w; base += kBlock) {
+        const int x = base + threadIdx.x;
+        uint32_t width = 0;
+        const size_t p = (size_t)y * w + x;
+        if (x < w) {
+            int l, u;
+            window_from_prediction(d_pred[p], p_pred, (int)p, k_sigma, r_fixed, r_min, r_max, D,
+                                   l, u);
+            lo[p] = (int16_t)l;
+            hi[p] = (int16_t)u;
+            width = (uint32_t)(u - l + 1);
+        }
+        uint32_t excl;
+        const uint32_t tot = block_exclusive_scan(width, excl, ws);
+        if (x < w) off[p] = running + excl;
+        running += tot;
+    }
+    if (threadIdx.x == 0) row_tot[y] = running;
+}
+
+__global__ __launch_bounds__(kBlock) void windows_offset_kernel(int w, int h,
+                                                                uint32_t* __restrict__ off,
+                                                                const uint32_t* __restrict__ row_tot) {
+    __shared__ uint32_t ws[kBlock / 64];
+    const int y = blockIdx.x;
+    uint32_t part = 0;
+    for (int i = threadIdx.x; i < y; i += kBlock) part += row_tot[i];
+    uint32_t excl;
+    const uint32_t base = block_exclusive_scan(part, excl, ws);
+    for (int x = threadIdx.x; x < w; x += kBlock) off[(size_t)y * w + x] += base;
+    if (y == h - 1 && threadIdx.x == 0) off[(size_t)h * w] = base + row_tot[h - 1];
+}
+
+// ------------------------------------------------------------------ SGM common
+template <bool FULL>
+__device__ inline void window_of(const Windows& win, int p, int& lo, int& hi, uint32_t& off) {
+    if (FULL) {
+        lo = 0;
+        hi = win.max_disp - 1;
+        off = (uint32_t)p * (uint32_t)win.max_disp;
+    } else {
+        lo = win.lo[p];
+        hi = win.hi[p];
+        off = win.off[p];
+    }
+}
+
+// Minimum over each 16-lane row, left in every lane of the row (DPP:
+// quad_perm xor 1, xor 2, then row_ror 4 and 8).
+__device__ inline int row_min16(int v) {
+    v = min(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_mov_dpp(v, 0x124, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false));
+    return v;
+}
+
+// Minimum over a lane group of G (16, 32 or 64) lanes; every lane of the
+// group must be active.  Rows are combined through scalar registers.
+template <int G>
+__device__ inline int group_min(int v) {
+    v = row_min16(v);
+    if (G == 16) return v;
+    const int r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+    const int r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+    if (G == 64) return min(min(r0, r1), min(r2, r3));
+    return (threadIdx.x & 32) ? min(r2, r3) : min(r0, r1);
+}
+
+// Orders this lane group's LDS writes before its later LDS reads.  A wave's
+// LDS instructions execute in issue order, so only the compiler has to be
+// stopped from moving them; no wait on outstanding global stores is needed.
+__device__ inline void lds_order() { __asm__ volatile("" ::: "memory"); }
+
+// ------------------------------------------------------------------ cost
+// C(p, d) = popcount(cL(x,y) ^ cR(x-d,y)), or 62 where x-d < 0, written once
+// per search slot (uint8, ragged layout).  One block per 64-pixel row
+// segment stages the left codes and the right codes x0-(D-1) .. x0+63 in LDS.
+constexpr int kSeg = 64;
+
+template <int G, bool FULL>
+__global__ __launch_bounds__(kBlock) void cost_kernel(SgmLaunch a) {
+    constexpr int GPB = kBlock / G;
+    __shared__ uint64_t crs[kSeg + kMaxDisp];
+    __shared__ uint64_t cls[kSeg];
+    const int W = a.w, D = a.win.max_disp;
+    const int y = blockIdx.y, x0 = blockIdx.x * kSeg;
+    const int base = x0 - (D - 1);
+    const uint64_t* rowl = a.census_l + (size_t)y * W;
+    const uint64_t* rowr = a.census_r + (size_t)y * W;
+    for (int i = threadIdx.x; i < kSeg + D - 1; i += kBlock) {
+        const int xr = base + i;
+        crs[i] = (xr >= 0 && xr < W) ? rowr[xr] : 0ull;
+    }
+    for (int i = threadIdx.x; i < kSeg; i += kBlock) cls[i] = (x0 + i < W) ? rowl[x0 + i] : 0ull;
+    __syncthreads();
+    const int grp = threadIdx.x / G, lane = threadIdx.x % G;
+    for (int i = grp; i < kSeg; i += GPB) {
+        const int x = x0 + i;
+        if (x >= W) break;
+        int lo, hi;
+        uint32_t off;
+        window_of<FULL>(a.win, y * W + x, lo, hi, off);
+        const uint64_t cl = cls[i];
+        for (int sl = lane; sl <= hi - lo; sl += G) {
+            const int d = lo + sl;
+            const int c = (x - d >= 0) ? __popcll(cl ^ crs[i + (D - 1) - d]) : kCensusBits;
+            a.cost[off + (uint32_t)sl] = (uint8_t)c;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ SGM paths
+// Scanline tasks, longest first: rows left-to-right and right-to-left,
+// columns down and up, then the four diagonal families (W+H-1 lines each).
+__device__ inline void decode_task(int t, int W, int H, int& dir, int& x, int& y, int& len) {
+    if (t < 2 * H) {
+        dir = t / H;
+        y = t - dir * H;
+        x = dir == 0 ? 0 : W - 1;
+        len = W;
+        return;
+    }
+    t -= 2 * H;
+    if (t < 2 * W) {
+        dir = 2 + t / W;
+        x = t - (dir - 2) * W;
+        y = dir == 2 ? 0 : H - 1;
+        len = H;
+        return;
+    }
+    t -= 2 * W;
+    const int nd = W + H - 1;
+    dir = 4 + t / nd;
+    const int i = t - (dir - 4) * nd;
+    switch (dir) {
+        case 4:  // (1,1)
+            if (i < W) { x = i; y = 0; } else { x = 0; y = i - W + 1; }
+            len = min(W - x, H - y);
+            break;
+        case 5:  // (-1,1)
+            if (i < W) { x = i; y = 0; } else { x = W - 1; y = i - W + 1; }
+            len = min(x + 1, H - y);
+            break;
+        case 6:  // (1,-1)
+            if (i < W) { x = i; y = H - 1; } else { x = 0; y = i - W; }
+            len = min(W - x, y + 1);
+            break;
+        default:  // (-1,-1)
+            if (i < W) { x = i; y = H - 1; } else { x = W - 1; y = i - W; }
+            len = min(x + 1, y + 1);
+            break;
+    }
+}
+
+__device__ inline void dir_step(int dir, int& dx, int& dy) {
+    // (1,0) (-1,0) (0,1) (0,-1) (1,1) (-1,1) (1,-1) (-1,-1)
+    dx = (dir == 0 || dir == 4 || dir == 6) ? 1 : ((dir == 1 || dir == 5 || dir == 7) ? -1 : 0);
+    dy = (dir == 2 || dir == 4 || dir == 5) ? 1 : ((dir == 3 || dir == 6 || dir == 7) ? -1 : 0);
+}
+
+// Costs of this lane's slots s = lane + G*k of one pixel's window.
+template <int G, int K>
+__device__ inline void load_costs(const uint8_t* __restrict__ cost, uint32_t off, int w, int lane,
+                                  int (&c)[K]) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int s = lane + G * k;
+        c[k] = (int)cost[off + (uint32_t)min(s, w - 1)];
+    }
+}
+
+// One lane group of G lanes walks one scanline; lane l owns slots
+// s = l + G*k (k < K) of each pixel's window.  The previous pixel's path
+// costs sit in a per-group LDS row (ping-pong) indexed by disparity minus
+// the previous window's lo, so ragged windows realign by plain indexing.
+// Window metadata is prefetched 2*PF steps ahead and costs PF steps ahead,
+// unconditionally (clamped to the scanline's last pixel) and into ring
+// slots named at compile time, so a step waits only on memory operations
+// issued PF steps earlier.  A zero predecessor row over the first window
+// makes the first step L = C.
+template <int G, int K, bool FULL, int PF>
+__global__ __launch_bounds__(kBlock) void sgm_paths_kernel(SgmLaunch a, int n_tasks) {
+    constexpr int GPB = kBlock / G;
+    constexpr int RM = 2 * PF;
+    __shared__ uint16_t lds[GPB][2][G * K];
+    const int grp = threadIdx.x / G, lane = threadIdx.x % G;
+    const int task = blockIdx.x * GPB + grp;
+    if (task >= n_tasks) return;
+    const int W = a.w, H = a.h;
+    int dir, x, y, len, dx, dy;
+    decode_task(task, W, H, dir, x, y, len);
+    dir_step(dir, dx, dy);
+    uint8_t* __restrict__ vol = a.vol + (size_t)dir * a.vol_stride;
+    const uint8_t* __restrict__ cost = a.cost;
+    uint16_t* b0 = lds[grp][0];
+    uint16_t* b1 = lds[grp][1];
+    const int p1 = a.p1, p2 = a.p2;
+    const int dp = dy * W + dx;
+    const int p0 = y * W + x;
+    const int p_last = p0 + (len - 1) * dp;
+
+    int mlo[RM], mw[RM];
+    uint32_t moff[RM];
+    auto load_meta = [&](int j, int pix) {
+        int hi;
+        window_of<FULL>(a.win, pix, mlo[j], hi, moff[j]);
+        mw[j] = hi - mlo[j] + 1;
+    };
+#pragma unroll
+    for (int j = 0; j < RM; ++j) load_meta(j, j < len ? p0 + j * dp : p_last);
+    int cst[PF][K];
+#pragma unroll
+    for (int j = 0; j < PF; ++j) load_costs<G, K>(cost, moff[j], mw[j], lane, cst[j]);
+
+    // zero predecessor over the first window
+    for (int s = lane; s < G * K; s += G) b1[s] = 0;
+    lds_order();
+    int lo_q = mlo[0], w_q = mw[0], m_q = 0;
+    int p = p0;
+
+    auto step = [&](int ti, int tc, int parity) {
+        const int lo_c = mlo[ti], w_c = mw[ti];
+        const uint32_t off_c = moff[ti];
+        uint16_t* cur = parity ? b1 : b0;
+        const uint16_t* prv = parity ? b0 : b1;
+        int mn = kInf;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int s = lane + G * k;
+            if (s < w_c) {
+                const int j = lo_c + s - lo_q;
+                const int v0 = (unsigned)j < (unsigned)w_q ? (int)prv[j] : kInf;
+                const int vm = (unsigned)(j - 1) < (unsigned)w_q ? (int)prv[j - 1] : kInf;
+                const int vp = (unsigned)(j + 1) < (unsigned)w_q ? (int)prv[j + 1] : kInf;
+                const int best = min(min(v0, min(vm, vp) + p1), m_q + p2);
+                const int L = cst[tc][k] + best - m_q;
+                cur[s] = (uint16_t)L;
+                vol[off_c + (uint32_t)s] = (uint8_t)L;
+                mn = min(mn, L);
+            }
+        }
+        lds_order();
+        m_q = group_min<G>(mn);
+        lo_q = lo_c;
+        w_q = w_c;
+    };
+
+    int i = 0;
+    for (; i + RM <= len; i += RM) {
+#pragma unroll
+        for (int u = 0; u < RM; ++u) {
+            step(u, u % PF, u & 1);
+            load_costs<G, K>(cost, moff[(u + PF) % RM], mw[(u + PF) % RM], lane, cst[u % PF]);
+            load_meta(u, (i + u + RM < len) ? p + RM * dp : p_last);
+            p += dp;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < RM; ++u) {
+        if (i + u < len) {
+            step(u, u % PF, u & 1);
+            if (u + PF < RM)
+                load_costs<G, K>(cost, moff[u + PF], mw[u + PF], lane, cst[u % PF]);
+            p += dp;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ SGM paths, full range
+// Full-range variant: every window is [0, D-1], so no realignment is needed
+// and the previous pixel's path costs stay in registers.  A lane group of G
+// lanes owns D = 2*NP*G disparities, lane l holding the contiguous slots
+// 2*NP*l .. 2*NP*l + 2*NP - 1 as NP registers of two 16-bit values each
+// (packed u16 arithmetic).  The d-1 / d+1 neighbours come from v_alignbit on
+// a lane's own registers plus one DPP lane shift for the slot owned by the
+// neighbouring lane; the group minimum m uses the DPP row reduction.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ inline u16x2 as_pk(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+__device__ inline uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ inline uint32_t pk_min(uint32_t a, uint32_t b) {
+    return as_u32(__builtin_elementwise_min(as_pk(a), as_pk(b)));
+}
+__device__ inline uint32_t pk_add(uint32_t a, uint32_t b) { return as_u32(as_pk(a) + as_pk(b)); }
+__device__ inline uint32_t pk_sub(uint32_t a, uint32_t b) { return as_u32(as_pk(a) - as_pk(b)); }
+// (hi:lo) >> 16: the upper half of lo becomes the lower half of the result.
+__device__ inline uint32_t align16(uint32_t hi, uint32_t lo) { return __builtin_amdgcn_alignbit(hi, lo, 16); }
+constexpr uint32_t kInfPk = 0x3fff3fffu;
+
+// Previous lane's value within a group of G lanes (lane 0 of the group gets
+// INF), and the next lane's (last lane gets INF).
+template <int G>
+__device__ inline uint32_t from_prev_lane(uint32_t v) {
+    if (G == 16) return __builtin_amdgcn_update_dpp(kInfPk, v, 0x111, 0xF, 0xF, false);  // row_shr:1
+    const uint32_t r = __builtin_amdgcn_update_dpp(kInfPk, v, 0x138, 0xF, 0xF, false);   // wave_shr:1
+    return (G == 32 && (threadIdx.x & 31) == 0) ? kInfPk : r;
+}
+template <int G>
+__device__ inline uint32_t from_next_lane(uint32_t v) {
+    if (G == 16) return __builtin_amdgcn_update_dpp(kInfPk, v, 0x101, 0xF, 0xF, false);  // row_shl:1
+    const uint32_t r = __builtin_amdgcn_update_dpp(kInfPk, v, 0x130, 0xF, 0xF, false);   // wave_shl:1
+    return (G == 32 && (threadIdx.x & 31) == 31) ? kInfPk : r;
+}
+
+// 2*NP cost bytes of one lane, loaded in one access.
+template <int NP> struct CostWord;
+template <> struct CostWord<1> { using T = uint16_t; };
+template <> struct CostWord<2> { using T = uint32_t; };
+template <> struct CostWord<4> { using T = uint2; };
+template <> struct CostWord<8> { using T = uint4; };
+
+template <int NP>
+__device__ inline void unpack_costs(const typename CostWord<NP>::T& w, uint32_t (&c)[NP]) {
+    // bytes b0 b1 -> (b0 | b1 << 16)
+    if constexpr (NP == 1) {
+        c[0] = __builtin_amdgcn_perm(0u, (uint32_t)w, 0x0C010C00u);
+    } else if constexpr (NP == 2) {
+        c[0] = __builtin_amdgcn_perm(0u, w, 0x0C010C00u);
+        c[1] = __builtin_amdgcn_perm(0u, w, 0x0C030C02u);
+    } else {
+        const uint32_t* u = reinterpret_cast<const uint32_t*>(&w);
+#pragma unroll
+        for (int q = 0; q < NP / 2; ++q) {
+            c[2 * q] = __builtin_amdgcn_perm(0u, u[q], 0x0C010C00u);
+            c[2 * q + 1] = __builtin_amdgcn_perm(0u, u[q], 0x0C030C02u);
+        }
+    }
+}
+
+template <int NP>
+__device__ inline typename CostWord<NP>::T pack_costs(const uint32_t (&L)[NP]) {
+    // low bytes of the 16-bit halves, in slot order
+    if constexpr (NP == 1) {
+        return (uint16_t)__builtin_amdgcn_perm(0u, L[0], 0x0C0C0200u);
+    } else if constexpr (NP == 2) {
+        return __builtin_amdgcn_perm(L[1], L[0], 0x06040200u);
+    } else {
+        typename CostWord<NP>::T w;
+        uint32_t* u = reinterpret_cast<uint32_t*>(&w);
+#pragma unroll
+        for (int q = 0; q < NP / 2; ++q) u[q] = __builtin_amdgcn_perm(L[2 * q + 1], L[2 * q], 0x06040200u);
+        return w;
+    }
+}
+
+// Prefetch: the cost words of step i + PF are loaded while step i runs,
+// unconditionally (past the end of the scanline the last pixel is loaded
+// again) and into ring slots named at compile time, so no loaded register
+// is ever copied before use: a step waits only on loads and stores issued PF
+// steps earlier.  The zero initial state makes the first step L = C.
+template <int G, int NP, int PF>
+__global__ __launch_bounds__(kBlock) void sgm_paths_full_kernel(SgmLaunch a, int n_tasks) {
+    using Word = typename CostWord<NP>::T;
+    constexpr int GPB = kBlock / G;
+    const int grp = threadIdx.x / G, lane = threadIdx.x % G;
+    const int task = blockIdx.x * GPB + grp;
+    if (task >= n_tasks) return;
+    const int W = a.w, H = a.h;
+    int dir, x, y, len, dx, dy;
+    decode_task(task, W, H, dir, x, y, len);
+    dir_step(dir, dx, dy);
+    const Word* __restrict__ cost = reinterpret_cast<const Word*>(a.cost);
+    Word* __restrict__ vol = reinterpret_cast<Word*>(a.vol + (size_t)dir * a.vol_stride);
+    const int dp = dy * W + dx;
+    const int p0 = y * W + x;
+    const int p_last = p0 + (len - 1) * dp;
+    const uint32_t p1pk = (uint32_t)a.p1 * 0x10001u;
+    const int p2 = a.p2;
+
+    Word ring[PF];
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+        const int pj = j < len ? p0 + j * dp : p_last;
+        ring[j] = cost[(uint32_t)pj * G + lane];
+    }
+    uint32_t L[NP];
+#pragma unroll
+    for (int r = 0; r < NP; ++r) L[r] = 0u;
+    int m = 0;
+    int p = p0;
+
+    auto step = [&](const Word& w) {
+        uint32_t c[NP];
+        unpack_costs<NP>(w, c);
+        const uint32_t mpk = (uint32_t)m * 0x10001u;
+        const uint32_t m2pk = (uint32_t)(m + p2) * 0x10001u;
+        const uint32_t prv = from_prev_lane<G>(L[NP - 1]);
+        const uint32_t nxt = from_next_lane<G>(L[0]);
+        uint32_t Ln[NP];
+#pragma unroll
+        for (int r = 0; r < NP; ++r) {
+            const uint32_t lm1 = align16(L[r], r > 0 ? L[r - 1] : prv);
+            const uint32_t lp1 = align16(r + 1 < NP ? L[r + 1] : nxt, L[r]);
+            uint32_t t = pk_add(pk_min(lm1, lp1), p1pk);
+            t = pk_min(pk_min(t, L[r]), m2pk);
+            Ln[r] = pk_sub(pk_add(c[r], t), mpk);
+        }
+        uint32_t mv = Ln[0];
+#pragma unroll
+        for (int r = 0; r < NP; ++r) {
+            L[r] = Ln[r];
+            mv = pk_min(mv, Ln[r]);
+        }
+        vol[(uint32_t)p * G + lane] = pack_costs<NP>(L);
+        m = group_min<G>((int)min(mv & 0xffffu, mv >> 16));
+    };
+
+    int i = 0;
+    for (; i + PF <= len; i += PF) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            step(ring[u]);
+            const int pn = (i + u + PF < len) ? p + PF * dp : p_last;
+            ring[u] = cost[(uint32_t)pn * G + lane];
+            p += dp;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+        if (i + u < len) {
+            step(ring[u]);
+            p += dp;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ selection
+__device__ inline int sum_paths(const uint8_t* __restrict__ vol, size_t stride, uint32_t j) {
+    int s = 0;
+#pragma unroll
+    for (int r = 0; r < kNumPaths; ++r) s += vol[(size_t)r * stride + j];
+    return s;
+}
+
+// One block per 64-pixel row segment; a lane group of G lanes per pixel,
+// lane l owning slots l + G*k.  The winner-takes-all key (S << 9 | d) is a
+// group minimum (ties go to the smaller d).  Each slot also offers its key
+// to right pixel x-d: first into an LDS array covering x0-(D-1) .. x0+63,
+// then one global atomicMin per touched right pixel.  The pixel's S row is
+// kept in LDS for the parabola and the uncertainty walk.  Results before the
+// left-right check go to disp_wta / disp_sub / var_meas.
+template <int G, int K, bool FULL>
+__global__ __launch_bounds__(kBlock) void sgm_select_kernel(SgmLaunch a) {
+    constexpr int GPB = kBlock / G;
+    __shared__ uint32_t keyR[kSeg + kMaxDisp];
+    __shared__ uint16_t sS_all[GPB][G * K];
+    const int W = a.w, D = a.win.max_disp;
+    const int y = blockIdx.y, x0 = blockIdx.x * kSeg;
+    const int base = x0 - (D - 1);
+    const int grp = threadIdx.x / G, lane = threadIdx.x % G;
+    uint16_t* sS = sS_all[grp];
+    for (int i = threadIdx.x; i < kSeg + D - 1; i += kBlock) keyR[i] = 0xffffffffu;
+    __syncthreads();
+    const uint8_t* __restrict__ vol = a.vol;
+    const size_t stride = a.vol_stride;
+    for (int i = grp; i < kSeg; i += GPB) {
+        const int x = x0 + i;
+        if (x >= W) break;
+        const int p = y * W + x;
+        int lo, hi;
+        uint32_t off;
+        window_of<FULL>(a.win, p, lo, hi, off);
+        const int w = hi - lo + 1;
+        int kbest = 0x7fffffff;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int s = lane + G * k;
+            if (s < w) {
+                const int S = sum_paths(vol, stride, off + (uint32_t)s);
+                const int d = lo + s;
+                const int key = (S << 9) | d;
+                kbest = min(kbest, key);
+                sS[s] = (uint16_t)S;
+                if (a.agg) a.agg[off + (uint32_t)s] = (uint16_t)S;
+                if (x - d >= 0) atomicMin(&keyR[i + (D - 1) - d], (uint32_t)key);
+            }
+        }
+        lds_order();
+        kbest = group_min<G>(kbest);
+        if (lane == 0) {
+            const int ds = kbest & 511, sb = kbest >> 9;
+            const int j0 = ds - lo;
+            float sub = (float)ds;
+            if (ds > lo && ds < hi) {
+                const int sa = sS[j0 - 1], sc = sS[j0 + 1];
+                const int den = sa - 2 * sb + sc;
+                if (den > 0) sub = (float)ds + (float)(sa - sc) / (float)(2 * den);
+            }
+            int acc = 0, n = 0;
+            for (int j = 1; j0 - j >= 0; ++j) {
+                acc += (int)sS[j0 - j] - sb;
+                if (acc >= a.s_max) break;
+                ++n;
+            }
+            acc = 0;
+            for (int j = 1; j0 + j < w; ++j) {
+                acc += (int)sS[j0 + j] - sb;
+                if (acc >= a.s_max) break;
+                ++n;
+            }
+            a.disp_wta[p] = (int16_t)ds;
+            a.disp_sub[p] = sub;
+            a.var_meas[p] = (float)n;
+            if (a.wta_raw) a.wta_raw[p] = (int16_t)ds;
+        }
+        lds_order();
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kSeg + D - 1; i += kBlock) {
+        const int xr = base + i;
+        const uint32_t k = keyR[i];
+        if (xr >= 0 && xr < W && k != 0xffffffffu) atomicMin(&a.key_r[(size_t)y * W + xr], k);
+    }
+}
+
+// Right map and left-right check (in place on the selection's outputs).
+__global__ __launch_bounds__(kBlock) void sgm_lr_kernel(SgmLaunch a) {
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= a.w * a.h) return;
+    const uint32_t kr = a.key_r[p];
+    if (a.disp_right) a.disp_right[p] = kr == 0xffffffffu ? (int16_t)-1 : (int16_t)(kr & 511u);
+    if (a.lr_tol < 0) return;
+    const int x = p % a.w;
+    const int ds = a.disp_wta[p];
+    bool ok = false;
+    if (x - ds >= 0) {
+        const uint32_t k2 = a.key_r[p - ds];
+        if (k2 != 0xffffffffu) ok = abs(ds - (int)(k2 & 511u)) <= a.lr_tol;
+    }
+    if (!ok) {
+        a.disp_wta[p] = -1;
+        a.disp_sub[p] = -1.0f;
+        a.var_meas[p] = 0.0f;
+    }
+}
+
+// Copies the first n bytes of a ragged volume, n = w*h*D for the full range
+// or offsets[w*h] (read on the device) otherwise.
+template <bool FULL>
+__global__ __launch_bounds__(kBlock) void copy_slots_kernel(SgmLaunch a, const uint8_t* src,
+                                                            uint8_t* dst) {
+    const size_t n = FULL ? (size_t)a.w * a.h * a.win.max_disp : (size_t)a.win.off[a.w * a.h];
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+        dst[i] = src[i];
+}
+
+// ------------------------------------------------------------------ warp
+struct Mat4 {
+    float m[16];
+};
+struct Mat4d {
+    double m[16];
+};
+
+__global__ __launch_bounds__(kBlock) void fill_u64_kernel(unsigned long long* z, size_t n) {
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) z[i] = ~0ull;
+}
+
+// Decision pass, float32 in the documented order: the target pixel and the
+// key (~bits(d') << 32 | source index), so atomicMin keeps the largest d'
+// and, on equal d', the smaller source index, independent of thread order.
+__global__ __launch_bounds__(kBlock) void warp_scatter_kernel(const float* __restrict__ d_prev,
+                                                              int w, int h, Mat4 H,
+                                                              unsigned long long* zbuf) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= w * h) return;
+    const float d = d_prev[i];
+    if (!(d > 0.0f)) return;
+    const float xf = (float)(i % w), yf = (float)(i / w);
+    const float* m = H.m;
+    const float o0 = ((m[0] * xf + m[1] * yf) + m[2] * d) + m[3];
+    const float o1 = ((m[4] * xf + m[5] * yf) + m[6] * d) + m[7];
+    const float o3 = ((m[12] * xf + m[13] * yf) + m[14] * d) + m[15];
+    if (!(o3 > 0.0f)) return;
+    const float xp = o0 / o3, yp = o1 / o3, dp = d / o3;
+    const float vx = xp + 0.5f, vy = yp + 0.5f;
+    if (!(vx >= 0.0f) || !(vx < (float)w) || !(vy >= 0.0f) || !(vy < (float)h)) return;
+    const int xi = (int)floorf(vx), yi = (int)floorf(vy);
+    const unsigned long long key =
+        ((unsigned long long)(0xffffffffu - __float_as_uint(dp)) << 32) | (unsigned)i;
+    atomicMin(&zbuf[(size_t)yi * w + xi], key);
+}
+
+// Value pass: the winner's d' = d/omega_3 and p' = (d'/d)^2 p + q in double
+// (row 2 of H is exactly (0,0,1,0), so omega_2 = d), rounded once to float.
+__global__ __launch_bounds__(kBlock) void warp_decode_kernel(const unsigned long long* zbuf,
+                                                             const float* __restrict__ d_prev,
+                                                             const float* __restrict__ p_prev,
+                                                             int w, int n, Mat4d H, double q,
+                                                             float* __restrict__ d_pred,
+                                                             float* __restrict__ p_pred) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const unsigned long long k = zbuf[i];
+    if (k == ~0ull) {
+        d_pred[i] = -1.0f;
+        p_pred[i] = 0.0f;
+        return;
+    }
+    const int src = (int)(uint32_t)k;
+    const double x = (double)(src % w), y = (double)(src / w);
+    const double d = (double)d_prev[src], p = (double)p_prev[src];
+    const double* m = H.m;
+    const double o3 = m[12] * x + m[13] * y + m[14] * d + m[15];
+    const double dn = d / o3;
+    const double phi = dn / d;
+    d_pred[i] = (float)dn;
+    p_pred[i] = (float)(phi * phi * p + q);
+}
+
+// ------------------------------------------------------------------ Kalman
+__global__ __launch_bounds__(kBlock) void kalman_kernel(const float* d_pred, const float* p_pred,
+                                                        const float* z, const float* r, int n,
+                                                        int keep, float* d_out, float* p_out) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const float dp = d_pred[i], pp = p_pred[i], zz = z[i], rr = r[i];
+    const bool pv = dp >= 0.0f && pp > 0.0f;
+    const bool mv = zz >= 0.0f && rr >= 0.0f;
+    float d, p;
+    if (pv && mv) {
+        const float K = pp / (pp + rr);
+        d = dp + K * (zz - dp);
+        p = (1.0f - K) * pp;
+    } else if (mv) {
+        d = zz;
+        p = rr;
+    } else if (pv && keep) {
+        d = dp;
+        p = pp;
+    } else {
+        d = -1.0f;
+        p = 0.0f;
+    }
+    d_out[i] = d;
+    p_out[i] = p;
+}
+
+inline unsigned grid_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+hipError_t launch_census(const uint8_t* img, int w, int h, int pitch, uint64_t* out,
+                         hipStream_t s) {
+    dim3 grid((w + kCtW - 1) / kCtW, (h + kCtH - 1) / kCtH, 1);
+    census_kernel<<<grid, kBlock, 0, s>>>(img, img, w, h, pitch, out, out, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_census_pair(const uint8_t* left, const uint8_t* right, int w, int h, int pitch,
+                              uint64_t* out_l, uint64_t* out_r, uint32_t* clear, hipStream_t s) {
+    dim3 grid((w + kCtW - 1) / kCtW, (h + kCtH - 1) / kCtH, 2);
+    census_kernel<<<grid, kBlock, 0, s>>>(left, right, w, h, pitch, out_l, out_r, clear);
+    return hipGetLastError();
+}
+
+hipError_t launch_sgm_cost(const SgmLaunch& a, hipStream_t s) {
+    dim3 grid((a.w + kSeg - 1) / kSeg, a.h);
+    if (a.win.lo == nullptr)
+        cost_kernel<64, true><<<grid, kBlock, 0, s>>>(a);
+    else
+        cost_kernel<16, false><<<grid, kBlock, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sgm_paths(const SgmLaunch& a, hipStream_t s) {
+    const int n_tasks = 2 * a.h + 2 * a.w + 4 * (a.w + a.h - 1);
+    const int D = a.win.max_disp;
+    const bool full = a.win.lo == nullptr;
+    auto grid = [&](int G) { return (unsigned)((n_tasks + kBlock / G - 1) / (kBlock / G)); };
+#define EGOSGM_PATHS(GG, KK, FF) \
+    sgm_paths_kernel<GG, KK, FF, 4><<<grid(GG), kBlock, 0, s>>>(a, n_tasks)
+#define EGOSGM_FULL(GG, NN) sgm_paths_full_kernel<GG, NN, 8><<<grid(GG), kBlock, 0, s>>>(a, n_tasks)
+    if (full) {
+        if (D == 64) EGOSGM_FULL(16, 2);
+        else if (D == 128) EGOSGM_FULL(32, 2);
+        else if (D == 256) EGOSGM_FULL(32, 4);
+        else if (D <= 64) EGOSGM_PATHS(64, 1, true);
+        else if (D <= 128) EGOSGM_PATHS(64, 2, true);
+        else EGOSGM_PATHS(64, 4, true);
+    } else {
+        if (D <= 16) EGOSGM_PATHS(16, 1, false);
+        else if (D <= 64) EGOSGM_PATHS(32, 2, false);
+        else if (D <= 128) EGOSGM_PATHS(32, 4, false);
+        else EGOSGM_PATHS(32, 8, false);
+    }
+#undef EGOSGM_PATHS
+#undef EGOSGM_FULL
+    return hipGetLastError();
+}
+
+hipError_t launch_sgm_select(const SgmLaunch& a, hipStream_t s) {
+    const int D = a.win.max_disp;
+    const bool full = a.win.lo == nullptr;
+    dim3 grid((a.w + kSeg - 1) / kSeg, a.h);
+#define EGOSGM_SEL(GG, KK, FF) sgm_select_kernel<GG, KK, FF><<<grid, kBlock, 0, s>>>(a)
+    if (full) {
+        if (D <= 64) EGOSGM_SEL(64, 1, true);
+        else if (D <= 128) EGOSGM_SEL(64, 2, true);
+        else EGOSGM_SEL(64, 4, true);
+    } else {
+        if (D <= 16) EGOSGM_SEL(16, 1, false);
+        else if (D <= 64) EGOSGM_SEL(16, 4, false);
+        else if (D <= 128) EGOSGM_SEL(16, 8, false);
+        else EGOSGM_SEL(16, 16, false);
+    }
+#undef EGOSGM_SEL
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    sgm_lr_kernel<<<grid_for((size_t)a.w * a.h), kBlock, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_slots(const SgmLaunch& a, const uint8_t* src, uint8_t* dst, hipStream_t s) {
+    if (a.win.lo == nullptr)
+        copy_slots_kernel<true><<<1024, kBlock, 0, s>>>(a, src, dst);
+    else
+        copy_slots_kernel<false><<<1024, kBlock, 0, s>>>(a, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_windows(const float* d_pred, const float* p_pred, int w, int h, float k_sigma,
+                          int r_fixed, int r_min, int r_max, int max_disp, int16_t* lo,
+                          int16_t* hi, uint32_t* off, uint32_t* row_tot, hipStream_t s) {
+    windows_row_kernel<<<h, kBlock, 0, s>>>(d_pred, p_pred, w, k_sigma, r_fixed, r_min, r_max,
+                                            max_disp, lo, hi, off, row_tot);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    windows_offset_kernel<<<h, kBlock, 0, s>>>(w, h, off, row_tot);
+    return hipGetLastError();
+}
+
+hipError_t launch_warp(const float* d_prev, const float* p_prev, int w, int h, const float* H,
+                       const double* Hd, double q, float* d_pred, float* p_pred,
+                       unsigned long long* zbuf, hipStream_t s) {
+    const size_t n = (size_t)w * h;
+    Mat4 m;
+    Mat4d md;
+    for (int i = 0; i < 16; ++i) {
+        m.m[i] = H[i];
+        md.m[i] = Hd[i];
+    }
+    fill_u64_kernel<<<grid_for(n), kBlock, 0, s>>>(zbuf, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    warp_scatter_kernel<<<grid_for(n), kBlock, 0, s>>>(d_prev, w, h, m, zbuf);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    warp_decode_kernel<<<grid_for(n), kBlock, 0, s>>>(zbuf, d_prev, p_prev, w, (int)n, md, q,
+                                                      d_pred, p_pred);
+    return hipGetLastError();
+}
+
+hipError_t launch_kalman(const float* d_pred, const float* p_pred, const float* z, const float* r,
+                         int n, int keep, float* d_out, float* p_out, hipStream_t s) {
+    kalman_kernel<<<grid_for((size_t)n), kBlock, 0, s>>>(d_pred, p_pred, z, r, n, keep, d_out,
+                                                         p_out);
+    return hipGetLastError();
+}
+
+}  // namespace egosgm

@@ -1,0 +1,315 @@
+"""Python binding of libegosgm (include/egosgm.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of libegosgm.so.  Tensors are torch tensors on the GPU (torch provides device
+memory and the stream); the functions pass their data pointers and the
+current HIP stream to the C ABI and raise on a non-zero status.  There is no
+fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libegosgm.so")
+_lib = None
+
+_vp, _i, _f, _d, _sz = C.c_void_p, C.c_int, C.c_float, C.c_double, C.c_size_t
+
+_SIGS = {
+    "egosgm_abi_version": ([], _i),
+    "egosgm_status_string": ([_i], C.c_char_p),
+    "egosgm_census": ([_vp, _i, _i, _i, _vp, _vp], _i),
+    "egosgm_sgm_workspace_bytes": ([_i, _i, _i], _sz),
+    "sgm_full": ([_vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _i),
+    "egosgm_windows_workspace_bytes": ([_i, _i], _sz),
+    "sgm_windows_from_prediction": ([_vp, _vp, _i, _i, _f, _i, _i, _i, _i, _vp, _vp, _vp, _vp,
+                                     _sz, _vp], _i),
+    "sgm_reduced": ([_vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                     _sz, _vp], _i),
+    "egosgm_warp_matrix": ([_vp, _vp, _d, _d, _d, _d, _vp], _i),
+    "warp_disparity": ([_vp, _vp, _i, _i, _vp, _vp, _d, _d, _d, _d, _f, _vp, _vp, _vp, _vp], _i),
+    "kalman_update": ([_vp, _vp, _vp, _vp, _i, _i, _vp, _vp, _vp], _i),
+    "egosgm_timing_enable": ([_i], _i),
+    "egosgm_timing_read": ([_vp, _vp, _i], _i),
+}
+
+STAGES = ("census", "windows", "cost", "paths", "select", "warp", "kalman")
+
+
+def lib():
+    """Loads libegosgm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1708_06301_amd.build`")
+        h = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(h, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = h
+    return _lib
+
+
+class EgoSgmError(RuntimeError):
+    pass
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        msg = lib().egosgm_status_string(rc).decode()
+        raise EgoSgmError(f"{what}: {msg} ({rc})")
+
+
+class SgmParams(C.Structure):
+    _fields_ = [("max_disp", C.c_int32), ("p1", C.c_int32), ("p2", C.c_int32),
+                ("s_max", C.c_int32), ("lr_tol", C.c_int32)]
+
+
+class SgmDebug(C.Structure):
+    _fields_ = [("census_left", _vp), ("census_right", _vp), ("cost", _vp), ("paths", _vp),
+                ("agg", _vp), ("wta_raw", _vp)]
+
+
+@dataclass
+class MatchParams:
+    max_disp: int = 128
+    p1: int = 10
+    p2: int = 120
+    s_max: int = 80
+    lr_tol: int = 1
+
+    def c(self) -> SgmParams:
+        return SgmParams(self.max_disp, self.p1, self.p2, self.s_max, self.lr_tol)
+
+
+def _stream():
+    return _vp(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else _vp(t.data_ptr())
+
+
+def _need(t: torch.Tensor, dtype, numel=None, name="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise EgoSgmError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise EgoSgmError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise EgoSgmError(f"{name} must be contiguous")
+    if numel is not None and t.numel() < numel:
+        raise EgoSgmError(f"{name} holds {t.numel()} elements, needs {numel}")
+    return t
+
+
+def abi_version() -> int:
+    return lib().egosgm_abi_version()
+
+
+# ------------------------------------------------------------------ census
+def census(img: torch.Tensor) -> torch.Tensor:
+    """9x7 census codes (int64 tensor holding the uint64 bit patterns)."""
+    _need(img, torch.uint8, name="img")
+    h, w = img.shape
+    out = torch.empty((h, w), dtype=torch.int64, device=img.device)
+    _check(lib().egosgm_census(_ptr(img), w, h, w, _ptr(out), _stream()), "egosgm_census")
+    return out
+
+
+# ------------------------------------------------------------------ workspaces
+class Workspace:
+    """Device scratch for the matcher, grown on demand and reused."""
+
+    def __init__(self, device="cuda"):
+        self.device = torch.device(device)
+        self.sgm = None
+        self.win = None
+
+    def sgm_bytes(self, w, h, max_disp):
+        n = lib().egosgm_sgm_workspace_bytes(w, h, max_disp)
+        if n == 0:
+            raise EgoSgmError("workspace size: bad shape")
+        if self.sgm is None or self.sgm.numel() < n:
+            self.sgm = torch.empty(n, dtype=torch.uint8, device=self.device)
+        return self.sgm, n
+
+    def windows_bytes(self, w, h):
+        n = lib().egosgm_windows_workspace_bytes(w, h)
+        if self.win is None or self.win.numel() < n:
+            self.win = torch.empty(n, dtype=torch.uint8, device=self.device)
+        return self.win, n
+
+
+_default_ws = {}
+
+
+def _ws(device) -> Workspace:
+    key = str(device)
+    if key not in _default_ws:
+        _default_ws[key] = Workspace(device)
+    return _default_ws[key]
+
+
+def _outputs(h, w, device):
+    return dict(disp_wta=torch.empty((h, w), dtype=torch.int16, device=device),
+                disp_sub=torch.empty((h, w), dtype=torch.float32, device=device),
+                var_meas=torch.empty((h, w), dtype=torch.float32, device=device),
+                disp_right=torch.empty((h, w), dtype=torch.int16, device=device))
+
+
+def _debug(h, w, max_disp, total, device):
+    n = h * w
+    d = dict(census_left=torch.empty((h, w), dtype=torch.int64, device=device),
+             census_right=torch.empty((h, w), dtype=torch.int64, device=device),
+             cost=torch.empty(total, dtype=torch.uint8, device=device),
+             paths=torch.empty((8, n * max_disp), dtype=torch.uint8, device=device),
+             agg=torch.empty(total, dtype=torch.int16, device=device),
+             wta_raw=torch.empty((h, w), dtype=torch.int16, device=device))
+    s = SgmDebug(*[_ptr(d[k]) for k in ("census_left", "census_right", "cost", "paths", "agg",
+                                           "wta_raw")])
+    return d, s
+
+
+# ------------------------------------------------------------------ SGM
+def sgm_full(left: torch.Tensor, right: torch.Tensor, params: MatchParams | None = None,
+             debug: bool = False, out: dict | None = None, workspace: Workspace | None = None):
+    """Full-range SGM; returns dict disp_wta, disp_sub, var_meas, disp_right
+    (+ debug tensors: census_left/right, cost, paths, agg (int16 holding
+    uint16), wta_raw)."""
+    params = params or MatchParams()
+    _need(left, torch.uint8, name="left")
+    _need(right, torch.uint8, name="right")
+    h, w = left.shape
+    if right.shape != left.shape:
+        raise EgoSgmError("left/right shapes differ")
+    o = out if out is not None else _outputs(h, w, left.device)
+    ws, nbytes = (workspace or _ws(left.device)).sgm_bytes(w, h, params.max_disp)
+    dbg, dbg_c = (None, None)
+    if debug:
+        dbg, dbg_c = _debug(h, w, params.max_disp, h * w * params.max_disp, left.device)
+    prm = params.c()
+    rc = lib().sgm_full(_ptr(left), _ptr(right), w, h, w, C.byref(prm), _ptr(o["disp_wta"]),
+                        _ptr(o["disp_sub"]), _ptr(o["var_meas"]), _ptr(o.get("disp_right")),
+                        C.byref(dbg_c) if debug else None, _ptr(ws), nbytes, _stream())
+    _check(rc, "sgm_full")
+    if debug:
+        o = dict(o)
+        o.update(dbg)
+    return o
+
+
+def windows_from_prediction(d_pred: torch.Tensor, p_pred: torch.Tensor | None, max_disp: int,
+                            r_fixed: int = -1, r_min: int = 0, r_max: int = 256,
+                            k_sigma: float = 3.0, out=None, workspace: Workspace | None = None):
+    """Per-pixel windows (lo, hi, offsets) from a predicted map."""
+    _need(d_pred, torch.float32, name="d_pred")
+    if p_pred is not None:
+        _need(p_pred, torch.float32, d_pred.numel(), name="p_pred")
+    h, w = d_pred.shape
+    if out is None:
+        dev = d_pred.device
+        out = (torch.empty((h, w), dtype=torch.int16, device=dev),
+               torch.empty((h, w), dtype=torch.int16, device=dev),
+               torch.empty(h * w + 1, dtype=torch.int32, device=dev))
+    lo, hi, off = out
+    ws, nbytes = (workspace or _ws(d_pred.device)).windows_bytes(w, h)
+    rc = lib().sgm_windows_from_prediction(_ptr(d_pred), _ptr(p_pred), w, h, k_sigma, r_fixed,
+                                           r_min, r_max, max_disp, _ptr(lo), _ptr(hi),
+                                           _ptr(off), _ptr(ws), nbytes, _stream())
+    _check(rc, "sgm_windows_from_prediction")
+    return lo, hi, off
+
+
+def sgm_reduced(left: torch.Tensor, right: torch.Tensor, lo: torch.Tensor, hi: torch.Tensor,
+                offsets: torch.Tensor, params: MatchParams | None = None, debug: bool = False,
+                out: dict | None = None, workspace: Workspace | None = None, total: int | None = None):
+    """SGM over per-pixel windows; debug volumes are sized from `total` (read
+    back from offsets when not given)."""
+    params = params or MatchParams()
+    _need(left, torch.uint8, name="left")
+    _need(right, torch.uint8, name="right")
+    h, w = left.shape
+    _need(lo, torch.int16, h * w, "lo")
+    _need(hi, torch.int16, h * w, "hi")
+    _need(offsets, torch.int32, h * w + 1, "offsets")
+    o = out if out is not None else _outputs(h, w, left.device)
+    ws, nbytes = (workspace or _ws(left.device)).sgm_bytes(w, h, params.max_disp)
+    dbg, dbg_c = (None, None)
+    if debug:
+        if total is None:
+            total = int(offsets[h * w].item())
+        dbg, dbg_c = _debug(h, w, params.max_disp, total, left.device)
+    prm = params.c()
+    rc = lib().sgm_reduced(_ptr(left), _ptr(right), w, h, w, _ptr(lo), _ptr(hi), _ptr(offsets),
+                           C.byref(prm), _ptr(o["disp_wta"]), _ptr(o["disp_sub"]),
+                           _ptr(o["var_meas"]), _ptr(o.get("disp_right")),
+                           C.byref(dbg_c) if debug else None, _ptr(ws), nbytes, _stream())
+    _check(rc, "sgm_reduced")
+    if debug:
+        o = dict(o)
+        o.update(dbg)
+    return o
+
+
+# ------------------------------------------------------------------ warp / update
+def warp_matrix(R, t, f, cx, cy, baseline) -> np.ndarray:
+    """Host helper: the float32 H the warp uses."""
+    R = np.ascontiguousarray(R, dtype=np.float64).ravel()
+    t = np.ascontiguousarray(t, dtype=np.float64).ravel()
+    H = np.zeros(16, np.float32)
+    _check(lib().egosgm_warp_matrix(R.ctypes.data_as(_vp), t.ctypes.data_as(_vp), f, cx, cy,
+                                    baseline, H.ctypes.data_as(_vp)), "egosgm_warp_matrix")
+    return H.reshape(4, 4)
+
+
+def warp_disparity(d_prev: torch.Tensor, p_prev: torch.Tensor, R, t, f, cx, cy, baseline, q,
+                   out=None, zbuf: torch.Tensor | None = None):
+    _need(d_prev, torch.float32, name="d_prev")
+    h, w = d_prev.shape
+    _need(p_prev, torch.float32, h * w, "p_prev")
+    dev = d_prev.device
+    if out is None:
+        out = (torch.empty((h, w), dtype=torch.float32, device=dev),
+               torch.empty((h, w), dtype=torch.float32, device=dev))
+    if zbuf is None:
+        zbuf = torch.empty(h * w, dtype=torch.int64, device=dev)
+    R = np.ascontiguousarray(R, dtype=np.float64).ravel()
+    t = np.ascontiguousarray(t, dtype=np.float64).ravel()
+    rc = lib().warp_disparity(_ptr(d_prev), _ptr(p_prev), w, h, R.ctypes.data_as(_vp),
+                              t.ctypes.data_as(_vp), f, cx, cy, baseline, q, _ptr(out[0]),
+                              _ptr(out[1]), _ptr(zbuf), _stream())
+    _check(rc, "warp_disparity")
+    return out
+
+
+def kalman_update(d_pred, p_pred, d_meas, r_meas, keep_unmeasured=0, out=None):
+    n = d_pred.numel()
+    for name, t in (("d_pred", d_pred), ("p_pred", p_pred), ("d_meas", d_meas), ("r_meas", r_meas)):
+        _need(t, torch.float32, n, name)
+    if out is None:
+        out = (torch.empty_like(d_pred), torch.empty_like(d_pred))
+    rc = lib().kalman_update(_ptr(d_pred), _ptr(p_pred), _ptr(d_meas), _ptr(r_meas), n,
+                             int(keep_unmeasured), _ptr(out[0]), _ptr(out[1]), _stream())
+    _check(rc, "kalman_update")
+    return out
+
+
+# ------------------------------------------------------------------ timing
+def timing_enable(on: bool = True):
+    _check(lib().egosgm_timing_enable(1 if on else 0), "egosgm_timing_enable")
+
+
+def timing_read() -> dict:
+    """{stage: (total_ms, launches)} for the stages recorded since the last read."""
+    ms = (C.c_double * len(STAGES))()
+    cnt = (C.c_int * len(STAGES))()
+    _check(lib().egosgm_timing_read(ms, cnt, len(STAGES)), "egosgm_timing_read")
+    return {s: (ms[i], cnt[i]) for i, s in enumerate(STAGES)}

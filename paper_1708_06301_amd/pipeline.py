@@ -1,0 +1,112 @@
+"""Per-camera-stream frame loop over the C ABI (Sec. 2: disparity prediction,
+stereo matching in the reduced space, disparity update).
+
+A StreamState keeps the stream's disparity and variance maps resident on the
+GPU between frames together with every buffer a frame needs, so a frame
+enqueues only kernels.  Frame 0, and every frame after reset(), matches over
+the full range; later frames warp the previous map by the ego-motion, derive
+per-pixel windows from the predicted variance (or a fixed radius) and match
+only inside them (Sec. 2.3; Sec. 3: the first frame searches everything).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import egosgm as eg
+
+
+@dataclass
+class Calib:
+    f: float
+    cx: float
+    cy: float
+    baseline: float
+
+
+@dataclass
+class FrameConfig:
+    max_disp: int = 128
+    p1: int = 10
+    p2: int = 120
+    s_max: int = 80
+    lr_tol: int = 1
+    q: float = 0.5            # ego-motion variance in disparity space (Eq. 5)
+    k_sigma: float = 3.0      # window half-width in standard deviations (Sec. 2.3)
+    r_fixed: int = -1         # >= 0: fixed window radius instead of k_sigma*sqrt(p)
+    r_min: int = 0
+    r_max: int = 256
+    keep_unmeasured: int = 0
+    full_range_only: bool = False   # plain SGM every frame (the baseline)
+
+    def match(self) -> eg.MatchParams:
+        return eg.MatchParams(self.max_disp, self.p1, self.p2, self.s_max, self.lr_tol)
+
+
+class StreamState:
+    def __init__(self, w: int, h: int, calib: Calib, cfg: FrameConfig, device="cuda"):
+        self.w, self.h, self.calib, self.cfg = w, h, calib, cfg
+        dev = torch.device(device)
+        self.device = dev
+        n = w * h
+        f32 = dict(dtype=torch.float32, device=dev)
+        self.d = torch.full((h, w), -1.0, **f32)     # D^{k}
+        self.p = torch.zeros((h, w), **f32)          # P^{k}
+        self.d_pred = torch.empty((h, w), **f32)
+        self.p_pred = torch.empty((h, w), **f32)
+        self.zbuf = torch.empty(n, dtype=torch.int64, device=dev)
+        self.lo = torch.empty((h, w), dtype=torch.int16, device=dev)
+        self.hi = torch.empty((h, w), dtype=torch.int16, device=dev)
+        self.off = torch.empty(n + 1, dtype=torch.int32, device=dev)
+        self.out = dict(disp_wta=torch.empty((h, w), dtype=torch.int16, device=dev),
+                        disp_sub=torch.empty((h, w), **f32),
+                        var_meas=torch.empty((h, w), **f32),
+                        disp_right=torch.empty((h, w), dtype=torch.int16, device=dev))
+        self.ws = eg.Workspace(dev)
+        self.ws.sgm_bytes(w, h, cfg.max_disp)
+        self.ws.windows_bytes(w, h)
+        self.invalid = torch.full((h, w), -1.0, **f32)
+        self.zeros = torch.zeros((h, w), **f32)
+        self.frame = 0
+
+    def reset(self):
+        """Drop the prediction: the next frame searches the full range."""
+        self.frame = 0
+
+    def step(self, left: torch.Tensor, right: torch.Tensor, R=None, t=None):
+        """Processes one stereo frame; R, t map the previous camera frame to
+        this one (M_k = R M_{k-1} + t).  Returns the updated (d, p) maps."""
+        cfg, c = self.cfg, self.calib
+        prm = cfg.match()
+        if self.frame == 0 or cfg.full_range_only:
+            eg.sgm_full(left, right, prm, out=self.out, workspace=self.ws)
+            eg.kalman_update(self.invalid, self.zeros, self.out["disp_sub"], self.out["var_meas"],
+                             cfg.keep_unmeasured, out=(self.d, self.p))
+        else:
+            eg.warp_disparity(self.d, self.p, R, t, c.f, c.cx, c.cy, c.baseline, cfg.q,
+                              out=(self.d_pred, self.p_pred), zbuf=self.zbuf)
+            eg.windows_from_prediction(self.d_pred, self.p_pred, cfg.max_disp, cfg.r_fixed,
+                                       cfg.r_min, cfg.r_max, cfg.k_sigma,
+                                       out=(self.lo, self.hi, self.off), workspace=self.ws)
+            eg.sgm_reduced(left, right, self.lo, self.hi, self.off, prm, out=self.out,
+                           workspace=self.ws)
+            eg.kalman_update(self.d_pred, self.p_pred, self.out["disp_sub"],
+                             self.out["var_meas"], cfg.keep_unmeasured, out=(self.d, self.p))
+        self.frame += 1
+        return self.d, self.p
+
+    def searched_slots(self) -> int:
+        """Disparities searched by the last reduced frame (synchronises)."""
+        return int(self.off[self.w * self.h].item()) & 0xFFFFFFFF
+
+
+def camera_of(seq) -> Calib:
+    cam = seq.cam
+    return Calib(cam.f, cam.cx, cam.cy, cam.baseline)
+
+
+def motions(seq):
+    return [None] + [tuple(np.asarray(a, np.float64) for a in seq.motion(k))
+                     for k in range(1, seq.n_frames)]

@@ -244,65 +244,115 @@ def make_scene(seed: int, n_frames: int, step: float = 1.0, yaw_sigma_deg: float
                  noise_sigma=noise_sigma, noise_seed=splitmix64(seed ^ 0x123457))
 
 
-def _raycast(scene: Scene, origin: np.ndarray, dirs: np.ndarray):
-    """Nearest hit distance along unit-z-normalised rays (t such that the
-    hit is origin + t*dir) and the hit points."""
+def _perlin_torch(perm: np.ndarray, device):
+    import torch
+    return torch.as_tensor(np.concatenate([perm, perm]), dtype=torch.int64, device=device)
+
+
+def _noise3_torch(p, x, y, z):
+    """Improved Perlin noise on torch tensors (float64)."""
+    import torch
+    fx, fy, fz = torch.floor(x), torch.floor(y), torch.floor(z)
+    X = fx.long() & 255
+    Y = fy.long() & 255
+    Z = fz.long() & 255
+    x, y, z = x - fx, y - fy, z - fz
+
+    def fade(t):
+        return t * t * t * (t * (t * 6.0 - 15.0) + 10.0)
+
+    def grad(hh, a, b, c):
+        hh = hh & 15
+        u = torch.where(hh < 8, a, b)
+        v = torch.where(hh < 4, b, torch.where((hh == 12) | (hh == 14), a, c))
+        return torch.where((hh & 1) != 0, -u, u) + torch.where((hh & 2) != 0, -v, v)
+
+    def lerp(t, a, b):
+        return a + t * (b - a)
+
+    u, v, w = fade(x), fade(y), fade(z)
+    A = p[X] + Y
+    AA, AB = p[A] + Z, p[A + 1] + Z
+    B = p[X + 1] + Y
+    BA, BB = p[B] + Z, p[B + 1] + Z
+    return lerp(w,
+                lerp(v, lerp(u, grad(p[AA], x, y, z), grad(p[BA], x - 1, y, z)),
+                     lerp(u, grad(p[AB], x, y - 1, z), grad(p[BB], x - 1, y - 1, z))),
+                lerp(v, lerp(u, grad(p[AA + 1], x, y, z - 1), grad(p[BA + 1], x - 1, y, z - 1)),
+                     lerp(u, grad(p[AB + 1], x, y - 1, z - 1), grad(p[BB + 1], x - 1, y - 1, z - 1))))
+
+
+def _fbm3_torch(p, x, y, z, octaves=4):
+    total = 0.0
+    amp, freq, norm = 1.0, 1.0, 0.0
+    for _ in range(octaves):
+        total = total + amp * _noise3_torch(p, x * freq, y * freq, z * freq)
+        norm += amp
+        amp *= 0.5
+        freq *= 2.0
+    return total / norm
+
+
+def _raycast(scene: Scene, origin, dirs):
+    """Nearest hit distance t along rays with unit camera-z component (so t
+    is the camera depth) and the world hit points; torch float64."""
+    import torch
+    dev = dirs.device
+    o = torch.as_tensor(origin, dtype=torch.float64, device=dev)
     n = dirs.shape[0]
-    t_best = np.full(n, np.inf)
-    # ground plane y = cam_height
+    t_best = torch.full((n,), float("inf"), dtype=torch.float64, device=dev)
     dy = dirs[:, 1]
-    with np.errstate(divide="ignore", invalid="ignore"):
-        tg = (scene.cam_height - origin[1]) / dy
-    tg = np.where((dy > 1e-12) & (tg > 0), tg, np.inf)
-    t_best = np.minimum(t_best, tg)
-    # boxes (slab test)
-    with np.errstate(divide="ignore", invalid="ignore"):
-        inv = 1.0 / dirs
-    for b in scene.boxes:
-        lo = b[:3]
-        hi = b[3:]
-        with np.errstate(invalid="ignore"):
-            t1 = (lo - origin) * inv
-            t2 = (hi - origin) * inv
-        tmin = np.nanmax(np.minimum(t1, t2), axis=1)
-        tmax = np.nanmin(np.maximum(t1, t2), axis=1)
+    tg = (scene.cam_height - o[1]) / dy
+    tg = torch.where((dy > 1e-12) & (tg > 0), tg, torch.full_like(tg, float("inf")))
+    t_best = torch.minimum(t_best, tg)
+    inv = 1.0 / dirs
+    boxes = torch.as_tensor(scene.boxes, dtype=torch.float64, device=dev)
+    for b in boxes:
+        t1 = (b[:3] - o) * inv
+        t2 = (b[3:] - o) * inv
+        lo = torch.minimum(t1, t2).nan_to_num(nan=-float("inf"))
+        hi = torch.maximum(t1, t2).nan_to_num(nan=float("inf"))
+        tmin = lo.max(dim=1).values
+        tmax = hi.min(dim=1).values
         hit = (tmax >= tmin) & (tmax > 0)
-        th = np.where(tmin > 0, tmin, tmax)
-        t_best = np.where(hit & (th < t_best), th, t_best)
-    # backdrop sphere (origin inside): far root
-    oc = origin - scene.backdrop_center
-    a = np.einsum("ij,ij->i", dirs, dirs)
-    bq = 2.0 * dirs @ oc
-    cq = oc @ oc - scene.backdrop_radius ** 2
-    disc = np.maximum(bq * bq - 4.0 * a * cq, 0.0)
-    ts = (-bq + np.sqrt(disc)) / (2.0 * a)
-    t_best = np.minimum(t_best, ts)
-    return t_best, origin[None, :] + t_best[:, None] * dirs
+        th = torch.where(tmin > 0, tmin, tmax)
+        t_best = torch.where(hit & (th < t_best), th, t_best)
+    oc = o - torch.as_tensor(scene.backdrop_center, dtype=torch.float64, device=dev)
+    a = (dirs * dirs).sum(1)
+    bq = 2.0 * (dirs @ oc)
+    cq = (oc @ oc) - scene.backdrop_radius ** 2
+    disc = torch.clamp(bq * bq - 4.0 * a * cq, min=0.0)
+    ts = (-bq + torch.sqrt(disc)) / (2.0 * a)
+    t_best = torch.minimum(t_best, ts)
+    return t_best, o[None, :] + t_best[:, None] * dirs
 
 
 def render_view(scene: Scene, cam: Camera, Rwc: np.ndarray, centre: np.ndarray,
-                noise_rng: np.random.Generator | None):
-    """Intensity image (uint8) and camera-frame depth z for one camera."""
-    yy, xx = np.mgrid[0:cam.h, 0:cam.w].astype(np.float64)
-    d_cam = np.stack([(xx - cam.cx) / cam.f, (yy - cam.cy) / cam.f, np.ones_like(xx)], -1)
-    d_cam = d_cam.reshape(-1, 3)
-    dirs = d_cam @ Rwc.T
+                noise_rng: np.random.Generator | None, device="cpu"):
+    """Intensity image (uint8 numpy) and camera-frame depth z for one camera."""
+    import torch
+    yy, xx = torch.meshgrid(torch.arange(cam.h, dtype=torch.float64, device=device),
+                            torch.arange(cam.w, dtype=torch.float64, device=device),
+                            indexing="ij")
+    d_cam = torch.stack([(xx - cam.cx) / cam.f, (yy - cam.cy) / cam.f, torch.ones_like(xx)], -1)
+    dirs = d_cam.reshape(-1, 3) @ torch.as_tensor(Rwc, dtype=torch.float64, device=device).T
     t, pts = _raycast(scene, centre, dirs)
-    z = t  # rays have unit camera-z component, so t is the camera depth
-    pn = Perlin(scene.tex_seed)
-    v = 128.0 + 180.0 * pn.fbm3(pts[:, 0] / 0.6, pts[:, 1] / 0.6, pts[:, 2] / 0.6, octaves=4)
+    perm = rng(scene.tex_seed).permutation(256).astype(np.int64)
+    p = _perlin_torch(perm, device)
+    v = 128.0 + 180.0 * _fbm3_torch(p, pts[:, 0] / 0.6, pts[:, 1] / 0.6, pts[:, 2] / 0.6)
+    v = v.cpu().numpy()
     if noise_rng is not None and scene.noise_sigma > 0:
         v = v + noise_rng.normal(0.0, scene.noise_sigma, size=v.shape)
-    return _to_u8(v).reshape(cam.h, cam.w), z.reshape(cam.h, cam.w)
+    return _to_u8(v).reshape(cam.h, cam.w), t.cpu().numpy().reshape(cam.h, cam.w)
 
 
-def render_frame(scene: Scene, cam: Camera, k: int, noise: bool = True):
+def render_frame(scene: Scene, cam: Camera, k: int, noise: bool = True, device="cpu"):
     """Left/right uint8 images and left ground-truth disparity for frame k."""
     Rwc, c = scene.poses[k]
     nr = rng(splitmix64(scene.noise_seed + k)) if noise else None
-    left, zl = render_view(scene, cam, Rwc, c, nr)
+    left, zl = render_view(scene, cam, Rwc, c, nr, device)
     cr = c + Rwc @ np.array([cam.baseline, 0.0, 0.0])
-    right, _ = render_view(scene, cam, Rwc, cr, nr)
+    right, _ = render_view(scene, cam, Rwc, cr, nr, device)
     gt = cam.f * cam.baseline / zl
     return left, right, gt
 
@@ -322,8 +372,8 @@ class Sequence:
     scene: Scene
     n_frames: int
 
-    def frame(self, k: int, noise: bool = True):
-        return render_frame(self.scene, self.cam, k, noise)
+    def frame(self, k: int, noise: bool = True, device="cpu"):
+        return render_frame(self.scene, self.cam, k, noise, device)
 
     def motion(self, k: int):
         return relative_motion(self.scene, k)

@@ -1,0 +1,108 @@
+"""The C ABI library loads, exports every declared entry point and validates
+arguments on the host (no GPU needed: nothing here enqueues work)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1708_06301_amd import egosgm as eg
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                      "include", "egosgm.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return re.findall(r"^\s*(?:int|size_t|const char\s*\*)\s*(\w+)\s*\(", text, flags=re.M)
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared()
+    assert {"sgm_full", "sgm_reduced", "warp_disparity", "kalman_update",
+            "sgm_windows_from_prediction", "egosgm_census"} <= set(names)
+    lib = eg.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert eg.abi_version() == 1
+
+
+def test_workspace_sizes():
+    lib = eg.lib()
+    n = lib.egosgm_sgm_workspace_bytes(1242, 375, 128)
+    assert n >= 8 * 1242 * 375 * 128 + 16 * 1242 * 375
+    assert lib.egosgm_sgm_workspace_bytes(0, 10, 64) == 0
+    assert lib.egosgm_sgm_workspace_bytes(10, 10, 257) == 0
+    assert lib.egosgm_windows_workspace_bytes(1242, 375) >= 4 * 375
+
+
+FAKE = C.c_void_p(0x1000)   # never dereferenced: validation fails first
+
+
+def _prm(**kw):
+    base = dict(max_disp=64, p1=10, p2=120, s_max=80, lr_tol=1)
+    base.update(kw)
+    return eg.SgmParams(*base.values())
+
+
+@pytest.mark.parametrize("kw,code", [(dict(max_disp=0), -1), (dict(max_disp=257), -1),
+                                     (dict(p1=-1), -1), (dict(p1=50, p2=40), -1),
+                                     (dict(p2=194), -1), (dict(s_max=-1), -1)])
+def test_sgm_rejects_bad_params(kw, code):
+    lib = eg.lib()
+    prm = _prm(**kw)
+    rc = lib.sgm_full(FAKE, FAKE, 64, 32, 64, C.byref(prm), FAKE, FAKE, FAKE, None, None,
+                      FAKE, 1 << 40, None)
+    assert rc == code
+
+
+def test_sgm_rejects_bad_shapes_and_workspace():
+    lib = eg.lib()
+    prm = _prm()
+    assert lib.sgm_full(None, FAKE, 64, 32, 64, C.byref(prm), FAKE, FAKE, FAKE, None, None,
+                        FAKE, 1 << 40, None) == -1
+    assert lib.sgm_full(FAKE, FAKE, 64, 32, 63, C.byref(prm), FAKE, FAKE, FAKE, None, None,
+                        FAKE, 1 << 40, None) == -1
+    assert lib.sgm_full(FAKE, FAKE, 5000, 32, 5000, C.byref(prm), FAKE, FAKE, FAKE, None, None,
+                        FAKE, 1 << 40, None) == -4
+    assert lib.sgm_full(FAKE, FAKE, 64, 32, 64, C.byref(prm), FAKE, FAKE, FAKE, None, None,
+                        FAKE, 100, None) == -2
+    assert lib.sgm_reduced(FAKE, FAKE, 64, 32, 64, None, FAKE, FAKE, C.byref(prm), FAKE, FAKE,
+                           FAKE, None, None, FAKE, 1 << 40, None) == -1
+
+
+def test_windows_warp_kalman_validation():
+    lib = eg.lib()
+    assert lib.sgm_windows_from_prediction(FAKE, None, 64, 32, 3.0, -1, 0, 8, 64, FAKE, FAKE,
+                                           FAKE, FAKE, 1 << 20, None) == -1
+    assert lib.sgm_windows_from_prediction(FAKE, FAKE, 64, 32, 3.0, -1, 9, 8, 64, FAKE, FAKE,
+                                           FAKE, FAKE, 1 << 20, None) == -1
+    assert lib.sgm_windows_from_prediction(FAKE, FAKE, 64, 32, 3.0, -1, 0, 8, 64, FAKE, FAKE,
+                                           FAKE, FAKE, 4, None) == -2
+    R = (C.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1)
+    t = (C.c_double * 3)(0, 0, -1)
+    assert lib.warp_disparity(FAKE, FAKE, 64, 32, R, t, 700.0, 32.0, 16.0, 0.54, 0.0, FAKE, FAKE,
+                              FAKE, None) == -1
+    assert lib.warp_disparity(FAKE, FAKE, 64, 32, R, t, -1.0, 32.0, 16.0, 0.54, 0.5, FAKE, FAKE,
+                              FAKE, None) == -1
+    assert lib.kalman_update(FAKE, FAKE, FAKE, FAKE, -1, 0, FAKE, FAKE, None) == -1
+    assert lib.kalman_update(FAKE, FAKE, FAKE, FAKE, 0, 0, FAKE, FAKE, None) == 0
+
+
+def test_warp_matrix_host_helper_matches_oracle(orc):
+    r = np.random.default_rng(0)
+    for _ in range(50):
+        a, b, c = r.normal(0, 0.05, 3)
+        Ry = np.array([[np.cos(a), 0, np.sin(a)], [0, 1, 0], [-np.sin(a), 0, np.cos(a)]])
+        Rx = np.array([[1, 0, 0], [0, np.cos(b), -np.sin(b)], [0, np.sin(b), np.cos(b)]])
+        Rz = np.array([[np.cos(c), -np.sin(c), 0], [np.sin(c), np.cos(c), 0], [0, 0, 1]])
+        R = Ry @ Rx @ Rz
+        t = r.normal(0, 1, 3)
+        cam = (r.uniform(300, 1500), r.uniform(100, 1000), r.uniform(50, 500), r.uniform(0.1, 1))
+        H = eg.warp_matrix(R, t, *cam)
+        Ho = orc.warp_matrix(R, t, *cam)
+        assert np.array_equal(H, Ho.astype(np.float32))
+    assert np.array_equal(eg.warp_matrix(np.eye(3), np.zeros(3), 718, 620.5, 187, 0.54),
+                          np.eye(4, dtype=np.float32))

@@ -1,0 +1,226 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Integer results (census codes, costs, path costs, aggregated costs, WTA and
+right maps, LR decisions, windows, warp validity) must be bit-exact; float
+results (subpixel, warp, Kalman) must be within 1e-4 px of the oracle's
+double-precision values.  Inputs are seeded synthetic images; every case
+prints its parameters before it runs.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as orc
+from paper_1708_06301_amd import egosgm as eg
+from paper_1708_06301_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+DEV = "cuda:0"
+
+
+def _say(*a):
+    print("CASE", *a, flush=True)
+
+
+def _gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _random_pair(w, h, seed, max_shift=20):
+    r = np.random.default_rng(seed)
+    left = synth.texture(w, h, seed, noise_sigma=8.0, scale=5.0)
+    shift = int(r.integers(0, max_shift + 1))
+    right = np.roll(left, -shift, axis=1)
+    right = np.clip(right.astype(int) + r.integers(-3, 4, size=right.shape), 0, 255).astype(np.uint8)
+    return left, right
+
+
+def _check_sgm(g, o, total, debug=True):
+    assert np.array_equal(_np(g["disp_wta"]), o["disp_wta"])
+    assert np.array_equal(_np(g["disp_right"]), o["disp_right"])
+    assert np.array_equal(_np(g["var_meas"]).astype(np.float64), o["var_meas"])
+    sub = _np(g["disp_sub"]).astype(np.float64)
+    assert np.array_equal(sub < 0, o["disp_sub"] < 0)
+    assert np.abs(sub - o["disp_sub"]).max() <= TOL
+    if debug:
+        assert np.array_equal(_np(g["wta_raw"]), o["wta_raw"])
+        assert np.array_equal(_np(g["census_left"]).view(np.uint64), o["census_l"])
+        assert np.array_equal(_np(g["census_right"]).view(np.uint64), o["census_r"])
+        assert np.array_equal(_np(g["cost"])[:total].astype(np.int32), o["cost"])
+        assert np.array_equal(_np(g["agg"])[:total].view(np.uint16).astype(np.int32), o["agg"])
+        paths = _np(g["paths"])
+        for k in range(8):
+            assert np.array_equal(paths[k, :total].astype(np.int32), o["paths"][k]), f"path {k}"
+
+
+@pytest.mark.parametrize("w,h", [(17, 9), (70, 13), (320, 96), (129, 7)])
+def test_census(w, h):
+    _say("census", w, h)
+    img = np.random.default_rng(w * h).integers(0, 256, size=(h, w)).astype(np.uint8)
+    g = _np(eg.census(_gpu(img))).view(np.uint64)
+    assert np.array_equal(g, orc.census(img))
+
+
+@pytest.mark.parametrize("w,h,D", [(37, 19, 8), (53, 21, 24), (66, 17, 40), (70, 23, 64),
+                                   (45, 30, 100), (70, 23, 128), (150, 9, 128), (290, 11, 256)])
+def test_sgm_full_tiny(w, h, D):
+    _say("sgm_full", w, h, D)
+    left, right = _random_pair(w, h, seed=w + 100 * D, max_shift=min(D - 1, 20))
+    prm = eg.MatchParams(max_disp=D, p1=7, p2=90, s_max=60, lr_tol=1)
+    g = eg.sgm_full(_gpu(left), _gpu(right), prm, debug=True)
+    o = orc.sgm(left, right, D, p1=7, p2=90, s_max=60, lr_tol=1, want_debug=True)
+    _check_sgm(g, o, w * h * D)
+
+
+def test_sgm_full_planes_config():
+    _say("sgm_full planes 320x96 D=64")
+    left, right, _ = synth.planes_pair()
+    prm = eg.MatchParams(max_disp=64, p1=10, p2=120, s_max=80, lr_tol=1)
+    g = eg.sgm_full(_gpu(left), _gpu(right), prm, debug=True)
+    o = orc.sgm(left, right, 64, p1=10, p2=120, s_max=80, lr_tol=1, want_debug=True)
+    _check_sgm(g, o, 320 * 96 * 64)
+
+
+def _random_windows(w, h, D, seed, rmax=6, frac_full=0.1):
+    r = np.random.default_rng(seed)
+    d = r.uniform(0, D - 1, size=(h, w)).astype(np.float32)
+    d[r.random((h, w)) < frac_full] = -1.0
+    p = r.uniform(0, (rmax / 3.0) ** 2, size=(h, w)).astype(np.float32)
+    return d, p
+
+
+@pytest.mark.parametrize("w,h,D,seed", [(37, 19, 16, 1), (64, 20, 64, 2), (91, 27, 128, 3),
+                                        (33, 5, 256, 4)])
+def test_sgm_reduced_ragged(w, h, D, seed):
+    _say("sgm_reduced", w, h, D, seed)
+    left, right = _random_pair(w, h, seed=seed + 7, max_shift=min(D - 1, 30))
+    d, p = _random_windows(w, h, D, seed)
+    lo, hi, off = eg.windows_from_prediction(_gpu(d), _gpu(p), D, r_min=0, r_max=12)
+    wo = orc.windows(d, p, D, r_min=0, r_max=12)
+    assert np.array_equal(_np(lo).ravel(), wo[0])
+    assert np.array_equal(_np(hi).ravel(), wo[1])
+    assert np.array_equal(_np(off).view(np.uint32), wo[2])
+    prm = eg.MatchParams(max_disp=D, p1=10, p2=120, s_max=80, lr_tol=1)
+    g = eg.sgm_reduced(_gpu(left), _gpu(right), lo, hi, off, prm, debug=True)
+    o = orc.sgm(left, right, D, windows=wo, want_debug=True)
+    _check_sgm(g, o, int(wo[2][-1]))
+
+
+@pytest.mark.parametrize("D", [48, 128])
+def test_sgm_reduced_full_windows_equal_full(D):
+    _say("reduced == full, 120x40", D)
+    left, right = _random_pair(120, 40, seed=17, max_shift=30)
+    lo, hi, off = eg.windows_from_prediction(_gpu(np.full((40, 120), -1, np.float32)), None, D,
+                                             r_fixed=3)
+    prm = eg.MatchParams(max_disp=D)
+    a = eg.sgm_reduced(_gpu(left), _gpu(right), lo, hi, off, prm, debug=True)
+    b = eg.sgm_full(_gpu(left), _gpu(right), prm, debug=True)
+    for k in ("disp_wta", "disp_sub", "var_meas", "disp_right", "agg", "paths"):
+        assert torch.equal(a[k], b[k]), k
+
+
+def test_windows_edge_values():
+    _say("windows edge values")
+    D = 128
+    d = np.array([10.5, 10.499999, 1.0, -1.0, 200.0, np.nan, 0.0, 127.0, 126.5, 65536.0,
+                  70000.0, -0.0, 3.5, 2.5], np.float32)
+    p = np.array([1.0, 1.0000001, 0.0, 100.0, -1.0, np.inf, 4.0, 0.25, np.nan, 1, 1, 2.25,
+                  1e-30, 1e30], np.float32)
+    for r_fixed in (-1, 4):
+        lo, hi, off = eg.windows_from_prediction(_gpu(d[None, :]), _gpu(p[None, :]), D,
+                                                 r_fixed=r_fixed, r_min=1, r_max=16)
+        wo = orc.windows(d, p, D, r_fixed=r_fixed, r_min=1, r_max=16)
+        assert np.array_equal(_np(lo).ravel(), wo[0]) and np.array_equal(_np(hi).ravel(), wo[1])
+        assert np.array_equal(_np(off).view(np.uint32), wo[2])
+    r = np.random.default_rng(3)
+    d = (r.integers(0, 300, 5000) / 2.0 + r.choice([0, 1e-6, -1e-6], 5000)).astype(np.float32)
+    p = (r.integers(0, 30, 5000) ** 2 / 9.0 * r.choice([1, 1 + 1e-7, 1 - 1e-7], 5000)).astype(np.float32)
+    lo, hi, off = eg.windows_from_prediction(_gpu(d.reshape(50, 100)), _gpu(p.reshape(50, 100)), D,
+                                             r_min=0, r_max=40)
+    wo = orc.windows(d, p, D, r_min=0, r_max=40)
+    assert np.array_equal(_np(lo).ravel(), wo[0]) and np.array_equal(_np(hi).ravel(), wo[1])
+    assert np.array_equal(_np(off).view(np.uint32), wo[2])
+
+
+def _rot(a, b, c):
+    ca, sa, cb, sb, cc, sc = np.cos(a), np.sin(a), np.cos(b), np.sin(b), np.cos(c), np.sin(c)
+    return (np.array([[ca, 0, sa], [0, 1, 0], [-sa, 0, ca]]) @
+            np.array([[1, 0, 0], [0, cb, -sb], [0, sb, cb]]) @
+            np.array([[cc, -sc, 0], [sc, cc, 0], [0, 0, 1]]))
+
+
+def _close(g, o):
+    """|g - o| within 1e-4 px, or half a float32 ulp of o where that is larger
+    (only for values above 2048, far outside any disparity range)."""
+    tol = np.maximum(TOL, 0.5 * np.spacing(np.abs(o).astype(np.float32)).astype(np.float64))
+    return bool((np.abs(g.astype(np.float64) - o) <= tol).all())
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4, 5])
+def test_warp(seed):
+    r = np.random.default_rng(seed)
+    w, h = (1242, 375) if seed == 0 else (int(r.integers(20, 300)), int(r.integers(10, 120)))
+    _say("warp", w, h, seed)
+    d = r.uniform(0.5, 120, size=(h, w)).astype(np.float32)
+    d[r.random((h, w)) < 0.1] = -1.0
+    p = r.uniform(0.01, 6, size=(h, w)).astype(np.float32)
+    R = _rot(*r.normal(0, 0.01, 3))
+    t = np.array([r.normal(0, 0.05), r.normal(0, 0.02), -abs(r.normal(1.0, 0.2))])
+    f = 718.0 * w / 1242.0
+    cam = (f, (w - 1) / 2, (h - 1) / 2, 0.54)
+    H = eg.warp_matrix(R, t, *cam)
+    Ho = orc.warp_matrix(R, t, *cam).astype(np.float32)
+    assert np.array_equal(H, Ho)
+    gd, gp = eg.warp_disparity(_gpu(d), _gpu(p), R, t, *cam, 0.5)
+    o = orc.warp(d, p, R, t, *cam, q=0.5)
+    gd, gp = _np(gd), _np(gp)
+    valid = o["winner"] >= 0
+    assert np.array_equal(gd >= 0, valid)
+    assert _close(gd[valid], o["d_pred"][valid])
+    assert _close(gp[valid], o["p_pred"][valid])
+    assert (gd[~valid] == -1).all() and (gp[~valid] == 0).all()
+
+
+def test_warp_identity_and_collisions():
+    _say("warp identity")
+    r = np.random.default_rng(9)
+    d = r.uniform(1, 50, size=(31, 77)).astype(np.float32)
+    p = r.uniform(0, 3, size=(31, 77)).astype(np.float32)
+    gd, gp = eg.warp_disparity(_gpu(d), _gpu(p), np.eye(3), np.zeros(3), 300.0, 38.0, 15.0, 0.5, 0.25)
+    assert np.array_equal(_np(gd), d) and np.array_equal(_np(gp), p + np.float32(0.25))
+    # many sources per target: strong backward motion contracts the image
+    d = np.full((40, 60), 20.0, np.float32) + r.uniform(0, 1, (40, 60)).astype(np.float32)
+    d[:, ::7] = 20.0  # exact ties between sources
+    p = r.uniform(0, 3, size=(40, 60)).astype(np.float32)
+    cam = (100.0, 29.5, 19.5, 0.5)
+    t = np.array([0.0, 0.0, 5.0])
+    gd, gp = eg.warp_disparity(_gpu(d), _gpu(p), np.eye(3), t, *cam, 0.5)
+    o = orc.warp(d, p, np.eye(3), t, *cam, q=0.5)
+    gd, gp = _np(gd), _np(gp)
+    assert np.array_equal(gd >= 0, o["winner"] >= 0)
+    assert _close(gd, o["d_pred"]) and _close(gp, o["p_pred"])
+
+
+def test_kalman():
+    _say("kalman")
+    r = np.random.default_rng(4)
+    n = 100003
+    dp = r.uniform(0, 255, n).astype(np.float32)
+    pp = r.uniform(0.001, 100, n).astype(np.float32)
+    z = (dp + r.normal(0, 3, n)).astype(np.float32)
+    rr = r.integers(0, 60, n).astype(np.float32)
+    dp[r.random(n) < 0.1] = -1
+    z[r.random(n) < 0.1] = -1
+    pp[r.random(n) < 0.02] = 0
+    for keep in (0, 1):
+        gd, gp = eg.kalman_update(*[_gpu(a) for a in (dp, pp, z, rr)], keep_unmeasured=keep)
+        od, op = orc.kalman(dp, pp, z, rr, keep)
+        gd, gp = _np(gd), _np(gp)
+        assert np.array_equal(gd < 0, od < 0)
+        assert np.abs(gd - od).max() <= TOL and np.abs(gp - op).max() <= TOL

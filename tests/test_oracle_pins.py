@@ -313,8 +313,9 @@ def test_warp_identity(orc):
     assert np.array_equal(H.astype(np.float32), np.eye(4, dtype=np.float32))
     out = orc.warp(d, p, np.eye(3), np.zeros(3), q=0.5, **CAM)
     assert np.array_equal(out["winner"].ravel(), np.arange(24 * 40))
-    assert np.array_equal(out["d_pred_f32"], d)
-    assert np.array_equal(out["p_pred_f32"], p + np.float32(0.5))
+    assert np.array_equal(out["d_key_f32"], d)
+    assert np.array_equal(out["d_pred"], d.astype(np.float64))
+    assert np.array_equal(out["p_pred"], p.astype(np.float64) + 0.5)
     assert np.abs(out["d_pred"] - d).max() < 1e-9
 
 
@@ -360,7 +361,7 @@ def test_warp_values_match_reprojection(orc):
     assert np.allclose(out["p_pred"].ravel()[ok], phi * phi * p.ravel()[win[ok]] + 0.5,
                        rtol=1e-12)
     # the float32 values the z-buffer compared agree with the double ones
-    assert np.abs(out["d_pred_f32"].ravel()[ok] - out["d_pred"].ravel()[ok]).max() < 1e-4
+    assert np.abs(out["d_key_f32"].ravel()[ok] - out["d_pred"].ravel()[ok]).max() < 1e-4
 
 
 def test_warp_forward_translation_closed_form(orc):
@@ -394,14 +395,18 @@ def test_warp_zbuffer_keeps_nearest(orc):
     # Equal predicted disparity: moving back by tau contracts the image about
     # the principal point, x' = x fb/(fb + tau d); with fb = 100, d = 2 and
     # tau = 61.1 the factor is 0.45, so x=2 -> 0.9 and x=3 -> 1.35 both land on
-    # pixel 1 with the same d'; the smaller predicted variance wins.
+    # pixel 1 with the same d'.  The paper is silent on such ties; the source
+    # with the smaller pixel index is kept, whatever the variances.
     cam2 = dict(f=100.0, cx=0.0, cy=0.0, b=1.0)
-    d = np.array([[-1, -1, 2.0, 2.0, -1, -1]], np.float32)
-    p = np.array([[1, 1, 4.0, 1.0, 1, 1]], np.float32)
-    out = orc.warp(d, p, np.eye(3), np.array([0.0, 0, 100.0 / 0.45 / 2 - 50.0]), q=0.5, **cam2)
-    assert out["winner"][0, 1] == 3
-    assert out["d_pred"][0, 1] == pytest.approx(0.9)
-    assert (out["winner"][0, [0, 2, 3, 4, 5]] == -1).all()
+    t = np.array([0.0, 0, 100.0 / 0.45 / 2 - 50.0])
+    for p2, p3 in ((4.0, 1.0), (1.0, 4.0)):
+        d = np.array([[-1, -1, 2.0, 2.0, -1, -1]], np.float32)
+        p = np.array([[1, 1, p2, p3, 1, 1]], np.float32)
+        out = orc.warp(d, p, np.eye(3), t, q=0.5, **cam2)
+        assert out["winner"][0, 1] == 2
+        assert out["d_pred"][0, 1] == pytest.approx(0.9)
+        assert out["p_pred"][0, 1] == pytest.approx(0.45 ** 2 * p2 + 0.5)
+        assert (out["winner"][0, [0, 2, 3, 4, 5]] == -1).all()
 
 
 def test_warp_drops_invalid_and_outside(orc):
