@@ -48,9 +48,14 @@ def build_sequence(n_frames, w, h, device):
     return seq, frames, pipeline.motions(seq)
 
 
-def run_sequence(state, frames, motions, events=None):
+def run_sequence(state, frames, motions, events=None, stage_timing=False):
+    """One step.  With stage_timing, the library's per-stage events are on
+    for frames 1.. only, so the stage figures describe the reduced frames."""
+    from paper_1708_06301_amd import egosgm as eg
     state.reset()
     for k, (L, R) in enumerate(frames):
+        if stage_timing:
+            eg.timing_enable(k > 0)
         if events is not None:
             events[k][0].record()
         if k == 0:
@@ -59,6 +64,8 @@ def run_sequence(state, frames, motions, events=None):
             state.step(L, R, *motions[k])
         if events is not None:
             events[k][1].record()
+    if stage_timing:
+        eg.timing_enable(False)
 
 
 def searched_updates(state, frames, motions):
@@ -80,14 +87,14 @@ def searched_updates(state, frames, motions):
     return tot, per
 
 
-def timed_steps(state, frames, motions, steps, with_events=True):
+def timed_steps(state, frames, motions, steps, with_events=True, stage_timing=False):
     import torch
     ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in frames] for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(steps):
-        run_sequence(state, frames, motions, ev[s] if with_events else None)
+        run_sequence(state, frames, motions, ev[s] if with_events else None, stage_timing)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     lat = np.array([[a.elapsed_time(b) for a, b in row] for row in ev]) if with_events else None
@@ -114,7 +121,8 @@ def cpu_baseline(seq, frames_np, motions, cfg, budget_s=20.0):
         else:
             Rm, t = motions[k]
             wp = orc.warp(d, p, Rm, t, cam.f, cam.cx, cam.cy, cam.baseline, cfg.q)
-            dp, pp = wp["d_pred"].astype(np.float32), wp["p_pred"].astype(np.float32)
+            dp, pp = orc.refine(wp["d_pred"].astype(np.float32), wp["p_pred"].astype(np.float32),
+                                cfg.edge_tol, cfg.fill_tol)
             win = orc.windows(dp, pp, cfg.max_disp, r_fixed=cfg.r_fixed, r_min=cfg.r_min,
                               r_max=cfg.r_max)
             o = orc.sgm(L, R, cfg.max_disp, cfg.p1, cfg.p2, cfg.s_max, cfg.lr_tol, windows=win)
@@ -128,7 +136,7 @@ def cpu_baseline(seq, frames_np, motions, cfg, budget_s=20.0):
     dt = time.perf_counter() - t0
     return dict(value=round(upd / dt / 1e9, 4), unit="GCUPS", cores=1, kind="oracle",
                 sample=f"frames 0..{k - 1} of the same sequence (frame 0 full range D="
-                       f"{cfg.max_disp}, then warp + windows r={cfg.r_fixed} + reduced SGM + "
+                       f"{cfg.max_disp}, then warp + refine + windows r={cfg.r_fixed} + reduced SGM + "
                        f"Kalman), single-threaded plain C oracle, {dt:.1f} s")
 
 
@@ -142,6 +150,7 @@ def main():
     ap.add_argument("--height", type=int, default=375)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the path has no "
@@ -159,11 +168,15 @@ def main():
     seq, frames, motions = build_sequence(nf, w, h, dev)
     calib = pipeline.camera_of(seq)
     cfg = pipeline.FrameConfig(max_disp=128, p1=10, p2=120, s_max=80, lr_tol=1, q=0.5,
-                               r_fixed=4, r_min=0, r_max=256)
+                               r_fixed=4, r_min=0, r_max=256, edge_tol=2.0, fill_tol=1.0)
     red = pipeline.StreamState(w, h, calib, cfg, dev)
     cfg_full = pipeline.FrameConfig(**{**cfg.__dict__, "full_range_only": True})
     full = pipeline.StreamState(w, h, calib, cfg_full, dev)
 
+    from paper_1708_06301_amd import autotune
+    tuning, tune_times = autotune.tune(lambda: run_sequence(red, frames, motions), w, h,
+                                       cfg.max_disp, tag="street", use_cache=not args.retune,
+                                       log=log)
     upd_red, per_frame = searched_updates(red, frames, motions)
     upd_full, _ = searched_updates(full, frames, motions)
     n = w * h
@@ -176,9 +189,7 @@ def main():
 
     # main timed region: reduced pipeline, stage events on
     eg.timing_read()
-    eg.timing_enable(True)
-    dt, lat = timed_steps(red, frames, motions, args.steps)
-    eg.timing_enable(False)
+    dt, lat = timed_steps(red, frames, motions, args.steps, stage_timing=True)
     stages = eg.timing_read()
     dt_full, lat_full = timed_steps(full, frames, motions, args.steps)
 
@@ -189,23 +200,21 @@ def main():
     fps_full = nf * args.steps / dt_full
     red_lat = lat[:, 1:].ravel()
 
-    # dominant kernel: the stage with the largest total time
+    # dominant kernel of the reduced frames (stage events cover frames 1..)
     dom = max(stages, key=lambda s: stages[s][0])
     dom_ms, dom_n = stages[dom]
     avg_ms = dom_ms / max(dom_n, 1)
-    # algorithmic bytes per launch of the dominant kernel, averaged over the
-    # step's launches (frame 0 full range, frames 1.. ragged); S_f = searched
-    # slots of frame f, n = pixels.
-    #   paths:  reads C once and writes L once per slot and direction (2 B per
-    #           update) plus, for ragged windows, lo/hi/offset (8 B) per pixel
-    #           and direction;
-    #   select: reads the 8 path costs per slot (8 B), the window (8 B/px,
-    #           ragged) and writes disparity, subpixel and variance (10 B/px).
-    n_ragged = nf - 1
+    # algorithmic bytes per launch of that kernel on a reduced frame, with
+    # S = mean searched slots of frames 1.. and n = pixels:
+    #   paths:  reads C and writes L once per slot and direction (16 B per
+    #           slot) plus lo/hi/offset (8 B) per pixel and direction;
+    #   select: reads the 8 path costs per slot (8 B), the window (8 B/px)
+    #           and writes disparity, subpixel and variance (10 B/px).
+    S_red = float(np.mean(per_frame[1:]))
     if dom == "paths":
-        alg_bytes = (2 * upd_red + 64 * n * n_ragged) / nf
+        alg_bytes = 16 * S_red + 64 * n
     elif dom == "select":
-        alg_bytes = (upd_red + 8 * n * n_ragged + 10 * n * nf) / nf
+        alg_bytes = 8 * S_red + 18 * n
     else:
         alg_bytes = None
     roof = None
@@ -230,7 +239,7 @@ def main():
         "dtype": "u8",
         "data": "synthetic",
         "config": {"workload": f"street sequence {w}x{h}, {nf} frames: frame 0 full SGM "
-                               f"D={cfg.max_disp}, frames 1-{nf - 1} warp + Kalman (f32) + "
+                               f"D={cfg.max_disp}, frames 1-{nf - 1} warp + refine + Kalman (f32) + "
                                f"reduced SGM r=+-{cfg.r_fixed}; census 9x7, 8 paths, P1=10, P2=120",
                    "w": w, "h": h, "frames": nf, "max_disp": cfg.max_disp, "r": cfg.r_fixed},
         "fps": round(fps, 1),
@@ -245,6 +254,7 @@ def main():
                             "per_frame": [round(x, 4) for x in search_frac]},
         "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
         "roofline": roof,
+        "tuning": tuning,
     }
     if not args.no_cpu_baseline:
         frames_np = [(L.cpu().numpy(), R.cpu().numpy()) for L, R in frames]

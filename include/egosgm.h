@@ -193,6 +193,26 @@ int warp_disparity(const float* d_prev, const float* p_prev, int w, int h,
                    double baseline, float q, float* d_pred, float* p_pred, uint64_t* zbuf,
                    void* stream);
 
+/* ------------------------------------------------------------------ refine
+ * Refinement of the predicted map (Sec. 2.2.2), three passes in order:
+ *  1. edge rejection: the paper drops predictions near disparity
+ *     discontinuities without stating a test; here a valid prediction is
+ *     dropped when a valid pixel of its 3x3 neighbourhood differs from it by
+ *     more than edge_tol (float32 comparison; edge_tol < 0 disables it);
+ *  2. horizontal one-pixel "zoom" hole filling (Eq. 7-8): an invalid pixel
+ *     whose left and right neighbours are valid with |a - b| < fill_tol gets
+ *     d = (a + b)/2 and the mean of the neighbours' variances (the paper
+ *     gives no variance rule); the pass reads the result of step 1 only;
+ *  3. the same with the vertical neighbours, reading the result of step 2.
+ * fill_tol <= 0 disables steps 2 and 3.  Means are correctly rounded floats.
+ * d_in, p_in: w*h float (a predicted map, e.g. from warp_disparity);
+ * d_out, p_out: w*h float, must not alias the inputs; workspace: device
+ * memory of egosgm_refine_workspace_bytes(w, h). */
+size_t egosgm_refine_workspace_bytes(int w, int h);
+int refine_prediction(const float* d_in, const float* p_in, int w, int h, float edge_tol,
+                      float fill_tol, float* d_out, float* p_out, void* workspace,
+                      size_t workspace_bytes, void* stream);
+
 /* ------------------------------------------------------------------ update
  * Pixel-wise Kalman update (Sec. 2.4, Eq. 10-12), float32 in this order:
  *   K = p/(p + r); d = d_pred + K (z - d_pred); p = (1 - K) p_pred.
@@ -206,8 +226,21 @@ int kalman_update(const float* d_pred, const float* p_pred, const float* d_meas,
                   const float* r_meas, int n, int keep_unmeasured, float* d_out, float* p_out,
                   void* stream);
 
+/* ------------------------------------------------------------------ tuning
+ * Launch shapes of the path kernels, process-wide (the second piece of state
+ * the library keeps; set it before enqueueing work, e.g. from an autotuner).
+ * Results never depend on it.  Defaults: {32, 32, 1}. */
+typedef struct egosgm_tuning {
+    int32_t full_group;   /* lanes per scanline of the full-range path kernel: 16, 32, 64 */
+    int32_t ragged_group; /* lanes per scanline of the ragged path kernel: 16, 32, 64      */
+    int32_t prio_long;    /* 1: the longest scanlines run at raised wave priority, 0: not */
+} egosgm_tuning;
+
+int egosgm_set_tuning(const egosgm_tuning* tuning);
+int egosgm_get_tuning(egosgm_tuning* tuning);
+
 /* ------------------------------------------------------------------ timing
- * Opt-in profiling aid (the one piece of state the library keeps): while
+ * Opt-in profiling aid (library state like the tuning above): while
  * enabled, each stage the library enqueues is bracketed by a pair of HIP
  * events recorded on the caller's stream.  egosgm_timing_read waits for the
  * recorded events, adds the elapsed milliseconds and launch counts per stage
@@ -221,7 +254,8 @@ typedef enum egosgm_stage {
     EGOSGM_STAGE_SELECT = 4,  /* WTA/subpixel/uncertainty/right map, LR (two kernels) */
     EGOSGM_STAGE_WARP = 5,    /* z-buffer clear, scatter, decode (three kernels) */
     EGOSGM_STAGE_KALMAN = 6,  /* Kalman update (one kernel)                      */
-    EGOSGM_STAGE_COUNT = 7
+    EGOSGM_STAGE_REFINE = 7,  /* prediction refinement (three kernels)           */
+    EGOSGM_STAGE_COUNT = 8
 } egosgm_stage;
 
 int egosgm_timing_enable(int on);

@@ -474,6 +474,73 @@ int orc_warp(const float* d_prev, const float* p_prev, int w, int h,
     return 0;
 }
 
+/* Refinement of the predicted map (Sec. 2.2.2), in this order:
+ *  1. edge rejection: the paper drops predictions near disparity
+ *     discontinuities without giving a test; here a valid predicted pixel is
+ *     dropped when a valid pixel of its 3x3 neighbourhood differs from it by
+ *     more than edge_tol (float32 comparison; edge_tol < 0 disables it);
+ *  2. horizontal "zoom" hole filling (Eq. 7-8): an invalid pixel whose left
+ *     and right neighbours are valid with |a - b| < fill_tol (float32) gets
+ *     d = (a + b)/2 and, as the paper gives no rule for the variance, the
+ *     mean of the two neighbours' variances; the pass reads the map left by
+ *     step 1 only, so fills do not propagate along a row;
+ *  3. the same with the vertical neighbours, reading the result of step 2.
+ * fill_tol <= 0 disables steps 2 and 3.  The means are exact in double and
+ * rounded once to float32.  Outputs may not alias the inputs. */
+int orc_refine(const float* d_in, const float* p_in, int w, int h, float edge_tol,
+               float fill_tol, float* d_out, float* p_out) {
+    if (!d_in || !p_in || !d_out || !p_out || w <= 0 || h <= 0) return -1;
+    const size_t n = (size_t)w * (size_t)h;
+    float* ed = malloc(n * sizeof(float));
+    float* ep = malloc(n * sizeof(float));
+    float* hd = malloc(n * sizeof(float));
+    float* hp = malloc(n * sizeof(float));
+    if (!ed || !ep || !hd || !hp) { free(ed); free(ep); free(hd); free(hp); return -2; }
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x) {
+            const size_t i = (size_t)y * w + x;
+            const float d = d_in[i];
+            int keep = d >= 0.0f;
+            if (keep && edge_tol >= 0.0f) {
+                for (int dy = -1; dy <= 1 && keep; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        const int xx = x + dx, yy = y + dy;
+                        if (xx < 0 || xx >= w || yy < 0 || yy >= h) continue;
+                        const float e = d_in[(size_t)yy * w + xx];
+                        if (e >= 0.0f && fabsf(d - e) > edge_tol) { keep = 0; break; }
+                    }
+            }
+            ed[i] = keep ? d : -1.0f;
+            ep[i] = keep ? p_in[i] : 0.0f;
+        }
+    for (size_t i = 0; i < n; ++i) { hd[i] = ed[i]; hp[i] = ep[i]; }
+    if (fill_tol > 0.0f) {
+        for (int y = 0; y < h; ++y)
+            for (int x = 1; x + 1 < w; ++x) {
+                const size_t i = (size_t)y * w + x;
+                const float a = ed[i - 1], b = ed[i + 1];
+                if (ed[i] < 0.0f && a >= 0.0f && b >= 0.0f && fabsf(a - b) < fill_tol) {
+                    hd[i] = (float)(((double)a + (double)b) / 2.0);
+                    hp[i] = (float)(((double)ep[i - 1] + (double)ep[i + 1]) / 2.0);
+                }
+            }
+    }
+    for (size_t i = 0; i < n; ++i) { d_out[i] = hd[i]; p_out[i] = hp[i]; }
+    if (fill_tol > 0.0f) {
+        for (int y = 1; y + 1 < h; ++y)
+            for (int x = 0; x < w; ++x) {
+                const size_t i = (size_t)y * w + x;
+                const float a = hd[i - w], b = hd[i + w];
+                if (hd[i] < 0.0f && a >= 0.0f && b >= 0.0f && fabsf(a - b) < fill_tol) {
+                    d_out[i] = (float)(((double)a + (double)b) / 2.0);
+                    p_out[i] = (float)(((double)hp[i - w] + (double)hp[i + w]) / 2.0);
+                }
+            }
+    }
+    free(ed); free(ep); free(hd); free(hp);
+    return 0;
+}
+
 /* Pixel-wise Kalman update (Sec. 2.4, Eq. 10-12):
  *   K = p/(p + r), d = d_pred + K (z - d_pred), p = (1 - K) p_pred.
  * Validity (the paper takes no prediction as it is, Sec. 2.3.2, and rejected

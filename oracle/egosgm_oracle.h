@@ -93,6 +93,11 @@ int orc_warp(const float* d_prev, const float* p_prev, int w, int h,
              double b, double q, double* d_pred, double* p_pred,
              int32_t* winner, float* d_key_f32);
 
+/* Prediction refinement: edge rejection, then horizontal and vertical
+ * one-pixel hole filling (float outputs, exact means). */
+int orc_refine(const float* d_in, const float* p_in, int w, int h, float edge_tol,
+               float fill_tol, float* d_out, float* p_out);
+
 /* Pixel-wise Kalman update in double. */
 int orc_kalman(const float* d_pred, const float* p_pred, const float* z,
                const float* r, int n, int keep_unmeasured,

@@ -211,3 +211,15 @@ def lr_check(disp_right, disp_wta, lr_tol=1, disp_sub=None, var_meas=None):
     var = None if var_meas is None else np.array(var_meas, dtype=np.float64, copy=True)
     _check(lib().orc_lr_check(_p(dr), w, h, lr_tol, _p(wta), _p(sub), _p(var)), "lr_check")
     return wta, sub, var
+
+
+def refine(d_pred, p_pred, edge_tol=-1.0, fill_tol=1.0):
+    """Edge rejection + zoom hole filling; returns float32 (d, p)."""
+    d = np.ascontiguousarray(d_pred, dtype=np.float32)
+    p = np.ascontiguousarray(p_pred, dtype=np.float32)
+    h, w = d.shape
+    od = np.zeros_like(d)
+    op = np.zeros_like(p)
+    _check(lib().orc_refine(_p(d), _p(p), w, h, C.c_float(edge_tol), C.c_float(fill_tol),
+                            _p(od), _p(op)), "refine")
+    return od, op

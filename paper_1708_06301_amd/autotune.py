@@ -1,0 +1,92 @@
+"""Autotuner for the path kernels' launch shapes.
+
+Results never depend on the launch shape (lanes per scanline of the
+full-range and ragged kernels, raised wave priority for the longest
+scanlines); only speed does.  tune() times a caller-supplied workload under
+each candidate egosgm_tuning with HIP events, keeps the fastest and caches it
+in a JSON file keyed by image size, disparity range and device name.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+import time
+
+import torch
+
+from . import egosgm as eg
+
+CACHE = os.environ.get("EGOSGM_TUNE_CACHE",
+                       os.path.join(os.path.expanduser("~"), ".cache", "egosgm_tuning.json"))
+
+CANDIDATES = [dict(full_group=f, ragged_group=r, prio_long=p)
+              for f, r, p in itertools.product((16, 32, 64), (16, 32, 64), (0, 1))]
+
+
+def _key(w, h, max_disp, tag=""):
+    name = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    return f"{name}|{w}x{h}|D{max_disp}|{tag}"
+
+
+def _load():
+    try:
+        with open(CACHE) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(cache):
+    try:
+        os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+        tmp = CACHE + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1)
+        os.replace(tmp, CACHE)
+    except OSError:
+        pass
+
+
+def time_workload(run, reps=3):
+    """Median milliseconds of run() (which enqueues work on the current stream)."""
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        run()
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def tune(run, w, h, max_disp, tag="", candidates=None, reps=3, use_cache=True, log=None):
+    """Picks the fastest tuning for run(), applies it and returns
+    (tuning dict, {candidate index: ms})."""
+    key = _key(w, h, max_disp, tag)
+    cache = _load() if use_cache else {}
+    if use_cache and key in cache:
+        best = cache[key]["tuning"]
+        eg.set_tuning(**best)
+        return best, cache[key].get("times", {})
+    cands = candidates or CANDIDATES
+    times = {}
+    run()  # warm caches and code objects
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for i, c in enumerate(cands):
+        eg.set_tuning(**c)
+        times[i] = time_workload(run, reps)
+        if log:
+            log(f"tune {c}: {times[i]:.3f} ms")
+    best_i = min(times, key=times.get)
+    best = cands[best_i]
+    eg.set_tuning(**best)
+    if log:
+        log(f"tuned in {time.time() - t0:.1f}s: {best} ({times[best_i]:.3f} ms)")
+    if use_cache:
+        cache[key] = {"tuning": best, "times": {str(k): v for k, v in times.items()}}
+        _store(cache)
+    return best, times

@@ -56,6 +56,10 @@ hipError_t timed(int stage, hipStream_t s, F&& fn) {
     return e;
 }
 
+// Launch-shape choices (set by egosgm_set_tuning; read at every launch).
+egosgm_tuning g_tuning = {32, 32, 1};
+std::mutex g_tuning_mu;
+
 constexpr size_t kAlign = 256;
 constexpr int kMaxWidth = 4064;  // the epilogue keeps 16 bytes per column of a row in LDS
 
@@ -120,6 +124,12 @@ int run_sgm(const uint8_t* left, const uint8_t* right, int w, int h, int pitch, 
     a.p2 = prm->p2;
     a.s_max = prm->s_max;
     a.lr_tol = prm->lr_tol;
+    {
+        std::lock_guard<std::mutex> g(g_tuning_mu);
+        a.full_group = g_tuning.full_group;
+        a.ragged_group = g_tuning.ragged_group;
+        a.prio_long = g_tuning.prio_long;
+    }
     a.cost = base + L.cost;
     a.key_r = reinterpret_cast<uint32_t*>(base + L.key_r);
     a.vol = base + L.vol;
@@ -306,6 +316,28 @@ int warp_disparity(const float* d_prev, const float* p_prev, int w, int h, const
                : EGOSGM_EDEVICE;
 }
 
+size_t egosgm_refine_workspace_bytes(int w, int h) {
+    if (w <= 0 || h <= 0) return 0;
+    return align_up((size_t)w * h * 2 * sizeof(float));
+}
+
+int refine_prediction(const float* d_in, const float* p_in, int w, int h, float edge_tol,
+                      float fill_tol, float* d_out, float* p_out, void* workspace,
+                      size_t workspace_bytes, void* stream) {
+    if (!d_in || !p_in || !d_out || !p_out) return EGOSGM_EINVAL;
+    if (w <= 0 || h <= 0 || (long long)w * h >= (1ll << 31)) return EGOSGM_EINVAL;
+    if (std::isnan(edge_tol) || std::isnan(fill_tol)) return EGOSGM_EINVAL;
+    if (d_out == d_in || p_out == p_in || d_out == p_in || p_out == d_in) return EGOSGM_EINVAL;
+    if (!workspace || workspace_bytes < egosgm_refine_workspace_bytes(w, h)) return EGOSGM_EWORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return timed(EGOSGM_STAGE_REFINE, s, [&] {
+               return launch_refine(d_in, p_in, w, h, edge_tol, fill_tol, d_out, p_out,
+                                    static_cast<float*>(workspace), s);
+           }) == hipSuccess
+               ? EGOSGM_OK
+               : EGOSGM_EDEVICE;
+}
+
 int kalman_update(const float* d_pred, const float* p_pred, const float* d_meas,
                   const float* r_meas, int n, int keep_unmeasured, float* d_out, float* p_out,
                   void* stream) {
@@ -319,6 +351,23 @@ int kalman_update(const float* d_pred, const float* p_pred, const float* d_meas,
            }) == hipSuccess
                ? EGOSGM_OK
                : EGOSGM_EDEVICE;
+}
+
+int egosgm_set_tuning(const egosgm_tuning* t) {
+    if (!t) return EGOSGM_EINVAL;
+    auto ok = [](int g) { return g == 16 || g == 32 || g == 64; };
+    if (!ok(t->full_group) || !ok(t->ragged_group) || (t->prio_long != 0 && t->prio_long != 1))
+        return EGOSGM_EINVAL;
+    std::lock_guard<std::mutex> g(g_tuning_mu);
+    g_tuning = *t;
+    return EGOSGM_OK;
+}
+
+int egosgm_get_tuning(egosgm_tuning* t) {
+    if (!t) return EGOSGM_EINVAL;
+    std::lock_guard<std::mutex> g(g_tuning_mu);
+    *t = g_tuning;
+    return EGOSGM_OK;
 }
 
 int egosgm_timing_enable(int on) {

@@ -27,6 +27,9 @@ struct SgmLaunch {
     int w, h;
     Windows win;
     int p1, p2, s_max, lr_tol;
+    int full_group;          // lanes per scanline, full-range path kernel (16, 32, 64)
+    int ragged_group;        // lanes per scanline, ragged path kernel (16, 32, 64)
+    int prio_long;           // raise the wave priority of the longest scanlines
     uint8_t* cost;           // matching cost per search slot
     uint32_t* key_r;         // w*h right-map keys (S << 9 | d), cleared by the census pass
     uint8_t* vol;            // 8 path volumes, direction-major
@@ -55,6 +58,8 @@ hipError_t launch_windows(const float* d_pred, const float* p_pred, int w, int h
 hipError_t launch_warp(const float* d_prev, const float* p_prev, int w, int h, const float* H,
                        const double* Hd, double q, float* d_pred, float* p_pred,
                        unsigned long long* zbuf, hipStream_t s);
+hipError_t launch_refine(const float* d_in, const float* p_in, int w, int h, float edge_tol,
+                         float fill_tol, float* d_out, float* p_out, float* tmp, hipStream_t s);
 hipError_t launch_kalman(const float* d_pred, const float* p_pred, const float* z,
                          const float* r, int n, int keep, float* d_out, float* p_out,
                          hipStream_t s);

@@ -293,8 +293,12 @@ __device__ inline void load_costs(const uint8_t* __restrict__ cost, uint32_t off
 
 // One lane group of G lanes walks one scanline; lane l owns slots
 // s = l + G*k (k < K) of each pixel's window.  The previous pixel's path
-// costs sit in a per-group LDS row (ping-pong) indexed by disparity minus
-// the previous window's lo, so ragged windows realign by plain indexing.
+// costs sit in a per-group LDS row (ping-pong) indexed by absolute disparity
+// (entry d+1, entries 0 and D+1 are guards).  Every entry outside the
+// predecessor's window holds +infinity: a step erases the row it has just
+// consumed, so the row is clean when it is written again two steps later.
+// The d-1, d, d+1 lookups therefore need no bounds checks, and ragged
+// windows realign by plain indexing.
 // Window metadata is prefetched 2*PF steps ahead and costs PF steps ahead,
 // unconditionally (clamped to the scanline's last pixel) and into ring
 // slots named at compile time, so a step waits only on memory operations
@@ -304,7 +308,8 @@ template <int G, int K, bool FULL, int PF>
 __global__ __launch_bounds__(kBlock) void sgm_paths_kernel(SgmLaunch a, int n_tasks) {
     constexpr int GPB = kBlock / G;
     constexpr int RM = 2 * PF;
-    __shared__ uint16_t lds[GPB][2][G * K];
+    constexpr int ROW = G * K + 2;
+    __shared__ uint16_t lds[GPB][2][ROW];
     const int grp = threadIdx.x / G, lane = threadIdx.x % G;
     const int task = blockIdx.x * GPB + grp;
     if (task >= n_tasks) return;
@@ -312,6 +317,8 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_kernel(SgmLaunch a, int n_ta
     int dir, x, y, len, dx, dy;
     decode_task(task, W, H, dir, x, y, len);
     dir_step(dir, dx, dy);
+    // the longest scanlines set the kernel's length: let them issue first
+    if (a.prio_long && len == (dir < 2 ? W : (dir < 4 ? H : -1))) __builtin_amdgcn_s_setprio(3);
     uint8_t* __restrict__ vol = a.vol + (size_t)dir * a.vol_stride;
     const uint8_t* __restrict__ cost = a.cost;
     uint16_t* b0 = lds[grp][0];
@@ -334,8 +341,13 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_kernel(SgmLaunch a, int n_ta
 #pragma unroll
     for (int j = 0; j < PF; ++j) load_costs<G, K>(cost, moff[j], mw[j], lane, cst[j]);
 
-    // zero predecessor over the first window
-    for (int s = lane; s < G * K; s += G) b1[s] = 0;
+    for (int e = lane; e < ROW; e += G) {
+        b0[e] = kInf;
+        b1[e] = kInf;
+    }
+    lds_order();
+    // zero predecessor over the first window (in b1, read by step 0)
+    for (int e = lane; e < mw[0]; e += G) b1[mlo[0] + 1 + e] = 0;
     lds_order();
     int lo_q = mlo[0], w_q = mw[0], m_q = 0;
     int p = p0;
@@ -344,24 +356,27 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_kernel(SgmLaunch a, int n_ta
         const int lo_c = mlo[ti], w_c = mw[ti];
         const uint32_t off_c = moff[ti];
         uint16_t* cur = parity ? b1 : b0;
-        const uint16_t* prv = parity ? b0 : b1;
+        uint16_t* prv = parity ? b0 : b1;
+        const int m2 = m_q + p2;
         int mn = kInf;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int s = lane + G * k;
             if (s < w_c) {
-                const int j = lo_c + s - lo_q;
-                const int v0 = (unsigned)j < (unsigned)w_q ? (int)prv[j] : kInf;
-                const int vm = (unsigned)(j - 1) < (unsigned)w_q ? (int)prv[j - 1] : kInf;
-                const int vp = (unsigned)(j + 1) < (unsigned)w_q ? (int)prv[j + 1] : kInf;
-                const int best = min(min(v0, min(vm, vp) + p1), m_q + p2);
+                const uint16_t* q = prv + lo_c + s;   // q[0] = d-1, q[1] = d, q[2] = d+1
+                const int best = min(min((int)q[1], min((int)q[0], (int)q[2]) + p1), m2);
                 const int L = cst[tc][k] + best - m_q;
-                cur[s] = (uint16_t)L;
+                cur[lo_c + s + 1] = (uint16_t)L;
                 vol[off_c + (uint32_t)s] = (uint8_t)L;
                 mn = min(mn, L);
             }
         }
         lds_order();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int s = lane + G * k;
+            if (s < w_q) prv[lo_q + s + 1] = kInf;
+        }
         m_q = group_min<G>(mn);
         lo_q = lo_c;
         w_q = w_c;
@@ -480,6 +495,8 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_full_kernel(SgmLaunch a, int
     int dir, x, y, len, dx, dy;
     decode_task(task, W, H, dir, x, y, len);
     dir_step(dir, dx, dy);
+    // the longest scanlines set the kernel's length: let them issue first
+    if (a.prio_long && len == (dir < 2 ? W : (dir < 4 ? H : -1))) __builtin_amdgcn_s_setprio(3);
     const Word* __restrict__ cost = reinterpret_cast<const Word*>(a.cost);
     Word* __restrict__ vol = reinterpret_cast<Word*>(a.vol + (size_t)dir * a.vol_stride);
     const int dp = dy * W + dx;
@@ -730,6 +747,60 @@ __global__ __launch_bounds__(kBlock) void warp_decode_kernel(const unsigned long
     p_pred[i] = (float)(phi * phi * p + q);
 }
 
+// ------------------------------------------------------------------ refinement
+// Edge rejection: a valid prediction is dropped when a valid pixel of its
+// 3x3 neighbourhood differs from it by more than edge_tol (edge_tol < 0:
+// plain copy).
+__global__ __launch_bounds__(kBlock) void refine_edge_kernel(const float* __restrict__ d_in,
+                                                             const float* __restrict__ p_in,
+                                                             int w, int h, float edge_tol,
+                                                             float* __restrict__ d_out,
+                                                             float* __restrict__ p_out) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= w * h) return;
+    const int x = i % w, y = i / w;
+    const float d = d_in[i];
+    bool keep = d >= 0.0f;
+    if (keep && edge_tol >= 0.0f) {
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int xx = x + dx, yy = y + dy;
+                if (xx < 0 || xx >= w || yy < 0 || yy >= h) continue;
+                const float e = d_in[yy * w + xx];
+                if (e >= 0.0f && fabsf(d - e) > edge_tol) keep = false;
+            }
+    }
+    d_out[i] = keep ? d : -1.0f;
+    p_out[i] = keep ? p_in[i] : 0.0f;
+}
+
+// One-pixel "zoom" hole filling along rows (step 1) or columns (step w): an
+// invalid pixel between two valid neighbours with |a - b| < fill_tol takes
+// their means.  (a + b) * 0.5f is the correctly rounded mean: the sum is
+// rounded once and halving is exact.
+__global__ __launch_bounds__(kBlock) void refine_fill_kernel(const float* __restrict__ d_in,
+                                                             const float* __restrict__ p_in,
+                                                             int w, int h, float fill_tol,
+                                                             int vertical,
+                                                             float* __restrict__ d_out,
+                                                             float* __restrict__ p_out) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= w * h) return;
+    const int x = i % w, y = i / w;
+    float d = d_in[i], p = p_in[i];
+    const bool inside = vertical ? (y >= 1 && y + 1 < h) : (x >= 1 && x + 1 < w);
+    if (d < 0.0f && inside) {
+        const int st = vertical ? w : 1;
+        const float a = d_in[i - st], b = d_in[i + st];
+        if (a >= 0.0f && b >= 0.0f && fabsf(a - b) < fill_tol) {
+            d = (a + b) * 0.5f;
+            p = (p_in[i - st] + p_in[i + st]) * 0.5f;
+        }
+    }
+    d_out[i] = d;
+    p_out[i] = p;
+}
+
 // ------------------------------------------------------------------ Kalman
 __global__ __launch_bounds__(kBlock) void kalman_kernel(const float* d_pred, const float* p_pred,
                                                         const float* z, const float* r, int n,
@@ -794,17 +865,35 @@ hipError_t launch_sgm_paths(const SgmLaunch& a, hipStream_t s) {
     sgm_paths_kernel<GG, KK, FF, 4><<<grid(GG), kBlock, 0, s>>>(a, n_tasks)
 #define EGOSGM_FULL(GG, NN) sgm_paths_full_kernel<GG, NN, 8><<<grid(GG), kBlock, 0, s>>>(a, n_tasks)
     if (full) {
-        if (D == 64) EGOSGM_FULL(16, 2);
-        else if (D == 128) EGOSGM_FULL(32, 2);
-        else if (D == 256) EGOSGM_FULL(32, 4);
-        else if (D <= 64) EGOSGM_PATHS(64, 1, true);
-        else if (D <= 128) EGOSGM_PATHS(64, 2, true);
-        else EGOSGM_PATHS(64, 4, true);
+        // packed kernel: D = 2 * NP * G
+        const int g = a.full_group;
+        if (D == 64) {
+            if (g == 32) EGOSGM_FULL(32, 1); else EGOSGM_FULL(16, 2);
+        } else if (D == 128) {
+            if (g == 16) EGOSGM_FULL(16, 4); else if (g == 64) EGOSGM_FULL(64, 1); else EGOSGM_FULL(32, 2);
+        } else if (D == 256) {
+            if (g == 16) EGOSGM_FULL(16, 8); else if (g == 64) EGOSGM_FULL(64, 2); else EGOSGM_FULL(32, 4);
+        } else if (D <= 64) {
+            EGOSGM_PATHS(64, 1, true);
+        } else if (D <= 128) {
+            EGOSGM_PATHS(64, 2, true);
+        } else {
+            EGOSGM_PATHS(64, 4, true);
+        }
     } else {
+        const int g = a.ragged_group;
         if (D <= 16) EGOSGM_PATHS(16, 1, false);
-        else if (D <= 64) EGOSGM_PATHS(32, 2, false);
-        else if (D <= 128) EGOSGM_PATHS(32, 4, false);
-        else EGOSGM_PATHS(32, 8, false);
+        else if (D <= 32) { if (g == 32) EGOSGM_PATHS(32, 1, false); else EGOSGM_PATHS(16, 2, false); }
+        else if (D <= 64) { if (g == 16) EGOSGM_PATHS(16, 4, false); else EGOSGM_PATHS(32, 2, false); }
+        else if (D <= 128) {
+            if (g == 16) EGOSGM_PATHS(16, 8, false);
+            else if (g == 64) EGOSGM_PATHS(64, 2, false);
+            else EGOSGM_PATHS(32, 4, false);
+        } else {
+            if (g == 16) EGOSGM_PATHS(16, 16, false);
+            else if (g == 64) EGOSGM_PATHS(64, 4, false);
+            else EGOSGM_PATHS(32, 8, false);
+        }
     }
 #undef EGOSGM_PATHS
 #undef EGOSGM_FULL
@@ -870,6 +959,19 @@ hipError_t launch_warp(const float* d_prev, const float* p_prev, int w, int h, c
     if (e != hipSuccess) return e;
     warp_decode_kernel<<<grid_for(n), kBlock, 0, s>>>(zbuf, d_prev, p_prev, w, (int)n, md, q,
                                                       d_pred, p_pred);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine(const float* d_in, const float* p_in, int w, int h, float edge_tol,
+                         float fill_tol, float* d_out, float* p_out, float* tmp, hipStream_t s) {
+    const size_t n = (size_t)w * h;
+    refine_edge_kernel<<<grid_for(n), kBlock, 0, s>>>(d_in, p_in, w, h, edge_tol, d_out, p_out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !(fill_tol > 0.0f)) return e;
+    refine_fill_kernel<<<grid_for(n), kBlock, 0, s>>>(d_out, p_out, w, h, fill_tol, 0, tmp, tmp + n);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    refine_fill_kernel<<<grid_for(n), kBlock, 0, s>>>(tmp, tmp + n, w, h, fill_tol, 1, d_out, p_out);
     return hipGetLastError();
 }
 

@@ -35,11 +35,15 @@ _SIGS = {
     "egosgm_warp_matrix": ([_vp, _vp, _d, _d, _d, _d, _vp], _i),
     "warp_disparity": ([_vp, _vp, _i, _i, _vp, _vp, _d, _d, _d, _d, _f, _vp, _vp, _vp, _vp], _i),
     "kalman_update": ([_vp, _vp, _vp, _vp, _i, _i, _vp, _vp, _vp], _i),
+    "egosgm_refine_workspace_bytes": ([_i, _i], _sz),
+    "refine_prediction": ([_vp, _vp, _i, _i, _f, _f, _vp, _vp, _vp, _sz, _vp], _i),
+    "egosgm_set_tuning": ([_vp], _i),
+    "egosgm_get_tuning": ([_vp], _i),
     "egosgm_timing_enable": ([_i], _i),
     "egosgm_timing_read": ([_vp, _vp, _i], _i),
 }
 
-STAGES = ("census", "windows", "cost", "paths", "select", "warp", "kalman")
+STAGES = ("census", "windows", "cost", "paths", "select", "warp", "kalman", "refine")
 
 
 def lib():
@@ -76,6 +80,22 @@ class SgmParams(C.Structure):
 class SgmDebug(C.Structure):
     _fields_ = [("census_left", _vp), ("census_right", _vp), ("cost", _vp), ("paths", _vp),
                 ("agg", _vp), ("wta_raw", _vp)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("full_group", C.c_int32), ("ragged_group", C.c_int32),
+                ("prio_long", C.c_int32)]
+
+
+def set_tuning(full_group: int = 32, ragged_group: int = 32, prio_long: int = 1):
+    t = Tuning(full_group, ragged_group, prio_long)
+    _check(lib().egosgm_set_tuning(C.byref(t)), "egosgm_set_tuning")
+
+
+def get_tuning() -> dict:
+    t = Tuning()
+    _check(lib().egosgm_get_tuning(C.byref(t)), "egosgm_get_tuning")
+    return dict(full_group=t.full_group, ragged_group=t.ragged_group, prio_long=t.prio_long)
 
 
 @dataclass
@@ -140,6 +160,12 @@ class Workspace:
         if self.sgm is None or self.sgm.numel() < n:
             self.sgm = torch.empty(n, dtype=torch.uint8, device=self.device)
         return self.sgm, n
+
+    def refine_bytes(self, w, h):
+        n = lib().egosgm_refine_workspace_bytes(w, h)
+        if getattr(self, "ref", None) is None or self.ref.numel() < n:
+            self.ref = torch.empty(n, dtype=torch.uint8, device=self.device)
+        return self.ref, n
 
     def windows_bytes(self, w, h):
         n = lib().egosgm_windows_workspace_bytes(w, h)
@@ -287,6 +313,21 @@ def warp_disparity(d_prev: torch.Tensor, p_prev: torch.Tensor, R, t, f, cx, cy, 
                               t.ctypes.data_as(_vp), f, cx, cy, baseline, q, _ptr(out[0]),
                               _ptr(out[1]), _ptr(zbuf), _stream())
     _check(rc, "warp_disparity")
+    return out
+
+
+def refine_prediction(d_in, p_in, edge_tol=2.0, fill_tol=1.0, out=None,
+                      workspace: Workspace | None = None):
+    """Edge rejection + one-pixel hole filling of a predicted map."""
+    _need(d_in, torch.float32, name="d_in")
+    h, w = d_in.shape
+    _need(p_in, torch.float32, h * w, "p_in")
+    if out is None:
+        out = (torch.empty_like(d_in), torch.empty_like(d_in))
+    ws, nbytes = (workspace or _ws(d_in.device)).refine_bytes(w, h)
+    rc = lib().refine_prediction(_ptr(d_in), _ptr(p_in), w, h, edge_tol, fill_tol, _ptr(out[0]),
+                                 _ptr(out[1]), _ptr(ws), nbytes, _stream())
+    _check(rc, "refine_prediction")
     return out
 
 

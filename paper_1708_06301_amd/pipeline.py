@@ -4,9 +4,10 @@ stereo matching in the reduced space, disparity update).
 A StreamState keeps the stream's disparity and variance maps resident on the
 GPU between frames together with every buffer a frame needs, so a frame
 enqueues only kernels.  Frame 0, and every frame after reset(), matches over
-the full range; later frames warp the previous map by the ego-motion, derive
-per-pixel windows from the predicted variance (or a fixed radius) and match
-only inside them (Sec. 2.3; Sec. 3: the first frame searches everything).
+the full range; later frames warp the previous map by the ego-motion, refine
+the prediction (edge rejection and hole filling, Sec. 2.2.2), derive per-pixel
+windows from the predicted variance (or a fixed radius) and match only inside
+them (Sec. 2.3; Sec. 3: the first frame searches everything).
 """
 from __future__ import annotations
 
@@ -39,6 +40,8 @@ class FrameConfig:
     r_min: int = 0
     r_max: int = 256
     keep_unmeasured: int = 0
+    edge_tol: float = 2.0     # prediction edge rejection (Sec. 2.2.2); < 0 disables
+    fill_tol: float = 1.0     # one-pixel hole filling, Eq. 7-8; <= 0 disables
     full_range_only: bool = False   # plain SGM every frame (the baseline)
 
     def match(self) -> eg.MatchParams:
@@ -54,6 +57,8 @@ class StreamState:
         f32 = dict(dtype=torch.float32, device=dev)
         self.d = torch.full((h, w), -1.0, **f32)     # D^{k}
         self.p = torch.zeros((h, w), **f32)          # P^{k}
+        self.d_warp = torch.empty((h, w), **f32)
+        self.p_warp = torch.empty((h, w), **f32)
         self.d_pred = torch.empty((h, w), **f32)
         self.p_pred = torch.empty((h, w), **f32)
         self.zbuf = torch.empty(n, dtype=torch.int64, device=dev)
@@ -67,6 +72,7 @@ class StreamState:
         self.ws = eg.Workspace(dev)
         self.ws.sgm_bytes(w, h, cfg.max_disp)
         self.ws.windows_bytes(w, h)
+        self.ws.refine_bytes(w, h)
         self.invalid = torch.full((h, w), -1.0, **f32)
         self.zeros = torch.zeros((h, w), **f32)
         self.frame = 0
@@ -86,7 +92,9 @@ class StreamState:
                              cfg.keep_unmeasured, out=(self.d, self.p))
         else:
             eg.warp_disparity(self.d, self.p, R, t, c.f, c.cx, c.cy, c.baseline, cfg.q,
-                              out=(self.d_pred, self.p_pred), zbuf=self.zbuf)
+                              out=(self.d_warp, self.p_warp), zbuf=self.zbuf)
+            eg.refine_prediction(self.d_warp, self.p_warp, cfg.edge_tol, cfg.fill_tol,
+                                 out=(self.d_pred, self.p_pred), workspace=self.ws)
             eg.windows_from_prediction(self.d_pred, self.p_pred, cfg.max_disp, cfg.r_fixed,
                                        cfg.r_min, cfg.r_max, cfg.k_sigma,
                                        out=(self.lo, self.hi, self.off), workspace=self.ws)

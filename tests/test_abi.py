@@ -106,3 +106,16 @@ def test_warp_matrix_host_helper_matches_oracle(orc):
         assert np.array_equal(H, Ho.astype(np.float32))
     assert np.array_equal(eg.warp_matrix(np.eye(3), np.zeros(3), 718, 620.5, 187, 0.54),
                           np.eye(4, dtype=np.float32))
+
+
+def test_tuning_validation():
+    import ctypes as C
+    lib = eg.lib()
+    before = eg.get_tuning()
+    bad = eg.Tuning(24, 32, 1)
+    assert lib.egosgm_set_tuning(C.byref(bad)) == -1
+    assert lib.egosgm_set_tuning(None) == -1
+    assert eg.get_tuning() == before
+    eg.set_tuning(16, 64, 0)
+    assert eg.get_tuning() == dict(full_group=16, ragged_group=64, prio_long=0)
+    eg.set_tuning(**before)

@@ -207,6 +207,21 @@ def test_warp_identity_and_collisions():
     assert _close(gd, o["d_pred"]) and _close(gp, o["p_pred"])
 
 
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_refine(seed):
+    r = np.random.default_rng(50 + seed)
+    h, w = (375, 1242) if seed == 0 else (int(r.integers(5, 90)), int(r.integers(5, 200)))
+    _say("refine", w, h, seed)
+    base = np.cumsum(r.normal(0, 0.4, size=(h, w)), axis=1).astype(np.float32) + 40
+    d = np.where(r.random((h, w)) < 0.3, -1.0, base).astype(np.float32)
+    d[r.random((h, w)) < 0.02] += 10.0
+    p = r.uniform(0.1, 4, size=(h, w)).astype(np.float32)
+    for edge_tol, fill_tol in ((-1.0, 1.0), (2.0, 1.0), (0.5, 0.0), (3.0, 2.5), (0.0, 0.25)):
+        gd, gp = eg.refine_prediction(_gpu(d), _gpu(p), edge_tol, fill_tol)
+        od, op = orc.refine(d, p, edge_tol, fill_tol)
+        assert np.array_equal(_np(gd), od) and np.array_equal(_np(gp), op), (edge_tol, fill_tol)
+
+
 def test_kalman():
     _say("kalman")
     r = np.random.default_rng(4)
@@ -224,3 +239,30 @@ def test_kalman():
         gd, gp = _np(gd), _np(gp)
         assert np.array_equal(gd < 0, od < 0)
         assert np.abs(gd - od).max() <= TOL and np.abs(gp - op).max() <= TOL
+
+
+@pytest.mark.parametrize("D", [64, 128, 256])
+def test_tuning_never_changes_results(D):
+    _say("tuning invariance", D)
+    import itertools
+    w, h = 97, 29
+    left, right = _random_pair(w, h, seed=D, max_shift=min(D - 1, 40))
+    d, p = _random_windows(w, h, D, seed=D + 1, frac_full=0.15)
+    wo = orc.windows(d, p, D, r_min=0, r_max=12)
+    o_full = orc.sgm(left, right, D)
+    o_red = orc.sgm(left, right, D, windows=wo)
+    L, R = _gpu(left), _gpu(right)
+    lo, hi, off = (_gpu(wo[0].reshape(h, w)), _gpu(wo[1].reshape(h, w)),
+                   _gpu(wo[2].view(np.int32)))
+    prm = eg.MatchParams(max_disp=D)
+    try:
+        for fg, rg, pr in itertools.product((16, 32, 64), (16, 32, 64), (0, 1)):
+            eg.set_tuning(fg, rg, pr)
+            a = eg.sgm_full(L, R, prm)
+            b = eg.sgm_reduced(L, R, lo, hi, off, prm)
+            assert np.array_equal(_np(a["disp_wta"]), o_full["disp_wta"]), (fg, rg, pr)
+            assert np.array_equal(_np(a["var_meas"]).astype(np.float64), o_full["var_meas"])
+            assert np.array_equal(_np(b["disp_wta"]), o_red["disp_wta"]), (fg, rg, pr)
+            assert np.array_equal(_np(b["disp_right"]), o_red["disp_right"]), (fg, rg, pr)
+    finally:
+        eg.set_tuning(32, 32, 1)

@@ -445,3 +445,45 @@ def test_kalman_validity_table(orc):
     assert d.tolist() == [-1, 7, -1, -1, 6] and p.tolist() == [0, 3, 0, 0, 2]
     d, p = orc.kalman(dp, pp, z, r, keep_unmeasured=1)
     assert d.tolist() == [5, 7, 5, -1, 6] and p.tolist() == [1, 3, 1, 0, 2]
+
+
+# ---------------------------------------------------------------- refinement
+def test_refine_golden(orc):
+    g = load("refine_hand.txt")
+    d, p = orc.refine(np.array(g["d_in"], np.float32), np.array(g["p_in"], np.float32),
+                      edge_tol=-1.0, fill_tol=1.0)
+    assert np.array_equal(d, np.array(g["d_out"], np.float32))
+    assert np.array_equal(p, np.array(g["p_out"], np.float32))
+    v = np.array(g["v_in"], np.float32)
+    d, p = orc.refine(v, np.ones_like(v), fill_tol=1.0)
+    assert np.array_equal(d, np.array(g["v_out"], np.float32))
+    assert np.array_equal(p[v < 0] > 0, np.array(g["v_out"])[v < 0] > 0)
+    e = np.array(g["e_in"], np.float32)
+    d, _ = orc.refine(e, np.ones_like(e), edge_tol=2.0, fill_tol=0.0)
+    assert np.array_equal(d, np.array(g["e_out"], np.float32))
+
+
+def test_refine_properties(orc):
+    r = np.random.default_rng(13)
+    d = r.uniform(0, 60, size=(30, 50)).astype(np.float32)
+    p = r.uniform(0.1, 3, size=(30, 50)).astype(np.float32)
+    # no holes, no edge test: identity
+    od, op = orc.refine(d, p, edge_tol=-1.0, fill_tol=1.0)
+    assert np.array_equal(od, d) and np.array_equal(op, p)
+    # a smooth ramp with every other column missing is filled exactly
+    ramp = np.tile(np.arange(50, dtype=np.float32) * 0.25, (30, 1))
+    holes = ramp.copy()
+    holes[:, 1::2] = -1
+    od, _ = orc.refine(holes, np.ones_like(holes), fill_tol=1.0)
+    assert np.array_equal(od[:, :-1], ramp[:, :-1])   # the last column has no right neighbour
+    # dissimilar neighbours never fill: gaps between 10 and 20 stay
+    d2 = np.tile(np.array([10, -1, 20, -1, 10], np.float32), (5, 1))
+    od, _ = orc.refine(d2, np.ones_like(d2), fill_tol=1.0)
+    assert (od[:, [1, 3]] == -1).all()
+    # edge rejection only removes pixels, and only near jumps larger than the tolerance
+    step = np.ones((8, 8), np.float32) * 5
+    step[:, 4:] = 9
+    od, _ = orc.refine(step, np.ones_like(step), edge_tol=3.0, fill_tol=0.0)
+    assert (od[:, [3, 4]] == -1).all() and (od[:, [0, 1, 2, 5, 6, 7]] >= 0).all()
+    od, _ = orc.refine(step, np.ones_like(step), edge_tol=4.0, fill_tol=0.0)
+    assert np.array_equal(od, step)
