@@ -227,13 +227,16 @@ int kalman_update(const float* d_pred, const float* p_pred, const float* d_meas,
                   void* stream);
 
 /* ------------------------------------------------------------------ tuning
- * Launch shapes of the path kernels, process-wide (the second piece of state
- * the library keeps; set it before enqueueing work, e.g. from an autotuner).
- * Results never depend on it.  Defaults: {32, 32, 1}. */
+ * Launch shapes and schedules of the path kernels, process-wide (the second
+ * piece of state the library keeps; set it before enqueueing work, e.g. from
+ * an autotuner).  Results never depend on it.  Defaults: {64, 64, 0}. */
 typedef struct egosgm_tuning {
-    int32_t full_group;   /* lanes per scanline of the full-range path kernel: 16, 32, 64 */
-    int32_t ragged_group; /* lanes per scanline of the ragged path kernel: 16, 32, 64      */
-    int32_t prio_long;    /* 1: the longest scanlines run at raised wave priority, 0: not */
+    int32_t full_group;      /* lanes per scanline, full-range kernel: 16, 32, 64             */
+    int32_t ragged_group;    /* lanes per scanline, ragged windows through LDS: 16, 32, 64    */
+    int32_t ragged_schedule; /* 0: every scanline through LDS (work follows the windows);
+                                1: the image rows (the longest scanlines) on packed registers
+                                   over all disparities, the rest through LDS;
+                                2: every scanline on packed registers                        */
 } egosgm_tuning;
 
 int egosgm_set_tuning(const egosgm_tuning* tuning);

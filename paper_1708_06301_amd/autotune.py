@@ -1,8 +1,8 @@
 """Autotuner for the path kernels' launch shapes.
 
 Results never depend on the launch shape (lanes per scanline of the
-full-range and ragged kernels, raised wave priority for the longest
-scanlines); only speed does.  tune() times a caller-supplied workload under
+full-range and ragged kernels, and which scanlines of a ragged frame run on
+packed registers); only speed does.  tune() times a caller-supplied workload under
 each candidate egosgm_tuning with HIP events, keeps the fastest and caches it
 in a JSON file keyed by image size, disparity range and device name.
 """
@@ -20,8 +20,8 @@ from . import egosgm as eg
 CACHE = os.environ.get("EGOSGM_TUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "egosgm_tuning.json"))
 
-CANDIDATES = [dict(full_group=f, ragged_group=r, prio_long=p)
-              for f, r, p in itertools.product((16, 32, 64), (16, 32, 64), (0, 1))]
+CANDIDATES = [dict(full_group=f, ragged_group=r, ragged_schedule=s)
+              for f, r, s in itertools.product((16, 32, 64), (16, 32, 64), (0, 1, 2))]
 
 
 def _key(w, h, max_disp, tag=""):

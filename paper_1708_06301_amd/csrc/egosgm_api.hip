@@ -57,7 +57,7 @@ hipError_t timed(int stage, hipStream_t s, F&& fn) {
 }
 
 // Launch-shape choices (set by egosgm_set_tuning; read at every launch).
-egosgm_tuning g_tuning = {32, 32, 1};
+egosgm_tuning g_tuning = {64, 64, 0};
 std::mutex g_tuning_mu;
 
 constexpr size_t kAlign = 256;
@@ -128,7 +128,7 @@ int run_sgm(const uint8_t* left, const uint8_t* right, int w, int h, int pitch, 
         std::lock_guard<std::mutex> g(g_tuning_mu);
         a.full_group = g_tuning.full_group;
         a.ragged_group = g_tuning.ragged_group;
-        a.prio_long = g_tuning.prio_long;
+        a.ragged_schedule = g_tuning.ragged_schedule;
     }
     a.cost = base + L.cost;
     a.key_r = reinterpret_cast<uint32_t*>(base + L.key_r);
@@ -356,7 +356,7 @@ int kalman_update(const float* d_pred, const float* p_pred, const float* d_meas,
 int egosgm_set_tuning(const egosgm_tuning* t) {
     if (!t) return EGOSGM_EINVAL;
     auto ok = [](int g) { return g == 16 || g == 32 || g == 64; };
-    if (!ok(t->full_group) || !ok(t->ragged_group) || (t->prio_long != 0 && t->prio_long != 1))
+    if (!ok(t->full_group) || !ok(t->ragged_group) || t->ragged_schedule < 0 || t->ragged_schedule > 2)
         return EGOSGM_EINVAL;
     std::lock_guard<std::mutex> g(g_tuning_mu);
     g_tuning = *t;

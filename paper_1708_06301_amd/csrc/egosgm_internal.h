@@ -29,7 +29,7 @@ struct SgmLaunch {
     int p1, p2, s_max, lr_tol;
     int full_group;          // lanes per scanline, full-range path kernel (16, 32, 64)
     int ragged_group;        // lanes per scanline, ragged path kernel (16, 32, 64)
-    int prio_long;           // raise the wave priority of the longest scanlines
+    int ragged_schedule;     // 0: all scanlines via LDS, 1: rows on packed registers, 2: all packed
     uint8_t* cost;           // matching cost per search slot
     uint32_t* key_r;         // w*h right-map keys (S << 9 | d), cleared by the census pass
     uint8_t* vol;            // 8 path volumes, direction-major

@@ -167,25 +167,31 @@ __device__ inline void window_of(const Windows& win, int p, int& lo, int& hi, ui
 }
 
 // Minimum over each 16-lane row, left in every lane of the row (DPP:
-// quad_perm xor 1, xor 2, then row_ror 4 and 8).
+// quad_perm xor 1, xor 2, then row_ror 4 and 8; each stage folds into one
+// v_min_i32_dpp).
 __device__ inline int row_min16(int v) {
-    v = min(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));
-    v = min(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));
-    v = min(v, __builtin_amdgcn_mov_dpp(v, 0x124, 0xF, 0xF, false));
-    v = min(v, __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0xB1, 0xF, 0xF, true));
+    v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x4E, 0xF, 0xF, true));
+    v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x124, 0xF, 0xF, true));
+    v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x128, 0xF, 0xF, true));
     return v;
 }
 
 // Minimum over a lane group of G (16, 32 or 64) lanes; every lane of the
-// group must be active.  Rows are combined through scalar registers.
+// group must be active.  Rows are chained with row_bcast 15 (rows 1 and 3
+// take row 0's and row 2's minimum) and row_bcast 31 (rows 2 and 3 take row
+// 1's), then the group's last lane is read into a scalar register.
 template <int G>
 __device__ inline int group_min(int v) {
     v = row_min16(v);
     if (G == 16) return v;
-    const int r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
-    const int r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
-    if (G == 64) return min(min(r0, r1), min(r2, r3));
-    return (threadIdx.x & 32) ? min(r2, r3) : min(r0, r1);
+    v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x142, 0xA, 0xF, false));
+    if (G == 32) {
+        const int a = __builtin_amdgcn_readlane(v, 31), b = __builtin_amdgcn_readlane(v, 63);
+        return (threadIdx.x & 32) ? b : a;
+    }
+    v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x143, 0xC, 0xF, false));
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 // Orders this lane group's LDS writes before its later LDS reads.  A wave's
@@ -291,6 +297,19 @@ __device__ inline void load_costs(const uint8_t* __restrict__ cost, uint32_t off
     }
 }
 
+// A scanline task: direction, first pixel, pixel step and length.
+struct Scan {
+    int dir, p0, dp, len;
+};
+
+__device__ inline Scan scan_of(int task, int W, int H) {
+    int dir, x, y, len, dx, dy;
+    decode_task(task, W, H, dir, x, y, len);
+    dir_step(dir, dx, dy);
+    return Scan{dir, y * W + x, dy * W + dx, len};
+}
+
+// ---- LDS scanline (ragged windows, work proportional to the window) ----
 // One lane group of G lanes walks one scanline; lane l owns slots
 // s = l + G*k (k < K) of each pixel's window.  The previous pixel's path
 // costs sit in a per-group LDS row (ping-pong) indexed by absolute disparity
@@ -305,27 +324,14 @@ __device__ inline void load_costs(const uint8_t* __restrict__ cost, uint32_t off
 // issued PF steps earlier.  A zero predecessor row over the first window
 // makes the first step L = C.
 template <int G, int K, bool FULL, int PF>
-__global__ __launch_bounds__(kBlock) void sgm_paths_kernel(SgmLaunch a, int n_tasks) {
-    constexpr int GPB = kBlock / G;
+__device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane,
+                                    uint16_t* b0, uint16_t* b1) {
     constexpr int RM = 2 * PF;
     constexpr int ROW = G * K + 2;
-    __shared__ uint16_t lds[GPB][2][ROW];
-    const int grp = threadIdx.x / G, lane = threadIdx.x % G;
-    const int task = blockIdx.x * GPB + grp;
-    if (task >= n_tasks) return;
-    const int W = a.w, H = a.h;
-    int dir, x, y, len, dx, dy;
-    decode_task(task, W, H, dir, x, y, len);
-    dir_step(dir, dx, dy);
-    // the longest scanlines set the kernel's length: let them issue first
-    if (a.prio_long && len == (dir < 2 ? W : (dir < 4 ? H : -1))) __builtin_amdgcn_s_setprio(3);
-    uint8_t* __restrict__ vol = a.vol + (size_t)dir * a.vol_stride;
+    uint8_t* __restrict__ vol = a.vol + (size_t)sc.dir * a.vol_stride;
     const uint8_t* __restrict__ cost = a.cost;
-    uint16_t* b0 = lds[grp][0];
-    uint16_t* b1 = lds[grp][1];
     const int p1 = a.p1, p2 = a.p2;
-    const int dp = dy * W + dx;
-    const int p0 = y * W + x;
+    const int dp = sc.dp, len = sc.len, p0 = sc.p0;
     const int p_last = p0 + (len - 1) * dp;
 
     int mlo[RM], mw[RM];
@@ -346,8 +352,7 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_kernel(SgmLaunch a, int n_ta
         b1[e] = kInf;
     }
     lds_order();
-    // zero predecessor over the first window (in b1, read by step 0)
-    for (int e = lane; e < mw[0]; e += G) b1[mlo[0] + 1 + e] = 0;
+    for (int e = lane; e < mw[0]; e += G) b1[mlo[0] + 1 + e] = 0;   // zero predecessor
     lds_order();
     int lo_q = mlo[0], w_q = mw[0], m_q = 0;
     int p = p0;
@@ -403,14 +408,12 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_kernel(SgmLaunch a, int n_ta
     }
 }
 
-// ------------------------------------------------------------------ SGM paths, full range
-// Full-range variant: every window is [0, D-1], so no realignment is needed
-// and the previous pixel's path costs stay in registers.  A lane group of G
-// lanes owns D = 2*NP*G disparities, lane l holding the contiguous slots
-// 2*NP*l .. 2*NP*l + 2*NP - 1 as NP registers of two 16-bit values each
-// (packed u16 arithmetic).  The d-1 / d+1 neighbours come from v_alignbit on
-// a lane's own registers plus one DPP lane shift for the slot owned by the
-// neighbouring lane; the group minimum m uses the DPP row reduction.
+// ---- packed register scanline ----
+// A lane group of G lanes holds all D = 2*NP*G disparities, lane l owning
+// the contiguous slots 2*NP*l .. 2*NP*l + 2*NP - 1 as NP registers of two
+// 16-bit values (packed u16 arithmetic).  The d-1 / d+1 neighbours come from
+// v_alignbit on a lane's own registers plus one DPP lane shift for the slot
+// owned by the neighbouring lane; the group minimum m uses DPP reductions.
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 __device__ inline u16x2 as_pk(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
 __device__ inline uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
@@ -438,7 +441,7 @@ __device__ inline uint32_t from_next_lane(uint32_t v) {
     return (G == 32 && (threadIdx.x & 31) == 31) ? kInfPk : r;
 }
 
-// 2*NP cost bytes of one lane, loaded in one access.
+// 2*NP cost bytes of one lane, loaded in one access (full range).
 template <int NP> struct CostWord;
 template <> struct CostWord<1> { using T = uint16_t; };
 template <> struct CostWord<2> { using T = uint32_t; };
@@ -479,77 +482,76 @@ __device__ inline typename CostWord<NP>::T pack_costs(const uint32_t (&L)[NP]) {
     }
 }
 
-// Prefetch: the cost words of step i + PF are loaded while step i runs,
-// unconditionally (past the end of the scanline the last pixel is loaded
-// again) and into ring slots named at compile time, so no loaded register
-// is ever copied before use: a step waits only on loads and stores issued PF
-// steps earlier.  The zero initial state makes the first step L = C.
+// One recurrence step on the packed registers: L <- C + min(L(d), L(d+-1) +
+// P1, m + P2) - m, and the new group minimum.  Entries whose cost is the
+// out-of-window marker 0x3fff stay >= 0x3fff - 255, far above any in-window
+// m + P2 (<= 255 + 193), so they never win a minimum: they act as +infinity
+// for the next step, and stay below 0x3fff + 193, so nothing overflows.
+template <int G, int NP>
+__device__ inline void packed_update(uint32_t (&L)[NP], const uint32_t (&c)[NP], int& m,
+                                     uint32_t p1pk, int p2) {
+    const uint32_t mpk = (uint32_t)m * 0x10001u;
+    const uint32_t m2pk = (uint32_t)(m + p2) * 0x10001u;
+    const uint32_t prv = from_prev_lane<G>(L[NP - 1]);
+    const uint32_t nxt = from_next_lane<G>(L[0]);
+    uint32_t Ln[NP];
+#pragma unroll
+    for (int r = 0; r < NP; ++r) {
+        const uint32_t lm1 = align16(L[r], r > 0 ? L[r - 1] : prv);
+        const uint32_t lp1 = align16(r + 1 < NP ? L[r + 1] : nxt, L[r]);
+        uint32_t t = pk_add(pk_min(lm1, lp1), p1pk);
+        t = pk_min(pk_min(t, L[r]), m2pk);
+        Ln[r] = pk_sub(pk_add(c[r], t), mpk);
+    }
+    uint32_t mv = Ln[0];
+#pragma unroll
+    for (int r = 0; r < NP; ++r) {
+        L[r] = Ln[r];
+        mv = pk_min(mv, Ln[r]);
+    }
+    m = group_min<G>((int)min(mv & 0xffffu, mv >> 16));
+}
+
+// Full range: costs and path costs are dense (pixel p, slot d at p*D + d),
+// one word of 2*NP bytes per lane.  Prefetch: the cost words of step i + PF
+// are loaded while step i runs, unconditionally (past the end of the
+// scanline the last pixel is loaded again) and into ring slots named at
+// compile time, so no loaded register is copied before use and a step waits
+// only on loads and stores issued PF steps earlier.  The zero initial state
+// makes the first step L = C.
 template <int G, int NP, int PF>
-__global__ __launch_bounds__(kBlock) void sgm_paths_full_kernel(SgmLaunch a, int n_tasks) {
+__device__ inline void packed_scanline_full(const SgmLaunch& a, const Scan& sc, int lane) {
     using Word = typename CostWord<NP>::T;
-    constexpr int GPB = kBlock / G;
-    const int grp = threadIdx.x / G, lane = threadIdx.x % G;
-    const int task = blockIdx.x * GPB + grp;
-    if (task >= n_tasks) return;
-    const int W = a.w, H = a.h;
-    int dir, x, y, len, dx, dy;
-    decode_task(task, W, H, dir, x, y, len);
-    dir_step(dir, dx, dy);
-    // the longest scanlines set the kernel's length: let them issue first
-    if (a.prio_long && len == (dir < 2 ? W : (dir < 4 ? H : -1))) __builtin_amdgcn_s_setprio(3);
-    const Word* __restrict__ cost = reinterpret_cast<const Word*>(a.cost);
-    Word* __restrict__ vol = reinterpret_cast<Word*>(a.vol + (size_t)dir * a.vol_stride);
-    const int dp = dy * W + dx;
-    const int p0 = y * W + x;
+    constexpr uint32_t WB = sizeof(Word);
+    const uint8_t* __restrict__ cost = a.cost;
+    uint8_t* __restrict__ vol = a.vol + (size_t)sc.dir * a.vol_stride;
+    const int dp = sc.dp, len = sc.len, p0 = sc.p0;
     const int p_last = p0 + (len - 1) * dp;
     const uint32_t p1pk = (uint32_t)a.p1 * 0x10001u;
     const int p2 = a.p2;
+    auto at = [&](int pix) { return ((uint32_t)pix * G + lane) * WB; };
 
     Word ring[PF];
 #pragma unroll
-    for (int j = 0; j < PF; ++j) {
-        const int pj = j < len ? p0 + j * dp : p_last;
-        ring[j] = cost[(uint32_t)pj * G + lane];
-    }
+    for (int j = 0; j < PF; ++j)
+        ring[j] = *reinterpret_cast<const Word*>(cost + at(j < len ? p0 + j * dp : p_last));
     uint32_t L[NP];
 #pragma unroll
     for (int r = 0; r < NP; ++r) L[r] = 0u;
     int m = 0;
     int p = p0;
-
     auto step = [&](const Word& w) {
         uint32_t c[NP];
         unpack_costs<NP>(w, c);
-        const uint32_t mpk = (uint32_t)m * 0x10001u;
-        const uint32_t m2pk = (uint32_t)(m + p2) * 0x10001u;
-        const uint32_t prv = from_prev_lane<G>(L[NP - 1]);
-        const uint32_t nxt = from_next_lane<G>(L[0]);
-        uint32_t Ln[NP];
-#pragma unroll
-        for (int r = 0; r < NP; ++r) {
-            const uint32_t lm1 = align16(L[r], r > 0 ? L[r - 1] : prv);
-            const uint32_t lp1 = align16(r + 1 < NP ? L[r + 1] : nxt, L[r]);
-            uint32_t t = pk_add(pk_min(lm1, lp1), p1pk);
-            t = pk_min(pk_min(t, L[r]), m2pk);
-            Ln[r] = pk_sub(pk_add(c[r], t), mpk);
-        }
-        uint32_t mv = Ln[0];
-#pragma unroll
-        for (int r = 0; r < NP; ++r) {
-            L[r] = Ln[r];
-            mv = pk_min(mv, Ln[r]);
-        }
-        vol[(uint32_t)p * G + lane] = pack_costs<NP>(L);
-        m = group_min<G>((int)min(mv & 0xffffu, mv >> 16));
+        packed_update<G, NP>(L, c, m, p1pk, p2);
+        *reinterpret_cast<Word*>(vol + at(p)) = pack_costs<NP>(L);
     };
-
     int i = 0;
     for (; i + PF <= len; i += PF) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
             step(ring[u]);
-            const int pn = (i + u + PF < len) ? p + PF * dp : p_last;
-            ring[u] = cost[(uint32_t)pn * G + lane];
+            ring[u] = *reinterpret_cast<const Word*>(cost + at((i + u + PF < len) ? p + PF * dp : p_last));
             p += dp;
         }
     }
@@ -559,6 +561,136 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_full_kernel(SgmLaunch a, int
             step(ring[u]);
             p += dp;
         }
+    }
+}
+
+// Ragged windows on the packed registers: the same recurrence over all D
+// disparities, slots outside the pixel's window [lo, hi] getting the
+// out-of-window marker cost (see packed_update), so the in-window results
+// equal those of the ragged recurrence exactly.  Costs are gathered byte by
+// byte from the ragged volume (clamped inside the window, masked on use);
+// only in-window path costs are stored.  Window metadata is prefetched 2*PF
+// steps ahead and cost bytes PF steps ahead, as in lds_scanline.
+template <int G, int NP, int PF>
+__device__ inline void packed_scanline_windowed(const SgmLaunch& a, const Scan& sc, int lane) {
+    constexpr int RM = 2 * PF;
+    constexpr int S = 2 * NP;      // slots per lane
+    const uint8_t* __restrict__ cost = a.cost;
+    uint8_t* __restrict__ vol = a.vol + (size_t)sc.dir * a.vol_stride;
+    const int dp = sc.dp, len = sc.len, p0 = sc.p0;
+    const int p_last = p0 + (len - 1) * dp;
+    const uint32_t p1pk = (uint32_t)a.p1 * 0x10001u;
+    const int p2 = a.p2;
+    const int d0 = S * lane;       // this lane's first disparity
+
+    int mlo[RM], mw[RM];
+    uint32_t moff[RM];
+    auto load_meta = [&](int j, int pix) {
+        int hi;
+        window_of<false>(a.win, pix, mlo[j], hi, moff[j]);
+        mw[j] = hi - mlo[j] + 1;
+    };
+    auto load_bytes = [&](int j, uint32_t (&b)[S]) {
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            const int s = min(max(d0 + t - mlo[j], 0), mw[j] - 1);
+            b[t] = cost[moff[j] + (uint32_t)s];
+        }
+    };
+#pragma unroll
+    for (int j = 0; j < RM; ++j) load_meta(j, j < len ? p0 + j * dp : p_last);
+    uint32_t cb[PF][S];
+#pragma unroll
+    for (int j = 0; j < PF; ++j) load_bytes(j, cb[j]);
+
+    uint32_t L[NP];
+#pragma unroll
+    for (int r = 0; r < NP; ++r) L[r] = 0u;
+    int m = 0;
+    int p = p0;
+    auto step = [&](int ti, int tc) {
+        const int lo = mlo[ti], w = mw[ti];
+        const uint32_t off = moff[ti];
+        uint32_t c[NP];
+#pragma unroll
+        for (int r = 0; r < NP; ++r) {
+            const bool in0 = (unsigned)(d0 + 2 * r - lo) < (unsigned)w;
+            const bool in1 = (unsigned)(d0 + 2 * r + 1 - lo) < (unsigned)w;
+            c[r] = (in0 ? cb[tc][2 * r] : 0x3fffu) | ((in1 ? cb[tc][2 * r + 1] : 0x3fffu) << 16);
+        }
+        packed_update<G, NP>(L, c, m, p1pk, p2);
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            const int s = d0 + t - lo;
+            if ((unsigned)s < (unsigned)w)
+                vol[off + (uint32_t)s] = (uint8_t)((t & 1) ? (L[t >> 1] >> 16) : L[t >> 1]);
+        }
+    };
+    int i = 0;
+    for (; i + RM <= len; i += RM) {
+#pragma unroll
+        for (int u = 0; u < RM; ++u) {
+            step(u, u % PF);
+            load_bytes((u + PF) % RM, cb[u % PF]);
+            load_meta(u, (i + u + RM < len) ? p + RM * dp : p_last);
+            p += dp;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < RM; ++u) {
+        if (i + u < len) {
+            step(u, u % PF);
+            if (u + PF < RM) load_bytes(u + PF, cb[u % PF]);
+            p += dp;
+        }
+    }
+}
+
+// ---- kernels ----
+// Generic: every scanline through LDS rows (any D; ragged or full windows).
+template <int G, int K, bool FULL, int PF>
+__global__ __launch_bounds__(kBlock) void sgm_paths_lds_kernel(SgmLaunch a, int n_tasks) {
+    constexpr int GPB = kBlock / G;
+    __shared__ uint16_t lds[GPB][2][G * K + 2];
+    const int grp = threadIdx.x / G, lane = threadIdx.x % G;
+    const int task = blockIdx.x * GPB + grp;
+    if (task >= n_tasks) return;
+    const Scan sc = scan_of(task, a.w, a.h);
+    lds_scanline<G, K, FULL, PF>(a, sc, lane, lds[grp][0], lds[grp][1]);
+}
+
+// Full range, D = 2*NP*G: every scanline on packed registers.
+template <int G, int NP, int PF>
+__global__ __launch_bounds__(kBlock) void sgm_paths_full_kernel(SgmLaunch a, int n_tasks) {
+    constexpr int GPB = kBlock / G;
+    const int grp = threadIdx.x / G, lane = threadIdx.x % G;
+    const int task = blockIdx.x * GPB + grp;
+    if (task >= n_tasks) return;
+    packed_scanline_full<G, NP, PF>(a, scan_of(task, a.w, a.h), lane);
+}
+
+// Ragged windows, D = 2*NP*GP.  Blocks below n_packed_blocks take the first
+// scanline tasks (the rows, longest first) on windowed packed registers;
+// the other blocks take the remaining tasks through LDS rows (work
+// proportional to the window).  n_packed_blocks = 0: all LDS; covering all
+// tasks: all packed.
+template <int GP, int NP, int GL, int K, int PF>
+__global__ __launch_bounds__(kBlock) void sgm_paths_ragged_kernel(SgmLaunch a, int n_tasks,
+                                                                   int n_packed_tasks,
+                                                                   int n_packed_blocks) {
+    if ((int)blockIdx.x < n_packed_blocks) {
+        constexpr int GPB = kBlock / GP;
+        const int grp = threadIdx.x / GP, lane = threadIdx.x % GP;
+        const int task = blockIdx.x * GPB + grp;
+        if (task >= n_packed_tasks) return;
+        packed_scanline_windowed<GP, NP, PF>(a, scan_of(task, a.w, a.h), lane);
+    } else {
+        constexpr int GPB = kBlock / GL;
+        __shared__ uint16_t lds[GPB][2][GL * K + 2];
+        const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
+        const int task = n_packed_tasks + (blockIdx.x - n_packed_blocks) * GPB + grp;
+        if (task >= n_tasks) return;
+        lds_scanline<GL, K, false, PF>(a, scan_of(task, a.w, a.h), lane, lds[grp][0], lds[grp][1]);
     }
 }
 
@@ -860,13 +992,14 @@ hipError_t launch_sgm_paths(const SgmLaunch& a, hipStream_t s) {
     const int n_tasks = 2 * a.h + 2 * a.w + 4 * (a.w + a.h - 1);
     const int D = a.win.max_disp;
     const bool full = a.win.lo == nullptr;
-    auto grid = [&](int G) { return (unsigned)((n_tasks + kBlock / G - 1) / (kBlock / G)); };
-#define EGOSGM_PATHS(GG, KK, FF) \
-    sgm_paths_kernel<GG, KK, FF, 4><<<grid(GG), kBlock, 0, s>>>(a, n_tasks)
-#define EGOSGM_FULL(GG, NN) sgm_paths_full_kernel<GG, NN, 8><<<grid(GG), kBlock, 0, s>>>(a, n_tasks)
+    auto blocks = [&](int n, int G) { return (n + kBlock / G - 1) / (kBlock / G); };
     if (full) {
-        // packed kernel: D = 2 * NP * G
+        // packed kernel where D = 2 * NP * G, LDS kernel otherwise
         const int g = a.full_group;
+#define EGOSGM_FULL(GG, NN) \
+    sgm_paths_full_kernel<GG, NN, 8><<<blocks(n_tasks, GG), kBlock, 0, s>>>(a, n_tasks)
+#define EGOSGM_LDSF(GG, KK) \
+    sgm_paths_lds_kernel<GG, KK, true, 4><<<blocks(n_tasks, GG), kBlock, 0, s>>>(a, n_tasks)
         if (D == 64) {
             if (g == 32) EGOSGM_FULL(32, 1); else EGOSGM_FULL(16, 2);
         } else if (D == 128) {
@@ -874,29 +1007,37 @@ hipError_t launch_sgm_paths(const SgmLaunch& a, hipStream_t s) {
         } else if (D == 256) {
             if (g == 16) EGOSGM_FULL(16, 8); else if (g == 64) EGOSGM_FULL(64, 2); else EGOSGM_FULL(32, 4);
         } else if (D <= 64) {
-            EGOSGM_PATHS(64, 1, true);
+            EGOSGM_LDSF(64, 1);
         } else if (D <= 128) {
-            EGOSGM_PATHS(64, 2, true);
+            EGOSGM_LDSF(64, 2);
         } else {
-            EGOSGM_PATHS(64, 4, true);
+            EGOSGM_LDSF(64, 4);
         }
-    } else {
-        const int g = a.ragged_group;
-        if (D <= 16) EGOSGM_PATHS(16, 1, false);
-        else if (D <= 32) { if (g == 32) EGOSGM_PATHS(32, 1, false); else EGOSGM_PATHS(16, 2, false); }
-        else if (D <= 64) { if (g == 16) EGOSGM_PATHS(16, 4, false); else EGOSGM_PATHS(32, 2, false); }
-        else if (D <= 128) {
-            if (g == 16) EGOSGM_PATHS(16, 8, false);
-            else if (g == 64) EGOSGM_PATHS(64, 2, false);
-            else EGOSGM_PATHS(32, 4, false);
-        } else {
-            if (g == 16) EGOSGM_PATHS(16, 16, false);
-            else if (g == 64) EGOSGM_PATHS(64, 4, false);
-            else EGOSGM_PATHS(32, 8, false);
-        }
-    }
-#undef EGOSGM_PATHS
 #undef EGOSGM_FULL
+#undef EGOSGM_LDSF
+        return hipGetLastError();
+    }
+    // ragged: the LDS kernel's lanes per scanline come from the tuning; the
+    // packed part (rows, or everything) uses 32 lanes over D rounded up to
+    // 64, 128 or 256.
+    const int g = a.ragged_group;
+    const int sched = a.ragged_schedule;   // 0: all LDS, 1: rows packed, 2: all packed
+    const int n_packed = sched == 0 ? 0 : (sched == 1 ? 2 * a.h : n_tasks);
+#define EGOSGM_RAG(NP, GL, KK)                                                                 \
+    do {                                                                                       \
+        const int nb_p = blocks(n_packed, 32);                                                 \
+        const int nb = nb_p + blocks(n_tasks - n_packed, GL);                                  \
+        sgm_paths_ragged_kernel<32, NP, GL, KK, 4><<<nb, kBlock, 0, s>>>(a, n_tasks, n_packed, \
+                                                                          nb_p);               \
+    } while (0)
+    if (D <= 64) {
+        if (g == 16) EGOSGM_RAG(1, 16, 4); else if (g == 64) EGOSGM_RAG(1, 64, 1); else EGOSGM_RAG(1, 32, 2);
+    } else if (D <= 128) {
+        if (g == 16) EGOSGM_RAG(2, 16, 8); else if (g == 32) EGOSGM_RAG(2, 32, 4); else EGOSGM_RAG(2, 64, 2);
+    } else {
+        if (g == 16) EGOSGM_RAG(4, 16, 16); else if (g == 32) EGOSGM_RAG(4, 32, 8); else EGOSGM_RAG(4, 64, 4);
+    }
+#undef EGOSGM_RAG
     return hipGetLastError();
 }
 

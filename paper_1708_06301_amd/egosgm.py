@@ -84,18 +84,22 @@ class SgmDebug(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("full_group", C.c_int32), ("ragged_group", C.c_int32),
-                ("prio_long", C.c_int32)]
+                ("ragged_schedule", C.c_int32)]
 
 
-def set_tuning(full_group: int = 32, ragged_group: int = 32, prio_long: int = 1):
-    t = Tuning(full_group, ragged_group, prio_long)
+DEFAULT_TUNING = dict(full_group=64, ragged_group=64, ragged_schedule=0)
+
+
+def set_tuning(full_group: int = 64, ragged_group: int = 64, ragged_schedule: int = 0):
+    t = Tuning(full_group, ragged_group, ragged_schedule)
     _check(lib().egosgm_set_tuning(C.byref(t)), "egosgm_set_tuning")
 
 
 def get_tuning() -> dict:
     t = Tuning()
     _check(lib().egosgm_get_tuning(C.byref(t)), "egosgm_get_tuning")
-    return dict(full_group=t.full_group, ragged_group=t.ragged_group, prio_long=t.prio_long)
+    return dict(full_group=t.full_group, ragged_group=t.ragged_group,
+                ragged_schedule=t.ragged_schedule)
 
 
 @dataclass

@@ -116,6 +116,7 @@ def test_tuning_validation():
     assert lib.egosgm_set_tuning(C.byref(bad)) == -1
     assert lib.egosgm_set_tuning(None) == -1
     assert eg.get_tuning() == before
+    assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, 3))) == -1
     eg.set_tuning(16, 64, 0)
-    assert eg.get_tuning() == dict(full_group=16, ragged_group=64, prio_long=0)
+    assert eg.get_tuning() == dict(full_group=16, ragged_group=64, ragged_schedule=0)
     eg.set_tuning(**before)

@@ -256,7 +256,7 @@ def test_tuning_never_changes_results(D):
                    _gpu(wo[2].view(np.int32)))
     prm = eg.MatchParams(max_disp=D)
     try:
-        for fg, rg, pr in itertools.product((16, 32, 64), (16, 32, 64), (0, 1)):
+        for fg, rg, pr in itertools.product((16, 32, 64), (16, 32, 64), (0, 1, 2)):
             eg.set_tuning(fg, rg, pr)
             a = eg.sgm_full(L, R, prm)
             b = eg.sgm_reduced(L, R, lo, hi, off, prm)
@@ -265,4 +265,4 @@ def test_tuning_never_changes_results(D):
             assert np.array_equal(_np(b["disp_wta"]), o_red["disp_wta"]), (fg, rg, pr)
             assert np.array_equal(_np(b["disp_right"]), o_red["disp_right"]), (fg, rg, pr)
     finally:
-        eg.set_tuning(32, 32, 1)
+        eg.set_tuning(**eg.DEFAULT_TUNING)
