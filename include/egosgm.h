@@ -226,10 +226,52 @@ int kalman_update(const float* d_pred, const float* p_pred, const float* d_meas,
                   const float* r_meas, int n, int keep_unmeasured, float* d_out, float* p_out,
                   void* stream);
 
+/* ------------------------------------------------------------------ batches
+ * Batched matching (many stereo pairs of any sizes, each with its own
+ * disparity range and either the full range or ragged windows, in one launch
+ * per stage), captured once into a HIP graph.  A plan owns the graph; the
+ * caller owns every buffer, which must keep its address while the plan lives
+ * (the graph bakes the pointers).  The windows' contents may change between
+ * runs; each run computes exactly what sgm_full / sgm_reduced computes for
+ * each pair alone. */
+typedef struct egosgm_pair {
+    const uint8_t* left;      /* w x h uint8, row pitch `pitch`                   */
+    const uint8_t* right;
+    int32_t w, h, pitch;
+    int32_t max_disp;         /* this pair's D, 1..256                            */
+    const int16_t* lo;        /* ragged windows (as sgm_reduced), or all three    */
+    const int16_t* hi;        /* NULL for the full range                          */
+    const uint32_t* offsets;
+    int16_t* disp_wta;        /* outputs, w*h each, as sgm_full                   */
+    float* disp_sub;
+    float* var_meas;
+    int16_t* disp_right;      /* nullable                                         */
+} egosgm_pair;
+
+typedef struct egosgm_plan egosgm_plan;
+
+/* Workspace bytes of a plan over pairs[0..n-1] (host array); 0 if invalid. */
+size_t egosgm_plan_workspace_bytes(const egosgm_pair* pairs, int n);
+
+/* Validates the pairs, lays out the workspace (device memory of at least
+ * egosgm_plan_workspace_bytes), uploads the per-pair tables (synchronously)
+ * and captures census, cost, paths, selection and left-right check of all
+ * pairs into one graph.  params: p1, p2, s_max, lr_tol shared by all pairs
+ * (max_disp is taken from each pair).  *out: the new plan. */
+int sgm_plan_create(const egosgm_pair* pairs, int n, const egosgm_sgm_params* params,
+                    void* workspace, size_t workspace_bytes, egosgm_plan** out);
+/* One launch of the captured graph on `stream`. */
+int sgm_plan_run(egosgm_plan* plan, void* stream);
+/* The same kernels launched one by one on `stream` (no graph), each stage
+ * bracketed by the timing events when timing is enabled. */
+int sgm_plan_run_eager(egosgm_plan* plan, void* stream);
+/* Frees the plan (not the buffers).  NULL is accepted. */
+int sgm_plan_destroy(egosgm_plan* plan);
+
 /* ------------------------------------------------------------------ tuning
  * Launch shapes and schedules of the path kernels, process-wide (the second
  * piece of state the library keeps; set it before enqueueing work, e.g. from
- * an autotuner).  Results never depend on it.  Defaults: {64, 64, 0}. */
+ * an autotuner).  Results never depend on it.  Defaults: {64, 64, 0, 16}. */
 typedef struct egosgm_tuning {
     int32_t full_group;      /* lanes per scanline, full-range kernel: 16, 32, 64             */
     int32_t ragged_group;    /* lanes per scanline, ragged windows through LDS: 16, 32, 64    */
@@ -237,6 +279,8 @@ typedef struct egosgm_tuning {
                                 1: the image rows (the longest scanlines) on packed registers
                                    over all disparities, the rest through LDS;
                                 2: every scanline on packed registers                        */
+    int32_t batch_group;     /* lanes per scanline in batched plans (fixed when a plan is
+                                created): 16, 32, 64                                           */
 } egosgm_tuning;
 
 int egosgm_set_tuning(const egosgm_tuning* tuning);
@@ -258,7 +302,11 @@ typedef enum egosgm_stage {
     EGOSGM_STAGE_WARP = 5,    /* z-buffer clear, scatter, decode (three kernels) */
     EGOSGM_STAGE_KALMAN = 6,  /* Kalman update (one kernel)                      */
     EGOSGM_STAGE_REFINE = 7,  /* prediction refinement (three kernels)           */
-    EGOSGM_STAGE_COUNT = 8
+    EGOSGM_STAGE_BATCH_CENSUS = 8,  /* batched plans, run eagerly: census        */
+    EGOSGM_STAGE_BATCH_COST = 9,    /* cost                                      */
+    EGOSGM_STAGE_BATCH_PATHS = 10,  /* 8-path aggregation                        */
+    EGOSGM_STAGE_BATCH_SELECT = 11, /* selection and left-right check            */
+    EGOSGM_STAGE_COUNT = 12
 } egosgm_stage;
 
 int egosgm_timing_enable(int on);

@@ -69,7 +69,7 @@ def tune(run, w, h, max_disp, tag="", candidates=None, reps=3, use_cache=True, l
     cache = _load() if use_cache else {}
     if use_cache and key in cache:
         best = cache[key]["tuning"]
-        eg.set_tuning(**best)
+        eg.set_tuning(**{**eg.get_tuning(), **best})
         return best, cache[key].get("times", {})
     cands = candidates or CANDIDATES
     times = {}
@@ -77,13 +77,13 @@ def tune(run, w, h, max_disp, tag="", candidates=None, reps=3, use_cache=True, l
     torch.cuda.synchronize()
     t0 = time.time()
     for i, c in enumerate(cands):
-        eg.set_tuning(**c)
+        eg.set_tuning(**{**eg.get_tuning(), **c})
         times[i] = time_workload(run, reps)
         if log:
             log(f"tune {c}: {times[i]:.3f} ms")
     best_i = min(times, key=times.get)
     best = cands[best_i]
-    eg.set_tuning(**best)
+    eg.set_tuning(**{**eg.get_tuning(), **best})
     if log:
         log(f"tuned in {time.time() - t0:.1f}s: {best} ({times[best_i]:.3f} ms)")
     if use_cache:

@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -57,7 +58,7 @@ hipError_t timed(int stage, hipStream_t s, F&& fn) {
 }
 
 // Launch-shape choices (set by egosgm_set_tuning; read at every launch).
-egosgm_tuning g_tuning = {64, 64, 0};
+egosgm_tuning g_tuning = {64, 64, 0, 16};
 std::mutex g_tuning_mu;
 
 constexpr size_t kAlign = 256;
@@ -115,6 +116,9 @@ int run_sgm(const uint8_t* left, const uint8_t* right, int w, int h, int pitch, 
     uint8_t* base = static_cast<uint8_t*>(ws);
 
     SgmLaunch a;
+    a.left = left;
+    a.right = right;
+    a.pitch = pitch;
     a.census_l = reinterpret_cast<uint64_t*>(base + L.census_l);
     a.census_r = reinterpret_cast<uint64_t*>(base + L.census_r);
     a.w = w;
@@ -171,7 +175,226 @@ int run_sgm(const uint8_t* left, const uint8_t* right, int w, int h, int pitch, 
 
 }  // namespace
 
+// ---------------------------------------------------------------- plans
+struct egosgm_plan {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int n = 0;
+    int max_disp = 0;
+    BatchTables tables{};
+};
+
+namespace {
+
+size_t pair_bytes(const egosgm_pair& p) {
+    WsLayout L;
+    ws_layout(p.w, p.h, p.max_disp, L);
+    return L.total;
+}
+
+int check_pair(const egosgm_pair& p) {
+    if (!p.left || !p.right || !p.disp_wta || !p.disp_sub || !p.var_meas) return EGOSGM_EINVAL;
+    const int rc = check_shape(p.w, p.h, p.max_disp);
+    if (rc) return rc;
+    if (p.pitch < p.w) return EGOSGM_EINVAL;
+    if ((p.lo == nullptr) != (p.hi == nullptr) || (p.lo == nullptr) != (p.offsets == nullptr))
+        return EGOSGM_EINVAL;
+    return EGOSGM_OK;
+}
+
+struct PlanLayout {
+    size_t pairs, census_prefix, seg_prefix, pix_prefix, task_start, task_pair, task_local, task_count;
+    size_t data, total;
+    int n_ranges;
+};
+
+PlanLayout plan_layout(const egosgm_pair* pairs, int n) {
+    PlanLayout P;
+    P.n_ranges = 3 * n;
+    size_t o = 0;
+    P.pairs = o;         o += align_up((size_t)n * sizeof(SgmLaunch));
+    P.census_prefix = o; o += align_up((size_t)(n + 1) * sizeof(int));
+    P.seg_prefix = o;    o += align_up((size_t)(n + 1) * sizeof(int));
+    P.pix_prefix = o;    o += align_up((size_t)(n + 1) * sizeof(int));
+    P.task_start = o;    o += align_up((size_t)P.n_ranges * sizeof(int));
+    P.task_pair = o;     o += align_up((size_t)P.n_ranges * sizeof(int));
+    P.task_local = o;    o += align_up((size_t)P.n_ranges * sizeof(int));
+    P.task_count = o;    o += align_up((size_t)P.n_ranges * sizeof(int));
+    P.data = o;
+    for (int i = 0; i < n; ++i) o += pair_bytes(pairs[i]);
+    P.total = o;
+    return P;
+}
+
+}  // namespace
+
 extern "C" {
+
+size_t egosgm_plan_workspace_bytes(const egosgm_pair* pairs, int n) {
+    if (!pairs || n <= 0) return 0;
+    for (int i = 0; i < n; ++i)
+        if (check_pair(pairs[i])) return 0;
+    return plan_layout(pairs, n).total;
+}
+
+int sgm_plan_create(const egosgm_pair* pairs, int n, const egosgm_sgm_params* params,
+                    void* workspace, size_t workspace_bytes, egosgm_plan** out) {
+    if (!pairs || n <= 0 || !out) return EGOSGM_EINVAL;
+    *out = nullptr;
+    if (!params) return EGOSGM_EINVAL;
+    egosgm_sgm_params prm = *params;
+    int max_disp = 1;
+    for (int i = 0; i < n; ++i) {
+        const int rc = check_pair(pairs[i]);
+        if (rc) return rc;
+        max_disp = std::max(max_disp, pairs[i].max_disp);
+    }
+    prm.max_disp = max_disp;
+    int rc = check_params(&prm);
+    if (rc) return rc;
+    const PlanLayout P = plan_layout(pairs, n);
+    if (!workspace || workspace_bytes < P.total) return EGOSGM_EWORKSPACE;
+    uint8_t* base = static_cast<uint8_t*>(workspace);
+
+    std::vector<SgmLaunch> desc(n);
+    std::vector<int> cen(n + 1, 0), seg(n + 1, 0), pix(n + 1, 0);
+    std::vector<int> ts(P.n_ranges), tp(P.n_ranges), tl(P.n_ranges), tc(P.n_ranges);
+    size_t o = P.data;
+    long long tasks = 0, segs = 0, tiles = 0, pixels = 0;
+    for (int i = 0; i < n; ++i) {
+        const egosgm_pair& q = pairs[i];
+        WsLayout L;
+        ws_layout(q.w, q.h, q.max_disp, L);
+        SgmLaunch& a = desc[i];
+        a = SgmLaunch{};
+        a.left = q.left;
+        a.right = q.right;
+        a.pitch = q.pitch;
+        a.census_l = reinterpret_cast<uint64_t*>(base + o + L.census_l);
+        a.census_r = reinterpret_cast<uint64_t*>(base + o + L.census_r);
+        a.key_r = reinterpret_cast<uint32_t*>(base + o + L.key_r);
+        a.cost = base + o + L.cost;
+        a.vol = base + o + L.vol;
+        a.vol_stride = L.vol_stride;
+        a.w = q.w;
+        a.h = q.h;
+        a.win = Windows{q.lo, q.hi, q.offsets, q.max_disp};
+        a.p1 = prm.p1;
+        a.p2 = prm.p2;
+        a.s_max = prm.s_max;
+        a.lr_tol = prm.lr_tol;
+        a.disp_wta = q.disp_wta;
+        a.disp_sub = q.disp_sub;
+        a.var_meas = q.var_meas;
+        a.disp_right = q.disp_right;
+        o += L.total;
+        cen[i] = (int)tiles;
+        seg[i] = (int)segs;
+        pix[i] = (int)pixels;
+        tiles += (long long)((q.w + 63) / 64) * ((q.h + 3) / 4);
+        segs += (long long)((q.w + 63) / 64) * q.h;
+        pixels += (long long)q.w * q.h;
+    }
+    cen[n] = (int)tiles;
+    seg[n] = (int)segs;
+    pix[n] = (int)pixels;
+    // scanline tasks by class: rows (2h), columns (2w), diagonals (4(w+h-1))
+    int r = 0;
+    for (int cls = 0; cls < 3; ++cls)
+        for (int i = 0; i < n; ++i) {
+            const int w = pairs[i].w, h = pairs[i].h;
+            const int cnt = cls == 0 ? 2 * h : (cls == 1 ? 2 * w : 4 * (w + h - 1));
+            ts[r] = (int)tasks;
+            tp[r] = i;
+            tl[r] = cls == 0 ? 0 : (cls == 1 ? 2 * h : 2 * h + 2 * w);
+            tc[r] = cnt;
+            tasks += (cnt + 3) / 4 * 4;   // ranges start at multiples of 4
+            ++r;
+        }
+    if (tasks >= (1ll << 31) || pixels >= (1ll << 31) || segs >= (1ll << 31)) return EGOSGM_EUNSUPPORTED;
+
+    auto up = [&](size_t off, const void* src, size_t bytes) {
+        return hipMemcpy(base + off, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    if (!up(P.pairs, desc.data(), n * sizeof(SgmLaunch)) ||
+        !up(P.census_prefix, cen.data(), (n + 1) * sizeof(int)) ||
+        !up(P.seg_prefix, seg.data(), (n + 1) * sizeof(int)) ||
+        !up(P.pix_prefix, pix.data(), (n + 1) * sizeof(int)) ||
+        !up(P.task_start, ts.data(), P.n_ranges * sizeof(int)) ||
+        !up(P.task_pair, tp.data(), P.n_ranges * sizeof(int)) ||
+        !up(P.task_local, tl.data(), P.n_ranges * sizeof(int)) ||
+        !up(P.task_count, tc.data(), P.n_ranges * sizeof(int)))
+        return EGOSGM_EDEVICE;
+
+    BatchTables t;
+    t.pairs = reinterpret_cast<const SgmLaunch*>(base + P.pairs);
+    t.census_prefix = reinterpret_cast<const int*>(base + P.census_prefix);
+    t.seg_prefix = reinterpret_cast<const int*>(base + P.seg_prefix);
+    t.pix_prefix = reinterpret_cast<const int*>(base + P.pix_prefix);
+    t.task_start = reinterpret_cast<const int*>(base + P.task_start);
+    t.task_pair = reinterpret_cast<const int*>(base + P.task_pair);
+    t.task_local = reinterpret_cast<const int*>(base + P.task_local);
+    t.task_count = reinterpret_cast<const int*>(base + P.task_count);
+    {
+        std::lock_guard<std::mutex> g(g_tuning_mu);
+        t.group = g_tuning.batch_group;
+    }
+    t.n = n;
+    t.n_ranges = P.n_ranges;
+    t.n_tasks = (int)tasks;
+    t.host_census_blocks = (int)tiles;
+    t.host_seg_blocks = (int)segs;
+    t.host_pixels = (int)pixels;
+
+    egosgm_plan* plan = new egosgm_plan;
+    plan->n = n;
+    plan->max_disp = max_disp;
+    plan->tables = t;
+    hipStream_t cs = nullptr;
+    bool ok = hipStreamCreate(&cs) == hipSuccess;
+    ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        const hipError_t le = launch_sgm_batch(t, max_disp, cs);
+        const hipError_t ce = hipStreamEndCapture(cs, &plan->graph);
+        ok = le == hipSuccess && ce == hipSuccess && plan->graph;
+    }
+    ok = ok && hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0) == hipSuccess;
+    if (cs) (void)hipStreamDestroy(cs);
+    if (!ok) {
+        sgm_plan_destroy(plan);
+        return EGOSGM_EDEVICE;
+    }
+    *out = plan;
+    return EGOSGM_OK;
+}
+
+int sgm_plan_run(egosgm_plan* plan, void* stream) {
+    if (!plan || !plan->exec) return EGOSGM_EINVAL;
+    return hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream)) == hipSuccess
+               ? EGOSGM_OK
+               : EGOSGM_EDEVICE;
+}
+
+int sgm_plan_run_eager(egosgm_plan* plan, void* stream) {
+    if (!plan || !plan->exec) return EGOSGM_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const BatchTables& t = plan->tables;
+    return timed(EGOSGM_STAGE_BATCH_CENSUS, s, [&] { return launch_batch_stage(t, plan->max_disp, 0, s); }) == hipSuccess &&
+                   timed(EGOSGM_STAGE_BATCH_COST, s, [&] { return launch_batch_stage(t, plan->max_disp, 1, s); }) == hipSuccess &&
+                   timed(EGOSGM_STAGE_BATCH_PATHS, s, [&] { return launch_batch_stage(t, plan->max_disp, 2, s); }) == hipSuccess &&
+                   timed(EGOSGM_STAGE_BATCH_SELECT, s, [&] { return launch_batch_stage(t, plan->max_disp, 3, s); }) == hipSuccess &&
+                   timed(EGOSGM_STAGE_BATCH_SELECT, s, [&] { return launch_batch_stage(t, plan->max_disp, 4, s); }) == hipSuccess
+               ? EGOSGM_OK
+               : EGOSGM_EDEVICE;
+}
+
+int sgm_plan_destroy(egosgm_plan* plan) {
+    if (!plan) return EGOSGM_OK;
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    delete plan;
+    return EGOSGM_OK;
+}
 
 int egosgm_abi_version(void) { return EGOSGM_ABI_VERSION; }
 
@@ -356,7 +579,8 @@ int kalman_update(const float* d_pred, const float* p_pred, const float* d_meas,
 int egosgm_set_tuning(const egosgm_tuning* t) {
     if (!t) return EGOSGM_EINVAL;
     auto ok = [](int g) { return g == 16 || g == 32 || g == 64; };
-    if (!ok(t->full_group) || !ok(t->ragged_group) || t->ragged_schedule < 0 || t->ragged_schedule > 2)
+    if (!ok(t->full_group) || !ok(t->ragged_group) || !ok(t->batch_group) || t->ragged_schedule < 0 ||
+        t->ragged_schedule > 2)
         return EGOSGM_EINVAL;
     std::lock_guard<std::mutex> g(g_tuning_mu);
     g_tuning = *t;

@@ -22,6 +22,9 @@ struct Windows {
 };
 
 struct SgmLaunch {
+    const uint8_t* left;     // images (read by the batched census pass)
+    const uint8_t* right;
+    int pitch;
     const uint64_t* census_l;
     const uint64_t* census_r;
     int w, h;
@@ -42,6 +45,25 @@ struct SgmLaunch {
     int16_t* wta_raw;        // nullable (debug)
 };
 
+// Device tables of a batched launch (all pointers into device memory),
+// plus the host-side launch sizes.
+struct BatchTables {
+    const SgmLaunch* pairs;     // n descriptors
+    const int* census_prefix;   // n+1: census tiles per pair
+    const int* seg_prefix;      // n+1: 64-pixel row segments per pair (cost, select)
+    const int* pix_prefix;      // n+1: pixels per pair
+    const int* task_start;      // n_ranges: first global scanline task of each range
+    const int* task_pair;       // n_ranges: pair of each range
+    const int* task_local;      // n_ranges: first local task of each range
+    const int* task_count;      // n_ranges: real tasks of each range (the rest is padding)
+    int n, n_ranges, n_tasks;
+    int group;                  // lanes per scanline of the path kernel (16, 32, 64)
+    int host_census_blocks, host_seg_blocks, host_pixels;
+};
+
+hipError_t launch_sgm_batch(const BatchTables& t, int max_disp, hipStream_t s);
+// stage 0 census, 1 cost, 2 paths, 3 selection, 4 left-right check
+hipError_t launch_batch_stage(const BatchTables& t, int max_disp, int stage, hipStream_t s);
 hipError_t launch_census(const uint8_t* img, int w, int h, int pitch, uint64_t* out,
                          hipStream_t s);
 hipError_t launch_census_pair(const uint8_t* left, const uint8_t* right, int w, int h,

@@ -24,22 +24,33 @@ constexpr int kCtW = 64;          // output tile width  (one wave per row)
 constexpr int kCtH = kBlock / kCtW;  // output tile height
 constexpr int kHaloX = 4, kHaloY = 3;
 
-__global__ __launch_bounds__(kBlock) void census_kernel(const uint8_t* __restrict__ img0,
-                                                        const uint8_t* __restrict__ img1,
-                                                        int w, int h, int pitch,
-                                                        uint64_t* __restrict__ out0,
-                                                        uint64_t* __restrict__ out1,
-                                                        uint32_t* __restrict__ clear) {
-    const uint8_t* img = blockIdx.z ? img1 : img0;
-    uint64_t* out = blockIdx.z ? out1 : out0;
+// Every buffer the kernels touch is global memory.  Accesses go through
+// explicitly global pointers so that the compiler emits global (not flat)
+// instructions also where a pointer comes from a descriptor read from
+// memory: flat loads count against the LDS wait counter as well, and every
+// LDS wait would then drain the outstanding global prefetches.
+template <class T>
+using gmem = __attribute__((address_space(1))) T;
+template <class T>
+__device__ inline gmem<T>* gptr(T* p) {
+    return (gmem<T>*)p;
+}
+
+// One 64x4 output tile of one image; clear (nullable) gets 0xffffffff per
+// pixel (the right-map keys of the matcher, reset here so that no memset is
+// needed in a captured graph).
+__device__ inline void census_tile(const uint8_t* __restrict__ img, int w, int h, int pitch,
+                                   uint64_t* __restrict__ out, uint32_t* __restrict__ clear,
+                                   int tx, int ty) {
     constexpr int TW = kCtW + 2 * kHaloX, TH = kCtH + 2 * kHaloY;
     __shared__ uint8_t tile[TH][TW];
-    const int x0 = blockIdx.x * kCtW, y0 = blockIdx.y * kCtH;
+    const gmem<const uint8_t>* __restrict__ gimg = gptr(img);
+    const int x0 = tx * kCtW, y0 = ty * kCtH;
     for (int i = threadIdx.x; i < TW * TH; i += kBlock) {
-        const int ty = i / TW, tx = i - ty * TW;
-        const int gx = min(max(x0 + tx - kHaloX, 0), w - 1);
-        const int gy = min(max(y0 + ty - kHaloY, 0), h - 1);
-        tile[ty][tx] = img[(size_t)gy * pitch + gx];
+        const int r = i / TW, c = i - r * TW;
+        const int gx = min(max(x0 + c - kHaloX, 0), w - 1);
+        const int gy = min(max(y0 + r - kHaloY, 0), h - 1);
+        tile[r][c] = gimg[(size_t)gy * pitch + gx];
     }
     __syncthreads();
     const int lx = threadIdx.x % kCtW, ly = threadIdx.x / kCtW;
@@ -57,8 +68,20 @@ __global__ __launch_bounds__(kBlock) void census_kernel(const uint8_t* __restric
             ++k;
         }
     }
-    out[(size_t)y * w + x] = code;
-    if (clear && blockIdx.z == 0) clear[(size_t)y * w + x] = 0xffffffffu;
+    gptr(out)[(size_t)y * w + x] = code;
+    if (clear) gptr(clear)[(size_t)y * w + x] = 0xffffffffu;
+}
+
+__global__ __launch_bounds__(kBlock) void census_kernel(const uint8_t* __restrict__ img0,
+                                                        const uint8_t* __restrict__ img1,
+                                                        int w, int h, int pitch,
+                                                        uint64_t* __restrict__ out0,
+                                                        uint64_t* __restrict__ out1,
+                                                        uint32_t* __restrict__ clear) {
+    if (blockIdx.z == 0)
+        census_tile(img0, w, h, pitch, out0, clear, blockIdx.x, blockIdx.y);
+    else
+        census_tile(img1, w, h, pitch, out1, nullptr, blockIdx.x, blockIdx.y);
 }
 
 // ------------------------------------------------------------------ windows
@@ -153,16 +176,20 @@ __global__ __launch_bounds__(kBlock) void windows_offset_kernel(int w, int h,
 }
 
 // ------------------------------------------------------------------ SGM common
-template <bool FULL>
+// Window modes: ragged arrays, full range, or decided per pair at run time
+// (batched launches mixing both).
+constexpr int kWinRagged = 0, kWinFull = 1, kWinAny = 2;
+
+template <int WM>
 __device__ inline void window_of(const Windows& win, int p, int& lo, int& hi, uint32_t& off) {
-    if (FULL) {
+    if (WM == kWinFull || (WM == kWinAny && win.lo == nullptr)) {
         lo = 0;
         hi = win.max_disp - 1;
         off = (uint32_t)p * (uint32_t)win.max_disp;
     } else {
-        lo = win.lo[p];
-        hi = win.hi[p];
-        off = win.off[p];
+        lo = gptr(win.lo)[p];
+        hi = gptr(win.hi)[p];
+        off = gptr(win.off)[p];
     }
 }
 
@@ -205,16 +232,17 @@ __device__ inline void lds_order() { __asm__ volatile("" ::: "memory"); }
 // segment stages the left codes and the right codes x0-(D-1) .. x0+63 in LDS.
 constexpr int kSeg = 64;
 
-template <int G, bool FULL>
-__global__ __launch_bounds__(kBlock) void cost_kernel(SgmLaunch a) {
+template <int G, int WM>
+__device__ inline void cost_segment(const SgmLaunch& a, int seg, int y) {
     constexpr int GPB = kBlock / G;
     __shared__ uint64_t crs[kSeg + kMaxDisp];
     __shared__ uint64_t cls[kSeg];
     const int W = a.w, D = a.win.max_disp;
-    const int y = blockIdx.y, x0 = blockIdx.x * kSeg;
+    const int x0 = seg * kSeg;
     const int base = x0 - (D - 1);
-    const uint64_t* rowl = a.census_l + (size_t)y * W;
-    const uint64_t* rowr = a.census_r + (size_t)y * W;
+    const gmem<const uint64_t>* rowl = gptr(a.census_l + (size_t)y * W);
+    const gmem<const uint64_t>* rowr = gptr(a.census_r + (size_t)y * W);
+    gmem<uint8_t>* __restrict__ cost = gptr(a.cost);
     for (int i = threadIdx.x; i < kSeg + D - 1; i += kBlock) {
         const int xr = base + i;
         crs[i] = (xr >= 0 && xr < W) ? rowr[xr] : 0ull;
@@ -227,14 +255,19 @@ __global__ __launch_bounds__(kBlock) void cost_kernel(SgmLaunch a) {
         if (x >= W) break;
         int lo, hi;
         uint32_t off;
-        window_of<FULL>(a.win, y * W + x, lo, hi, off);
+        window_of<WM>(a.win, y * W + x, lo, hi, off);
         const uint64_t cl = cls[i];
         for (int sl = lane; sl <= hi - lo; sl += G) {
             const int d = lo + sl;
             const int c = (x - d >= 0) ? __popcll(cl ^ crs[i + (D - 1) - d]) : kCensusBits;
-            a.cost[off + (uint32_t)sl] = (uint8_t)c;
+            cost[off + (uint32_t)sl] = (uint8_t)c;
         }
     }
+}
+
+template <int G, int WM>
+__global__ __launch_bounds__(kBlock) void cost_kernel(SgmLaunch a) {
+    cost_segment<G, WM>(a, blockIdx.x, blockIdx.y);
 }
 
 // ------------------------------------------------------------------ SGM paths
@@ -288,7 +321,7 @@ __device__ inline void dir_step(int dir, int& dx, int& dy) {
 
 // Costs of this lane's slots s = lane + G*k of one pixel's window.
 template <int G, int K>
-__device__ inline void load_costs(const uint8_t* __restrict__ cost, uint32_t off, int w, int lane,
+__device__ inline void load_costs(const gmem<uint8_t>* __restrict__ cost, uint32_t off, int w, int lane,
                                   int (&c)[K]) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -323,13 +356,13 @@ __device__ inline Scan scan_of(int task, int W, int H) {
 // slots named at compile time, so a step waits only on memory operations
 // issued PF steps earlier.  A zero predecessor row over the first window
 // makes the first step L = C.
-template <int G, int K, bool FULL, int PF>
+template <int G, int K, int WM, int PF>
 __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane,
                                     uint16_t* b0, uint16_t* b1) {
     constexpr int RM = 2 * PF;
     constexpr int ROW = G * K + 2;
-    uint8_t* __restrict__ vol = a.vol + (size_t)sc.dir * a.vol_stride;
-    const uint8_t* __restrict__ cost = a.cost;
+    gmem<uint8_t>* __restrict__ vol = gptr(a.vol + (size_t)sc.dir * a.vol_stride);
+    const gmem<uint8_t>* __restrict__ cost = gptr(a.cost);
     const int p1 = a.p1, p2 = a.p2;
     const int dp = sc.dp, len = sc.len, p0 = sc.p0;
     const int p_last = p0 + (len - 1) * dp;
@@ -338,7 +371,7 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
     uint32_t moff[RM];
     auto load_meta = [&](int j, int pix) {
         int hi;
-        window_of<FULL>(a.win, pix, mlo[j], hi, moff[j]);
+        window_of<WM>(a.win, pix, mlo[j], hi, moff[j]);
         mw[j] = hi - mlo[j] + 1;
     };
 #pragma unroll
@@ -445,8 +478,11 @@ __device__ inline uint32_t from_next_lane(uint32_t v) {
 template <int NP> struct CostWord;
 template <> struct CostWord<1> { using T = uint16_t; };
 template <> struct CostWord<2> { using T = uint32_t; };
-template <> struct CostWord<4> { using T = uint2; };
-template <> struct CostWord<8> { using T = uint4; };
+// (clang vector types: they load and store through global pointers)
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+template <> struct CostWord<4> { using T = u32x2; };
+template <> struct CostWord<8> { using T = u32x4; };
 
 template <int NP>
 __device__ inline void unpack_costs(const typename CostWord<NP>::T& w, uint32_t (&c)[NP]) {
@@ -523,8 +559,8 @@ template <int G, int NP, int PF>
 __device__ inline void packed_scanline_full(const SgmLaunch& a, const Scan& sc, int lane) {
     using Word = typename CostWord<NP>::T;
     constexpr uint32_t WB = sizeof(Word);
-    const uint8_t* __restrict__ cost = a.cost;
-    uint8_t* __restrict__ vol = a.vol + (size_t)sc.dir * a.vol_stride;
+    const gmem<uint8_t>* __restrict__ cost = gptr(a.cost);
+    gmem<uint8_t>* __restrict__ vol = gptr(a.vol + (size_t)sc.dir * a.vol_stride);
     const int dp = sc.dp, len = sc.len, p0 = sc.p0;
     const int p_last = p0 + (len - 1) * dp;
     const uint32_t p1pk = (uint32_t)a.p1 * 0x10001u;
@@ -534,7 +570,7 @@ __device__ inline void packed_scanline_full(const SgmLaunch& a, const Scan& sc, 
     Word ring[PF];
 #pragma unroll
     for (int j = 0; j < PF; ++j)
-        ring[j] = *reinterpret_cast<const Word*>(cost + at(j < len ? p0 + j * dp : p_last));
+        ring[j] = *reinterpret_cast<const gmem<Word>*>(cost + at(j < len ? p0 + j * dp : p_last));
     uint32_t L[NP];
 #pragma unroll
     for (int r = 0; r < NP; ++r) L[r] = 0u;
@@ -544,14 +580,14 @@ __device__ inline void packed_scanline_full(const SgmLaunch& a, const Scan& sc, 
         uint32_t c[NP];
         unpack_costs<NP>(w, c);
         packed_update<G, NP>(L, c, m, p1pk, p2);
-        *reinterpret_cast<Word*>(vol + at(p)) = pack_costs<NP>(L);
+        *reinterpret_cast<gmem<Word>*>(vol + at(p)) = pack_costs<NP>(L);
     };
     int i = 0;
     for (; i + PF <= len; i += PF) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
             step(ring[u]);
-            ring[u] = *reinterpret_cast<const Word*>(cost + at((i + u + PF < len) ? p + PF * dp : p_last));
+            ring[u] = *reinterpret_cast<const gmem<Word>*>(cost + at((i + u + PF < len) ? p + PF * dp : p_last));
             p += dp;
         }
     }
@@ -575,8 +611,8 @@ template <int G, int NP, int PF>
 __device__ inline void packed_scanline_windowed(const SgmLaunch& a, const Scan& sc, int lane) {
     constexpr int RM = 2 * PF;
     constexpr int S = 2 * NP;      // slots per lane
-    const uint8_t* __restrict__ cost = a.cost;
-    uint8_t* __restrict__ vol = a.vol + (size_t)sc.dir * a.vol_stride;
+    const gmem<uint8_t>* __restrict__ cost = gptr(a.cost);
+    gmem<uint8_t>* __restrict__ vol = gptr(a.vol + (size_t)sc.dir * a.vol_stride);
     const int dp = sc.dp, len = sc.len, p0 = sc.p0;
     const int p_last = p0 + (len - 1) * dp;
     const uint32_t p1pk = (uint32_t)a.p1 * 0x10001u;
@@ -587,7 +623,7 @@ __device__ inline void packed_scanline_windowed(const SgmLaunch& a, const Scan& 
     uint32_t moff[RM];
     auto load_meta = [&](int j, int pix) {
         int hi;
-        window_of<false>(a.win, pix, mlo[j], hi, moff[j]);
+        window_of<kWinRagged>(a.win, pix, mlo[j], hi, moff[j]);
         mw[j] = hi - mlo[j] + 1;
     };
     auto load_bytes = [&](int j, uint32_t (&b)[S]) {
@@ -648,7 +684,7 @@ __device__ inline void packed_scanline_windowed(const SgmLaunch& a, const Scan& 
 
 // ---- kernels ----
 // Generic: every scanline through LDS rows (any D; ragged or full windows).
-template <int G, int K, bool FULL, int PF>
+template <int G, int K, int WM, int PF>
 __global__ __launch_bounds__(kBlock) void sgm_paths_lds_kernel(SgmLaunch a, int n_tasks) {
     constexpr int GPB = kBlock / G;
     __shared__ uint16_t lds[GPB][2][G * K + 2];
@@ -656,7 +692,7 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_lds_kernel(SgmLaunch a, int 
     const int task = blockIdx.x * GPB + grp;
     if (task >= n_tasks) return;
     const Scan sc = scan_of(task, a.w, a.h);
-    lds_scanline<G, K, FULL, PF>(a, sc, lane, lds[grp][0], lds[grp][1]);
+    lds_scanline<G, K, WM, PF>(a, sc, lane, lds[grp][0], lds[grp][1]);
 }
 
 // Full range, D = 2*NP*G: every scanline on packed registers.
@@ -690,12 +726,12 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_ragged_kernel(SgmLaunch a, i
         const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
         const int task = n_packed_tasks + (blockIdx.x - n_packed_blocks) * GPB + grp;
         if (task >= n_tasks) return;
-        lds_scanline<GL, K, false, PF>(a, scan_of(task, a.w, a.h), lane, lds[grp][0], lds[grp][1]);
+        lds_scanline<GL, K, kWinRagged, PF>(a, scan_of(task, a.w, a.h), lane, lds[grp][0], lds[grp][1]);
     }
 }
 
 // ------------------------------------------------------------------ selection
-__device__ inline int sum_paths(const uint8_t* __restrict__ vol, size_t stride, uint32_t j) {
+__device__ inline int sum_paths(const gmem<uint8_t>* __restrict__ vol, size_t stride, uint32_t j) {
     int s = 0;
 #pragma unroll
     for (int r = 0; r < kNumPaths; ++r) s += vol[(size_t)r * stride + j];
@@ -709,19 +745,19 @@ __device__ inline int sum_paths(const uint8_t* __restrict__ vol, size_t stride, 
 // then one global atomicMin per touched right pixel.  The pixel's S row is
 // kept in LDS for the parabola and the uncertainty walk.  Results before the
 // left-right check go to disp_wta / disp_sub / var_meas.
-template <int G, int K, bool FULL>
-__global__ __launch_bounds__(kBlock) void sgm_select_kernel(SgmLaunch a) {
+template <int G, int K, int WM>
+__device__ inline void select_segment(const SgmLaunch& a, int seg, int y) {
     constexpr int GPB = kBlock / G;
     __shared__ uint32_t keyR[kSeg + kMaxDisp];
     __shared__ uint16_t sS_all[GPB][G * K];
     const int W = a.w, D = a.win.max_disp;
-    const int y = blockIdx.y, x0 = blockIdx.x * kSeg;
+    const int x0 = seg * kSeg;
     const int base = x0 - (D - 1);
     const int grp = threadIdx.x / G, lane = threadIdx.x % G;
     uint16_t* sS = sS_all[grp];
     for (int i = threadIdx.x; i < kSeg + D - 1; i += kBlock) keyR[i] = 0xffffffffu;
     __syncthreads();
-    const uint8_t* __restrict__ vol = a.vol;
+    const gmem<uint8_t>* __restrict__ vol = gptr(a.vol);
     const size_t stride = a.vol_stride;
     for (int i = grp; i < kSeg; i += GPB) {
         const int x = x0 + i;
@@ -729,7 +765,7 @@ __global__ __launch_bounds__(kBlock) void sgm_select_kernel(SgmLaunch a) {
         const int p = y * W + x;
         int lo, hi;
         uint32_t off;
-        window_of<FULL>(a.win, p, lo, hi, off);
+        window_of<WM>(a.win, p, lo, hi, off);
         const int w = hi - lo + 1;
         int kbest = 0x7fffffff;
 #pragma unroll
@@ -741,7 +777,7 @@ __global__ __launch_bounds__(kBlock) void sgm_select_kernel(SgmLaunch a) {
                 const int key = (S << 9) | d;
                 kbest = min(kbest, key);
                 sS[s] = (uint16_t)S;
-                if (a.agg) a.agg[off + (uint32_t)s] = (uint16_t)S;
+                if (a.agg) gptr(a.agg)[off + (uint32_t)s] = (uint16_t)S;
                 if (x - d >= 0) atomicMin(&keyR[i + (D - 1) - d], (uint32_t)key);
             }
         }
@@ -768,10 +804,10 @@ __global__ __launch_bounds__(kBlock) void sgm_select_kernel(SgmLaunch a) {
                 if (acc >= a.s_max) break;
                 ++n;
             }
-            a.disp_wta[p] = (int16_t)ds;
-            a.disp_sub[p] = sub;
-            a.var_meas[p] = (float)n;
-            if (a.wta_raw) a.wta_raw[p] = (int16_t)ds;
+            gptr(a.disp_wta)[p] = (int16_t)ds;
+            gptr(a.disp_sub)[p] = sub;
+            gptr(a.var_meas)[p] = (float)n;
+            if (a.wta_raw) gptr(a.wta_raw)[p] = (int16_t)ds;
         }
         lds_order();
     }
@@ -779,39 +815,125 @@ __global__ __launch_bounds__(kBlock) void sgm_select_kernel(SgmLaunch a) {
     for (int i = threadIdx.x; i < kSeg + D - 1; i += kBlock) {
         const int xr = base + i;
         const uint32_t k = keyR[i];
-        if (xr >= 0 && xr < W && k != 0xffffffffu) atomicMin(&a.key_r[(size_t)y * W + xr], k);
+        if (xr >= 0 && xr < W && k != 0xffffffffu)
+            __hip_atomic_fetch_min(gptr(a.key_r) + (size_t)y * W + xr, k, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
+template <int G, int K, int WM>
+__global__ __launch_bounds__(kBlock) void sgm_select_kernel(SgmLaunch a) {
+    select_segment<G, K, WM>(a, blockIdx.x, blockIdx.y);
+}
+
 // Right map and left-right check (in place on the selection's outputs).
-__global__ __launch_bounds__(kBlock) void sgm_lr_kernel(SgmLaunch a) {
-    const int p = blockIdx.x * kBlock + threadIdx.x;
-    if (p >= a.w * a.h) return;
-    const uint32_t kr = a.key_r[p];
-    if (a.disp_right) a.disp_right[p] = kr == 0xffffffffu ? (int16_t)-1 : (int16_t)(kr & 511u);
+__device__ inline void lr_pixel(const SgmLaunch& a, int p) {
+    const gmem<uint32_t>* key_r = gptr(a.key_r);
+    const uint32_t kr = key_r[p];
+    if (a.disp_right) gptr(a.disp_right)[p] = kr == 0xffffffffu ? (int16_t)-1 : (int16_t)(kr & 511u);
     if (a.lr_tol < 0) return;
     const int x = p % a.w;
-    const int ds = a.disp_wta[p];
+    const int ds = gptr(a.disp_wta)[p];
     bool ok = false;
     if (x - ds >= 0) {
-        const uint32_t k2 = a.key_r[p - ds];
+        const uint32_t k2 = key_r[p - ds];
         if (k2 != 0xffffffffu) ok = abs(ds - (int)(k2 & 511u)) <= a.lr_tol;
     }
     if (!ok) {
-        a.disp_wta[p] = -1;
-        a.disp_sub[p] = -1.0f;
-        a.var_meas[p] = 0.0f;
+        gptr(a.disp_wta)[p] = -1;
+        gptr(a.disp_sub)[p] = -1.0f;
+        gptr(a.var_meas)[p] = 0.0f;
     }
+}
+
+__global__ __launch_bounds__(kBlock) void sgm_lr_kernel(SgmLaunch a) {
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p < a.w * a.h) lr_pixel(a, p);
 }
 
 // Copies the first n bytes of a ragged volume, n = w*h*D for the full range
 // or offsets[w*h] (read on the device) otherwise.
-template <bool FULL>
+template <int WM>
 __global__ __launch_bounds__(kBlock) void copy_slots_kernel(SgmLaunch a, const uint8_t* src,
                                                             uint8_t* dst) {
-    const size_t n = FULL ? (size_t)a.w * a.h * a.win.max_disp : (size_t)a.win.off[a.w * a.h];
+    const size_t n = WM == kWinFull ? (size_t)a.w * a.h * a.win.max_disp : (size_t)a.win.off[a.w * a.h];
     for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
         dst[i] = src[i];
+}
+
+// ------------------------------------------------------------------ batched launches
+// Many stereo pairs (any sizes, full or ragged windows, own D) in one launch
+// per stage.  Each stage maps its blocks (or, for the paths, its scanline
+// tasks) to (pair, local index) through prefix tables; scanline tasks are
+// ordered rows, then columns, then diagonals across all pairs, so the
+// longest chains start first.
+__device__ inline int last_leq(const int* __restrict__ prefix, int n, int v) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= v) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline const SgmLaunch& pair_of(const BatchTables& t, int i) {
+    return t.pairs[i];
+}
+
+__global__ __launch_bounds__(kBlock) void census_batch_kernel(BatchTables t) {
+    const int i = last_leq(t.census_prefix, t.n, (int)blockIdx.x);
+    const SgmLaunch a = pair_of(t, i);
+    const int local = (int)blockIdx.x - t.census_prefix[i];
+    const int tiles_x = (a.w + kCtW - 1) / kCtW;
+    const int tx = local % tiles_x, ty = local / tiles_x;
+    if (blockIdx.z == 0)
+        census_tile(a.left, a.w, a.h, a.pitch, const_cast<uint64_t*>(a.census_l), a.key_r, tx, ty);
+    else
+        census_tile(a.right, a.w, a.h, a.pitch, const_cast<uint64_t*>(a.census_r), nullptr, tx, ty);
+}
+
+__global__ __launch_bounds__(kBlock) void cost_batch_kernel(BatchTables t) {
+    const int i = last_leq(t.seg_prefix, t.n, (int)blockIdx.x);
+    const SgmLaunch a = pair_of(t, i);
+    const int local = (int)blockIdx.x - t.seg_prefix[i];
+    const int segs_x = (a.w + kSeg - 1) / kSeg;
+    cost_segment<16, kWinAny>(a, local % segs_x, local / segs_x);
+}
+
+// Task ranges start at multiples of 4 (padded with idle tasks), so the
+// lane groups of one wave always belong to the same pair and the pair's
+// descriptor stays wave-uniform for any G.
+template <int G, int K, int PF>
+__global__ __launch_bounds__(kBlock) void paths_batch_kernel(BatchTables t) {
+    constexpr int GPB = kBlock / G;
+    __shared__ uint16_t lds[GPB][2][G * K + 2];
+    const int grp = threadIdx.x / G, lane = threadIdx.x % G;
+    const int task = (int)blockIdx.x * GPB + grp;
+    if (task >= t.n_tasks) return;
+    const int wave_task = __builtin_amdgcn_readfirstlane(task);
+    const int r = __builtin_amdgcn_readfirstlane(last_leq(t.task_start, t.n_ranges, wave_task));
+    const int i = __builtin_amdgcn_readfirstlane(t.task_pair[r]);
+    const int rel = task - t.task_start[r];
+    if (rel >= t.task_count[r]) return;                 // padding
+    const SgmLaunch a = pair_of(t, i);
+    lds_scanline<G, K, kWinAny, PF>(a, scan_of(t.task_local[r] + rel, a.w, a.h), lane, lds[grp][0],
+                                    lds[grp][1]);
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void select_batch_kernel(BatchTables t) {
+    const int i = last_leq(t.seg_prefix, t.n, (int)blockIdx.x);
+    const SgmLaunch a = pair_of(t, i);
+    const int local = (int)blockIdx.x - t.seg_prefix[i];
+    const int segs_x = (a.w + kSeg - 1) / kSeg;
+    select_segment<16, K, kWinAny>(a, local % segs_x, local / segs_x);
+}
+
+__global__ __launch_bounds__(kBlock) void lr_batch_kernel(BatchTables t) {
+    const int g = (int)blockIdx.x * kBlock + (int)threadIdx.x;
+    if (g >= t.pix_prefix[t.n]) return;
+    const int i = last_leq(t.pix_prefix, t.n, g);
+    lr_pixel(pair_of(t, i), g - t.pix_prefix[i]);
 }
 
 // ------------------------------------------------------------------ warp
@@ -982,9 +1104,9 @@ hipError_t launch_census_pair(const uint8_t* left, const uint8_t* right, int w, 
 hipError_t launch_sgm_cost(const SgmLaunch& a, hipStream_t s) {
     dim3 grid((a.w + kSeg - 1) / kSeg, a.h);
     if (a.win.lo == nullptr)
-        cost_kernel<64, true><<<grid, kBlock, 0, s>>>(a);
+        cost_kernel<64, kWinFull><<<grid, kBlock, 0, s>>>(a);
     else
-        cost_kernel<16, false><<<grid, kBlock, 0, s>>>(a);
+        cost_kernel<16, kWinRagged><<<grid, kBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -999,7 +1121,7 @@ hipError_t launch_sgm_paths(const SgmLaunch& a, hipStream_t s) {
 #define EGOSGM_FULL(GG, NN) \
     sgm_paths_full_kernel<GG, NN, 8><<<blocks(n_tasks, GG), kBlock, 0, s>>>(a, n_tasks)
 #define EGOSGM_LDSF(GG, KK) \
-    sgm_paths_lds_kernel<GG, KK, true, 4><<<blocks(n_tasks, GG), kBlock, 0, s>>>(a, n_tasks)
+    sgm_paths_lds_kernel<GG, KK, kWinFull, 4><<<blocks(n_tasks, GG), kBlock, 0, s>>>(a, n_tasks)
         if (D == 64) {
             if (g == 32) EGOSGM_FULL(32, 1); else EGOSGM_FULL(16, 2);
         } else if (D == 128) {
@@ -1047,14 +1169,14 @@ hipError_t launch_sgm_select(const SgmLaunch& a, hipStream_t s) {
     dim3 grid((a.w + kSeg - 1) / kSeg, a.h);
 #define EGOSGM_SEL(GG, KK, FF) sgm_select_kernel<GG, KK, FF><<<grid, kBlock, 0, s>>>(a)
     if (full) {
-        if (D <= 64) EGOSGM_SEL(64, 1, true);
-        else if (D <= 128) EGOSGM_SEL(64, 2, true);
-        else EGOSGM_SEL(64, 4, true);
+        if (D <= 64) EGOSGM_SEL(64, 1, kWinFull);
+        else if (D <= 128) EGOSGM_SEL(64, 2, kWinFull);
+        else EGOSGM_SEL(64, 4, kWinFull);
     } else {
-        if (D <= 16) EGOSGM_SEL(16, 1, false);
-        else if (D <= 64) EGOSGM_SEL(16, 4, false);
-        else if (D <= 128) EGOSGM_SEL(16, 8, false);
-        else EGOSGM_SEL(16, 16, false);
+        if (D <= 16) EGOSGM_SEL(16, 1, kWinRagged);
+        else if (D <= 64) EGOSGM_SEL(16, 4, kWinRagged);
+        else if (D <= 128) EGOSGM_SEL(16, 8, kWinRagged);
+        else EGOSGM_SEL(16, 16, kWinRagged);
     }
 #undef EGOSGM_SEL
     hipError_t e = hipGetLastError();
@@ -1065,9 +1187,9 @@ hipError_t launch_sgm_select(const SgmLaunch& a, hipStream_t s) {
 
 hipError_t launch_copy_slots(const SgmLaunch& a, const uint8_t* src, uint8_t* dst, hipStream_t s) {
     if (a.win.lo == nullptr)
-        copy_slots_kernel<true><<<1024, kBlock, 0, s>>>(a, src, dst);
+        copy_slots_kernel<kWinFull><<<1024, kBlock, 0, s>>>(a, src, dst);
     else
-        copy_slots_kernel<false><<<1024, kBlock, 0, s>>>(a, src, dst);
+        copy_slots_kernel<kWinRagged><<<1024, kBlock, 0, s>>>(a, src, dst);
     return hipGetLastError();
 }
 
@@ -1080,6 +1202,50 @@ hipError_t launch_windows(const float* d_pred, const float* p_pred, int w, int h
     if (e != hipSuccess) return e;
     windows_offset_kernel<<<h, kBlock, 0, s>>>(w, h, off, row_tot);
     return hipGetLastError();
+}
+
+hipError_t launch_batch_stage(const BatchTables& t, int max_disp, int stage, hipStream_t s) {
+    switch (stage) {
+        case 0:
+            census_batch_kernel<<<dim3(t.host_census_blocks, 1, 2), kBlock, 0, s>>>(t);
+            break;
+        case 1:
+            cost_batch_kernel<<<t.host_seg_blocks, kBlock, 0, s>>>(t);
+            break;
+        case 2: {
+            const int g = t.group;
+            const unsigned pb = (unsigned)((t.n_tasks + kBlock / g - 1) / (kBlock / g));
+#define EGOSGM_PB(GG)                                                                   \
+    do {                                                                                \
+        if (max_disp <= 64) paths_batch_kernel<GG, 64 / GG, 4><<<pb, kBlock, 0, s>>>(t);   \
+        else if (max_disp <= 128) paths_batch_kernel<GG, 128 / GG, 4><<<pb, kBlock, 0, s>>>(t); \
+        else paths_batch_kernel<GG, 256 / GG, 4><<<pb, kBlock, 0, s>>>(t);                 \
+    } while (0)
+            if (g == 16) EGOSGM_PB(16);
+            else if (g == 32) EGOSGM_PB(32);
+            else EGOSGM_PB(64);
+#undef EGOSGM_PB
+            break;
+        }
+        case 3:
+            if (max_disp <= 16) select_batch_kernel<1><<<t.host_seg_blocks, kBlock, 0, s>>>(t);
+            else if (max_disp <= 64) select_batch_kernel<4><<<t.host_seg_blocks, kBlock, 0, s>>>(t);
+            else if (max_disp <= 128) select_batch_kernel<8><<<t.host_seg_blocks, kBlock, 0, s>>>(t);
+            else select_batch_kernel<16><<<t.host_seg_blocks, kBlock, 0, s>>>(t);
+            break;
+        default:
+            lr_batch_kernel<<<grid_for((size_t)t.host_pixels), kBlock, 0, s>>>(t);
+            break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sgm_batch(const BatchTables& t, int max_disp, hipStream_t s) {
+    for (int stage = 0; stage < 5; ++stage) {
+        const hipError_t e = launch_batch_stage(t, max_disp, stage, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_warp(const float* d_prev, const float* p_prev, int w, int h, const float* H,

@@ -37,13 +37,19 @@ _SIGS = {
     "kalman_update": ([_vp, _vp, _vp, _vp, _i, _i, _vp, _vp, _vp], _i),
     "egosgm_refine_workspace_bytes": ([_i, _i], _sz),
     "refine_prediction": ([_vp, _vp, _i, _i, _f, _f, _vp, _vp, _vp, _sz, _vp], _i),
+    "egosgm_plan_workspace_bytes": ([_vp, _i], _sz),
+    "sgm_plan_create": ([_vp, _i, _vp, _vp, _sz, _vp], _i),
+    "sgm_plan_run": ([_vp, _vp], _i),
+    "sgm_plan_run_eager": ([_vp, _vp], _i),
+    "sgm_plan_destroy": ([_vp], _i),
     "egosgm_set_tuning": ([_vp], _i),
     "egosgm_get_tuning": ([_vp], _i),
     "egosgm_timing_enable": ([_i], _i),
     "egosgm_timing_read": ([_vp, _vp, _i], _i),
 }
 
-STAGES = ("census", "windows", "cost", "paths", "select", "warp", "kalman", "refine")
+STAGES = ("census", "windows", "cost", "paths", "select", "warp", "kalman", "refine",
+          "batch_census", "batch_cost", "batch_paths", "batch_select")
 
 
 def lib():
@@ -84,14 +90,18 @@ class SgmDebug(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("full_group", C.c_int32), ("ragged_group", C.c_int32),
-                ("ragged_schedule", C.c_int32)]
+                ("ragged_schedule", C.c_int32), ("batch_group", C.c_int32)]
 
 
-DEFAULT_TUNING = dict(full_group=64, ragged_group=64, ragged_schedule=0)
+DEFAULT_TUNING = dict(full_group=64, ragged_group=64, ragged_schedule=0, batch_group=16)
 
 
-def set_tuning(full_group: int = 64, ragged_group: int = 64, ragged_schedule: int = 0):
-    t = Tuning(full_group, ragged_group, ragged_schedule)
+def set_tuning(full_group: int = 64, ragged_group: int = 64, ragged_schedule: int = 0,
+               batch_group: int | None = None):
+    """Sets the launch shapes; batch_group None keeps the current one."""
+    if batch_group is None:
+        batch_group = get_tuning()["batch_group"] if _lib is not None else 16
+    t = Tuning(full_group, ragged_group, ragged_schedule, batch_group)
     _check(lib().egosgm_set_tuning(C.byref(t)), "egosgm_set_tuning")
 
 
@@ -99,7 +109,7 @@ def get_tuning() -> dict:
     t = Tuning()
     _check(lib().egosgm_get_tuning(C.byref(t)), "egosgm_get_tuning")
     return dict(full_group=t.full_group, ragged_group=t.ragged_group,
-                ragged_schedule=t.ragged_schedule)
+                ragged_schedule=t.ragged_schedule, batch_group=t.batch_group)
 
 
 @dataclass
@@ -358,3 +368,75 @@ def timing_read() -> dict:
     cnt = (C.c_int * len(STAGES))()
     _check(lib().egosgm_timing_read(ms, cnt, len(STAGES)), "egosgm_timing_read")
     return {s: (ms[i], cnt[i]) for i, s in enumerate(STAGES)}
+
+
+# ------------------------------------------------------------------ batches
+class PairDesc(C.Structure):
+    _fields_ = [("left", _vp), ("right", _vp), ("w", C.c_int32), ("h", C.c_int32),
+                ("pitch", C.c_int32), ("max_disp", C.c_int32), ("lo", _vp), ("hi", _vp),
+                ("offsets", _vp), ("disp_wta", _vp), ("disp_sub", _vp), ("var_meas", _vp),
+                ("disp_right", _vp)]
+
+
+class Plan:
+    """Batched matching of many pairs in one captured graph.
+
+    pairs: list of dicts with left, right (uint8 GPU tensors), max_disp and
+    optional windows=(lo, hi, offsets) (else full range).  Outputs are
+    allocated per pair (plan.outputs[i]) unless given as out=dict.  Every
+    tensor is referenced by the plan so its address stays fixed; windows may
+    be rewritten in place between runs."""
+
+    def __init__(self, pairs, params: MatchParams | None = None, device=None):
+        params = params or MatchParams()
+        self._keep = []
+        self.outputs = []
+        descs = (PairDesc * len(pairs))()
+        for i, q in enumerate(pairs):
+            L, R = q["left"], q["right"]
+            _need(L, torch.uint8, name="left")
+            _need(R, torch.uint8, name="right")
+            h, w = L.shape
+            D = int(q.get("max_disp", params.max_disp))
+            win = q.get("windows")
+            o = q.get("out") or _outputs(h, w, L.device)
+            lo = hi = off = None
+            if win is not None:
+                lo, hi, off = win
+                _need(lo, torch.int16, h * w, "lo")
+                _need(hi, torch.int16, h * w, "hi")
+                _need(off, torch.int32, h * w + 1, "offsets")
+            descs[i] = PairDesc(_ptr(L), _ptr(R), w, h, w, D, _ptr(lo), _ptr(hi), _ptr(off),
+                                _ptr(o["disp_wta"]), _ptr(o["disp_sub"]), _ptr(o["var_meas"]),
+                                _ptr(o.get("disp_right")))
+            self._keep += [L, R, lo, hi, off]
+            self.outputs.append(o)
+        self.n = len(pairs)
+        nbytes = lib().egosgm_plan_workspace_bytes(descs, self.n)
+        if nbytes == 0:
+            raise EgoSgmError("plan workspace: invalid pair descriptors")
+        dev = device or pairs[0]["left"].device
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        prm = params.c()
+        self._plan = _vp()
+        torch.cuda.synchronize(dev)
+        _check(lib().sgm_plan_create(descs, self.n, C.byref(prm), _ptr(self.workspace), nbytes,
+                                     C.byref(self._plan)), "sgm_plan_create")
+        self._descs = descs
+
+    def run(self, eager: bool = False):
+        if eager:
+            _check(lib().sgm_plan_run_eager(self._plan, _stream()), "sgm_plan_run_eager")
+        else:
+            _check(lib().sgm_plan_run(self._plan, _stream()), "sgm_plan_run")
+
+    def close(self):
+        if getattr(self, "_plan", None):
+            lib().sgm_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -81,29 +81,52 @@ class StreamState:
         """Drop the prediction: the next frame searches the full range."""
         self.frame = 0
 
-    def step(self, left: torch.Tensor, right: torch.Tensor, R=None, t=None):
-        """Processes one stereo frame; R, t map the previous camera frame to
-        this one (M_k = R M_{k-1} + t).  Returns the updated (d, p) maps."""
+    def full_range_next(self) -> bool:
+        return self.frame == 0 or self.cfg.full_range_only
+
+    def predict(self, R=None, t=None):
+        """First half of a frame: warp, refine and windows (Sec. 2.2-2.3).
+        Returns (lo, hi, offsets) for this frame, or None when it is matched
+        over the full range."""
+        if self.full_range_next():
+            return None
         cfg, c = self.cfg, self.calib
-        prm = cfg.match()
-        if self.frame == 0 or cfg.full_range_only:
+        eg.warp_disparity(self.d, self.p, R, t, c.f, c.cx, c.cy, c.baseline, cfg.q,
+                          out=(self.d_warp, self.p_warp), zbuf=self.zbuf)
+        eg.refine_prediction(self.d_warp, self.p_warp, cfg.edge_tol, cfg.fill_tol,
+                             out=(self.d_pred, self.p_pred), workspace=self.ws)
+        eg.windows_from_prediction(self.d_pred, self.p_pred, cfg.max_disp, cfg.r_fixed,
+                                   cfg.r_min, cfg.r_max, cfg.k_sigma,
+                                   out=(self.lo, self.hi, self.off), workspace=self.ws)
+        return self.lo, self.hi, self.off
+
+    def match(self, left: torch.Tensor, right: torch.Tensor, windows):
+        """Stereo matching of this frame into self.out (Sec. 2.3)."""
+        prm = self.cfg.match()
+        if windows is None:
             eg.sgm_full(left, right, prm, out=self.out, workspace=self.ws)
+        else:
+            eg.sgm_reduced(left, right, *windows, prm, out=self.out, workspace=self.ws)
+
+    def update(self):
+        """Second half: the Kalman update of the prediction with self.out
+        (Sec. 2.4); the first frame takes the measurement as it is."""
+        cfg = self.cfg
+        if self.full_range_next():
             eg.kalman_update(self.invalid, self.zeros, self.out["disp_sub"], self.out["var_meas"],
                              cfg.keep_unmeasured, out=(self.d, self.p))
         else:
-            eg.warp_disparity(self.d, self.p, R, t, c.f, c.cx, c.cy, c.baseline, cfg.q,
-                              out=(self.d_warp, self.p_warp), zbuf=self.zbuf)
-            eg.refine_prediction(self.d_warp, self.p_warp, cfg.edge_tol, cfg.fill_tol,
-                                 out=(self.d_pred, self.p_pred), workspace=self.ws)
-            eg.windows_from_prediction(self.d_pred, self.p_pred, cfg.max_disp, cfg.r_fixed,
-                                       cfg.r_min, cfg.r_max, cfg.k_sigma,
-                                       out=(self.lo, self.hi, self.off), workspace=self.ws)
-            eg.sgm_reduced(left, right, self.lo, self.hi, self.off, prm, out=self.out,
-                           workspace=self.ws)
-            eg.kalman_update(self.d_pred, self.p_pred, self.out["disp_sub"],
-                             self.out["var_meas"], cfg.keep_unmeasured, out=(self.d, self.p))
+            eg.kalman_update(self.d_pred, self.p_pred, self.out["disp_sub"], self.out["var_meas"],
+                             cfg.keep_unmeasured, out=(self.d, self.p))
         self.frame += 1
         return self.d, self.p
+
+    def step(self, left: torch.Tensor, right: torch.Tensor, R=None, t=None):
+        """Processes one stereo frame; R, t map the previous camera frame to
+        this one (M_k = R M_{k-1} + t).  Returns the updated (d, p) maps."""
+        win = self.predict(R, t)
+        self.match(left, right, win)
+        return self.update()
 
     def searched_slots(self) -> int:
         """Disparities searched by the last reduced frame (synchronises)."""

@@ -112,11 +112,31 @@ def test_tuning_validation():
     import ctypes as C
     lib = eg.lib()
     before = eg.get_tuning()
-    bad = eg.Tuning(24, 32, 1)
+    bad = eg.Tuning(24, 32, 1, 16)
     assert lib.egosgm_set_tuning(C.byref(bad)) == -1
     assert lib.egosgm_set_tuning(None) == -1
     assert eg.get_tuning() == before
-    assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, 3))) == -1
-    eg.set_tuning(16, 64, 0)
-    assert eg.get_tuning() == dict(full_group=16, ragged_group=64, ragged_schedule=0)
+    assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, 3, 16))) == -1
+    assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, 0, 8))) == -1
+    eg.set_tuning(16, 64, 0, 32)
+    assert eg.get_tuning() == dict(full_group=16, ragged_group=64, ragged_schedule=0, batch_group=32)
     eg.set_tuning(**before)
+
+
+def test_plan_validation():
+    import ctypes as C
+    lib = eg.lib()
+    P = (eg.PairDesc * 1)()
+    assert lib.egosgm_plan_workspace_bytes(P, 1) == 0           # null pointers
+    P[0] = eg.PairDesc(FAKE, FAKE, 64, 32, 64, 128, None, None, None, FAKE, FAKE, FAKE, None)
+    n = lib.egosgm_plan_workspace_bytes(P, 1)
+    assert n >= lib.egosgm_sgm_workspace_bytes(64, 32, 128)
+    P[0].lo = FAKE                                               # lo without hi/offsets
+    assert lib.egosgm_plan_workspace_bytes(P, 1) == 0
+    out = C.c_void_p()
+    prm = _prm()
+    P[0].lo = None
+    assert lib.sgm_plan_create(P, 1, C.byref(prm), FAKE, 16, C.byref(out)) == -2
+    assert lib.sgm_plan_create(P, 0, C.byref(prm), FAKE, n, C.byref(out)) == -1
+    assert lib.sgm_plan_run(None, None) == -1
+    assert lib.sgm_plan_destroy(None) == 0

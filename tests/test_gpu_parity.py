@@ -266,3 +266,89 @@ def test_tuning_never_changes_results(D):
             assert np.array_equal(_np(b["disp_right"]), o_red["disp_right"]), (fg, rg, pr)
     finally:
         eg.set_tuning(**eg.DEFAULT_TUNING)
+
+
+# ---------------------------------------------------------------- batches
+def _batch_cases():
+    specs = [(37, 19, 16, False), (64, 20, 64, True), (91, 27, 128, True), (45, 30, 100, False),
+             (70, 23, 128, True), (130, 9, 256, True), (33, 41, 48, False)]
+    cases = []
+    for i, (w, h, D, ragged) in enumerate(specs):
+        left, right = _random_pair(w, h, seed=300 + i, max_shift=min(D - 1, 30))
+        win = None
+        if ragged:
+            d, p = _random_windows(w, h, D, seed=400 + i, frac_full=0.12)
+            wo = orc.windows(d, p, D, r_min=0, r_max=12)
+            win = (_gpu(wo[0].reshape(h, w)), _gpu(wo[1].reshape(h, w)), _gpu(wo[2].view(np.int32)))
+        cases.append(dict(left=_gpu(left), right=_gpu(right), max_disp=D, windows=win))
+    return cases
+
+
+def _single(case, prm):
+    p = eg.MatchParams(case["max_disp"], prm.p1, prm.p2, prm.s_max, prm.lr_tol)
+    if case["windows"] is None:
+        return eg.sgm_full(case["left"], case["right"], p)
+    return eg.sgm_reduced(case["left"], case["right"], *case["windows"], p)
+
+
+def _same(a, b):
+    for k in ("disp_wta", "disp_sub", "var_meas", "disp_right"):
+        if not torch.equal(a[k], b[k]):
+            return k
+    return None
+
+
+@pytest.mark.parametrize("group", [16, 32, 64])
+def test_plan_matches_single_pairs(group):
+    _say("plan of 7 mixed pairs, lanes per scanline", group)
+    cases = _batch_cases()
+    prm = eg.MatchParams(max_disp=256, p1=9, p2=110, s_max=70, lr_tol=1)
+    eg.set_tuning(**{**eg.DEFAULT_TUNING, "batch_group": group})
+    try:
+        plan = eg.Plan(cases, prm)
+    finally:
+        eg.set_tuning(**eg.DEFAULT_TUNING)
+    plan.run()
+    torch.cuda.synchronize()
+    for i, c in enumerate(cases):
+        ref = _single(c, prm)
+        torch.cuda.synchronize()
+        assert _same(plan.outputs[i], ref) is None, (i, _same(plan.outputs[i], ref))
+    # one pair also against the oracle
+    c = cases[2]
+    h, w = c["left"].shape
+    wo = tuple(t.cpu().numpy().ravel() for t in c["windows"][:2]) + (c["windows"][2].cpu().numpy().view(np.uint32),)
+    o = orc.sgm(c["left"].cpu().numpy(), c["right"].cpu().numpy(), 128, 9, 110, 70, 1, windows=wo)
+    assert np.array_equal(_np(plan.outputs[2]["disp_wta"]), o["disp_wta"])
+    plan.close()
+
+
+def test_plan_graph_replays_and_window_updates():
+    _say("plan replays")
+    cases = _batch_cases()[:4]
+    prm = eg.MatchParams()
+    plan = eg.Plan(cases, prm)
+    refs = [_single(c, prm) for c in cases]
+    for rep in range(3):
+        for o in plan.outputs:
+            for t in o.values():
+                t.fill_(7)
+        plan.run()
+        x = torch.randn(1000, device=DEV).sum()   # eager work between replays
+        torch.cuda.synchronize()
+        for i in range(len(cases)):
+            assert _same(plan.outputs[i], refs[i]) is None, (rep, i)
+    # rewrite the ragged windows in place and replay
+    c = cases[1]
+    h, w = c["left"].shape
+    d, p = _random_windows(w, h, 64, seed=999, frac_full=0.3)
+    wo = orc.windows(d, p, 64, r_min=0, r_max=6)
+    c["windows"][0].copy_(_gpu(wo[0].reshape(h, w)))
+    c["windows"][1].copy_(_gpu(wo[1].reshape(h, w)))
+    c["windows"][2].copy_(_gpu(wo[2].view(np.int32)))
+    plan.run()
+    ref = _single(c, prm)
+    torch.cuda.synchronize()
+    assert _same(plan.outputs[1], ref) is None
+    del x
+    plan.close()
