@@ -265,6 +265,29 @@ int sgm_plan_run(egosgm_plan* plan, void* stream);
 /* The same kernels launched one by one on `stream` (no graph), each stage
  * bracketed by the timing events when timing is enabled. */
 int sgm_plan_run_eager(egosgm_plan* plan, void* stream);
+/* Changes of one pair of a plan for its next runs (continuous batching over
+ * camera streams, Sec. 2: each stream's frame k is matched inside the
+ * windows of its own prediction, its first frame over the full range).
+ * index: the pair in the plan; active: 0 skips the pair in later runs
+ * (its outputs are left as they are); left/right: the pair's images, same
+ * shape and pitch as at creation; lo/hi/offsets: new windows as in
+ * sgm_reduced, or all three NULL for the full range. */
+typedef struct egosgm_pair_update {
+    int32_t index;
+    int32_t active;
+    const uint8_t* left;
+    const uint8_t* right;
+    const int16_t* lo;
+    const int16_t* hi;
+    const uint32_t* offsets;
+} egosgm_pair_update;
+
+/* Enqueues the changes upd[0..n-1] (host array, read before return) on
+ * `stream` as a small kernel, so they apply to the plan's runs enqueued
+ * after it on that stream (and are safe inside a captured graph).  The
+ * pointers must stay valid until those runs end.  EINVAL: bad index,
+ * NULL image, or windows given only in part (nothing is enqueued). */
+int sgm_plan_update(egosgm_plan* plan, const egosgm_pair_update* upd, int n, void* stream);
 /* Frees the plan (not the buffers).  NULL is accepted. */
 int sgm_plan_destroy(egosgm_plan* plan);
 
@@ -278,7 +301,9 @@ typedef struct egosgm_tuning {
     int32_t ragged_schedule; /* 0: every scanline through LDS (work follows the windows);
                                 1: the image rows (the longest scanlines) on packed registers
                                    over all disparities, the rest through LDS;
-                                2: every scanline on packed registers                        */
+                                2: every scanline on packed registers;
+                                3: every scanline on registers over its window, one wave
+                                   per scanline (window-start moves by lane permutes)        */
     int32_t batch_group;     /* lanes per scanline in batched plans (fixed when a plan is
                                 created): 16, 32, 64                                           */
 } egosgm_tuning;

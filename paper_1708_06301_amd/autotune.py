@@ -21,7 +21,7 @@ CACHE = os.environ.get("EGOSGM_TUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "egosgm_tuning.json"))
 
 CANDIDATES = [dict(full_group=f, ragged_group=r, ragged_schedule=s)
-              for f, r, s in itertools.product((16, 32, 64), (16, 32, 64), (0, 1, 2))]
+              for f, r, s in itertools.product((16, 32, 64), (16, 32, 64), (0, 1, 2, 3))]
 
 
 def _key(w, h, max_disp, tag=""):

@@ -182,6 +182,8 @@ struct egosgm_plan {
     int n = 0;
     int max_disp = 0;
     BatchTables tables{};
+    SgmLaunch* pairs_dev = nullptr;       // device descriptors (in the workspace)
+    std::vector<egosgm_pair> shape;       // creation-time pairs (shapes, outputs)
 };
 
 namespace {
@@ -287,6 +289,7 @@ int sgm_plan_create(const egosgm_pair* pairs, int n, const egosgm_sgm_params* pa
         a.disp_sub = q.disp_sub;
         a.var_meas = q.var_meas;
         a.disp_right = q.disp_right;
+        a.active = 1;
         o += L.total;
         cen[i] = (int)tiles;
         seg[i] = (int)segs;
@@ -350,6 +353,8 @@ int sgm_plan_create(const egosgm_pair* pairs, int n, const egosgm_sgm_params* pa
     plan->n = n;
     plan->max_disp = max_disp;
     plan->tables = t;
+    plan->pairs_dev = reinterpret_cast<SgmLaunch*>(base + P.pairs);
+    plan->shape.assign(pairs, pairs + n);
     hipStream_t cs = nullptr;
     bool ok = hipStreamCreate(&cs) == hipSuccess;
     ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
@@ -386,6 +391,27 @@ int sgm_plan_run_eager(egosgm_plan* plan, void* stream) {
                    timed(EGOSGM_STAGE_BATCH_SELECT, s, [&] { return launch_batch_stage(t, plan->max_disp, 4, s); }) == hipSuccess
                ? EGOSGM_OK
                : EGOSGM_EDEVICE;
+}
+
+int sgm_plan_update(egosgm_plan* plan, const egosgm_pair_update* upd, int n, void* stream) {
+    if (!plan || !plan->exec || n < 0 || (n > 0 && !upd)) return EGOSGM_EINVAL;
+    for (int j = 0; j < n; ++j) {
+        const egosgm_pair_update& u = upd[j];
+        if (u.index < 0 || u.index >= plan->n || !u.left || !u.right) return EGOSGM_EINVAL;
+        if ((u.lo == nullptr) != (u.hi == nullptr) || (u.lo == nullptr) != (u.offsets == nullptr))
+            return EGOSGM_EINVAL;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int j0 = 0; j0 < n; j0 += kPatchBatch) {
+        PlanPatches p{};
+        p.n = std::min(kPatchBatch, n - j0);
+        for (int j = 0; j < p.n; ++j) {
+            const egosgm_pair_update& u = upd[j0 + j];
+            p.p[j] = PlanPatch{u.index, u.active ? 1 : 0, u.left, u.right, u.lo, u.hi, u.offsets};
+        }
+        if (launch_plan_patch(plan->pairs_dev, p, s) != hipSuccess) return EGOSGM_EDEVICE;
+    }
+    return EGOSGM_OK;
 }
 
 int sgm_plan_destroy(egosgm_plan* plan) {
@@ -580,7 +606,7 @@ int egosgm_set_tuning(const egosgm_tuning* t) {
     if (!t) return EGOSGM_EINVAL;
     auto ok = [](int g) { return g == 16 || g == 32 || g == 64; };
     if (!ok(t->full_group) || !ok(t->ragged_group) || !ok(t->batch_group) || t->ragged_schedule < 0 ||
-        t->ragged_schedule > 2)
+        t->ragged_schedule > 3)
         return EGOSGM_EINVAL;
     std::lock_guard<std::mutex> g(g_tuning_mu);
     g_tuning = *t;

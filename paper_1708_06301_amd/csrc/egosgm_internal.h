@@ -43,6 +43,23 @@ struct SgmLaunch {
     int16_t* disp_right;     // nullable
     uint16_t* agg;           // nullable (debug)
     int16_t* wta_raw;        // nullable (debug)
+    int active;              // batched launches: 0 skips the pair
+};
+
+// One descriptor change of a plan (sgm_plan_update): the pair's active flag,
+// images and windows (lo == nullptr: full range).
+struct PlanPatch {
+    int index, active;
+    const uint8_t* left;
+    const uint8_t* right;
+    const int16_t* lo;
+    const int16_t* hi;
+    const uint32_t* off;
+};
+constexpr int kPatchBatch = 16;
+struct PlanPatches {
+    PlanPatch p[kPatchBatch];
+    int n;
 };
 
 // Device tables of a batched launch (all pointers into device memory),
@@ -62,6 +79,7 @@ struct BatchTables {
 };
 
 hipError_t launch_sgm_batch(const BatchTables& t, int max_disp, hipStream_t s);
+hipError_t launch_plan_patch(SgmLaunch* pairs, const PlanPatches& p, hipStream_t s);
 // stage 0 census, 1 cost, 2 paths, 3 selection, 4 left-right check
 hipError_t launch_batch_stage(const BatchTables& t, int max_disp, int stage, hipStream_t s);
 hipError_t launch_census(const uint8_t* img, int w, int h, int pitch, uint64_t* out,

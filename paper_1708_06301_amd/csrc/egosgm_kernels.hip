@@ -342,11 +342,15 @@ __device__ inline Scan scan_of(int task, int W, int H) {
     return Scan{dir, y * W + x, dy * W + dx, len};
 }
 
+// Entries of one LDS row of a scanline: absolute disparity d at index d+1,
+// for D <= G*K, plus room for a whole chunk of G lanes past any window.
+constexpr int lds_row(int G, int K) { return 2 * G * K + 2; }
+
 // ---- LDS scanline (ragged windows, work proportional to the window) ----
 // One lane group of G lanes walks one scanline; lane l owns slots
 // s = l + G*k (k < K) of each pixel's window.  The previous pixel's path
 // costs sit in a per-group LDS row (ping-pong) indexed by absolute disparity
-// (entry d+1, entries 0 and D+1 are guards).  Every entry outside the
+// (entry d+1; entry 0 and the entries past D are guards).  Every entry outside the
 // predecessor's window holds +infinity: a step erases the row it has just
 // consumed, so the row is clean when it is written again two steps later.
 // The d-1, d, d+1 lookups therefore need no bounds checks, and ragged
@@ -360,7 +364,7 @@ template <int G, int K, int WM, int PF>
 __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane,
                                     uint16_t* b0, uint16_t* b1) {
     constexpr int RM = 2 * PF;
-    constexpr int ROW = G * K + 2;
+    constexpr int ROW = lds_row(G, K);
     gmem<uint8_t>* __restrict__ vol = gptr(a.vol + (size_t)sc.dir * a.vol_stride);
     const gmem<uint8_t>* __restrict__ cost = gptr(a.cost);
     const int p1 = a.p1, p2 = a.p2;
@@ -387,9 +391,21 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
     lds_order();
     for (int e = lane; e < mw[0]; e += G) b1[mlo[0] + 1 + e] = 0;   // zero predecessor
     lds_order();
-    int lo_q = mlo[0], w_q = mw[0], m_q = 0;
+    int lo_q = mlo[0], m_q = 0;
+    // Chunks k (slots lane + G*k) written by the previous step: wave-uniform
+    // bits, since a chunk runs when any lane group of the wave needs it.
+    uint32_t done_q = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (k == 0 || __builtin_amdgcn_ballot_w64(lane + G * k < mw[0]) != 0) done_q |= 1u << k;
     int p = p0;
 
+    // One step.  A running chunk reads and writes all its lanes (the rows
+    // are 2*G*K+2 entries, so every index stays inside): lanes past the
+    // window write +infinity, which keeps the row outside the window at
+    // +infinity, and only the global store is masked.  The reads depend on
+    // nothing of the previous step's minimum, so they can issue while its
+    // reduction runs.
     auto step = [&](int ti, int tc, int parity) {
         const int lo_c = mlo[ti], w_c = mw[ti];
         const uint32_t off_c = moff[ti];
@@ -397,27 +413,29 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
         uint16_t* prv = parity ? b0 : b1;
         const int m2 = m_q + p2;
         int mn = kInf;
+        uint32_t done_c = 0;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int s = lane + G * k;
-            if (s < w_c) {
+            if (k == 0 || __builtin_amdgcn_ballot_w64(s < w_c) != 0) {
+                done_c |= 1u << k;
                 const uint16_t* q = prv + lo_c + s;   // q[0] = d-1, q[1] = d, q[2] = d+1
                 const int best = min(min((int)q[1], min((int)q[0], (int)q[2]) + p1), m2);
                 const int L = cst[tc][k] + best - m_q;
-                cur[lo_c + s + 1] = (uint16_t)L;
-                vol[off_c + (uint32_t)s] = (uint8_t)L;
-                mn = min(mn, L);
+                const bool in = s < w_c;
+                const int Lm = in ? L : kInf;
+                cur[lo_c + s + 1] = (uint16_t)Lm;
+                if (in) vol[off_c + (uint32_t)s] = (uint8_t)L;
+                mn = min(mn, Lm);
             }
         }
         lds_order();
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int s = lane + G * k;
-            if (s < w_q) prv[lo_q + s + 1] = kInf;
-        }
+        for (int k = 0; k < K; ++k)
+            if (done_q & (1u << k)) prv[lo_q + lane + G * k + 1] = kInf;
+        done_q = done_c;
         m_q = group_min<G>(mn);
         lo_q = lo_c;
-        w_q = w_c;
     };
 
     int i = 0;
@@ -682,17 +700,159 @@ __device__ inline void packed_scanline_windowed(const SgmLaunch& a, const Scan& 
     }
 }
 
+// ---- register scanline (ragged windows, one wave per scanline) ----
+// Lane j holds slot j + 64*k (chunk k < K) of the previous pixel's path
+// costs, counted from that pixel's window start lo_q.  Slots past a window
+// hold values >= kInf: their cost is the marker kInf, every candidate of a
+// minimum is >= the previous minimum, so they stay in [kInf, kInf + P2] and
+// act as +infinity, as the out-of-window marker does in packed_update.
+// A step whose window and predecessor window fit in one chunk takes the
+// d-1, d, d+1 predecessors by lane shifts: DPP when the window start is
+// unchanged, ds_bpermute by the start difference otherwise.  A step with a
+// wider window goes through an LDS row indexed by absolute disparity (entry
+// d+1, +infinity outside the written range, erased after use), as in
+// lds_scanline.  Every branch depends on wave-uniform values only.
+// Raw buffer over n bytes: stores at offsets >= n are discarded by the
+// hardware, which masks a store without a branch.  Word 3 is the gfx9
+// family's raw-buffer format word.
+__device__ inline __amdgpu_buffer_rsrc_t byte_buffer(void* base, uint32_t n) {
+    return __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)n, 0x00020000);
+}
+constexpr uint32_t kDropOffset = 0xffffffffu;
+
+__device__ inline int lane_from(int v, int t) {
+    const int r = __builtin_amdgcn_ds_bpermute(t << 2, v);
+    return (unsigned)t < 64u ? r : kInf;
+}
+
+template <int K, int WM, int PF>
+__device__ inline void reg_scanline(const SgmLaunch& a, const Scan& sc, int lane, uint16_t* row) {
+    constexpr int RM = 2 * PF;
+    constexpr int ROW = lds_row(64, K);
+    const __amdgpu_buffer_rsrc_t vol =
+        byte_buffer(a.vol + (size_t)sc.dir * a.vol_stride, (uint32_t)a.vol_stride);
+    const gmem<uint8_t>* __restrict__ cost = gptr(a.cost);
+    const int p1 = a.p1, p2 = a.p2;
+    const int dp = sc.dp, len = sc.len, p0 = sc.p0;
+    const int p_last = p0 + (len - 1) * dp;
+
+    int mlo[RM], mw[RM];
+    uint32_t moff[RM];
+    auto load_meta = [&](int j, int pix) {
+        int hi;
+        window_of<WM>(a.win, pix, mlo[j], hi, moff[j]);
+        mw[j] = hi - mlo[j] + 1;
+    };
+#pragma unroll
+    for (int j = 0; j < RM; ++j) load_meta(j, j < len ? p0 + j * dp : p_last);
+    int cst[PF][K];
+#pragma unroll
+    for (int j = 0; j < PF; ++j) load_costs<64, K>(cost, moff[j], mw[j], lane, cst[j]);
+
+    for (int e = lane; e < ROW; e += 64) row[e] = kInf;
+    lds_order();
+    int lo_q = __builtin_amdgcn_readfirstlane(mlo[0]);
+    int w_q = __builtin_amdgcn_readfirstlane(mw[0]);
+    int L[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) L[k] = lane + 64 * k < w_q ? 0 : kInf;   // zero predecessor
+    int m_q = 0;
+    int p = p0;
+
+    auto step = [&](int ti, int tc) {
+        const int lo_c = __builtin_amdgcn_readfirstlane(mlo[ti]);
+        const int w_c = __builtin_amdgcn_readfirstlane(mw[ti]);
+        const uint32_t off_c = __builtin_amdgcn_readfirstlane(moff[ti]);
+        const int m2 = m_q + p2;
+        int mn;
+        if (__builtin_expect(w_c <= 64 && w_q <= 64, 1)) {
+            const int dlt = lo_c - lo_q;
+            int A, B, C;
+            if (__builtin_expect(dlt == 0, 1)) {
+                A = __builtin_amdgcn_update_dpp(kInf, L[0], 0x138, 0xF, 0xF, false);   // wave_shr:1
+                B = L[0];
+                C = __builtin_amdgcn_update_dpp(kInf, L[0], 0x130, 0xF, 0xF, false);   // wave_shl:1
+            } else {
+                const int t = lane + dlt;
+                A = lane_from(L[0], t - 1);
+                B = lane_from(L[0], t);
+                C = lane_from(L[0], t + 1);
+            }
+            const bool in = lane < w_c;
+            const int c = in ? cst[tc][0] : kInf;
+            const int Ln = c + min(min(min(A, C) + p1, B), m2) - m_q;
+            L[0] = Ln;
+            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)Ln, vol, in ? off_c + (uint32_t)lane : kDropOffset,
+                                                 0, 0);
+            mn = Ln;
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k) row[lo_q + lane + 64 * k + 1] = (uint16_t)L[k];
+            lds_order();
+            mn = kInf;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int s = lane + 64 * k;
+                const uint16_t* q = row + lo_c + s;   // q[0] = d-1, q[1] = d, q[2] = d+1
+                const bool in = s < w_c;
+                const int c = in ? cst[tc][k] : kInf;
+                const int Ln = c + min(min(min((int)q[0], (int)q[2]) + p1, (int)q[1]), m2) - m_q;
+                L[k] = Ln;
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)Ln, vol, in ? off_c + (uint32_t)s : kDropOffset,
+                                                     0, 0);
+                mn = min(mn, Ln);
+            }
+            lds_order();
+#pragma unroll
+            for (int k = 0; k < K; ++k) row[lo_q + lane + 64 * k + 1] = kInf;
+        }
+        m_q = group_min<64>(mn);
+        lo_q = lo_c;
+        w_q = w_c;
+    };
+
+    int i = 0;
+    for (; i + RM <= len; i += RM) {
+#pragma unroll
+        for (int u = 0; u < RM; ++u) {
+            step(u, u % PF);
+            load_costs<64, K>(cost, moff[(u + PF) % RM], mw[(u + PF) % RM], lane, cst[u % PF]);
+            load_meta(u, (i + u + RM < len) ? p + RM * dp : p_last);
+            p += dp;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < RM; ++u) {
+        if (i + u < len) {
+            step(u, u % PF);
+            if (u + PF < RM) load_costs<64, K>(cost, moff[u + PF], mw[u + PF], lane, cst[u % PF]);
+            p += dp;
+        }
+    }
+}
+
 // ---- kernels ----
 // Generic: every scanline through LDS rows (any D; ragged or full windows).
 template <int G, int K, int WM, int PF>
 __global__ __launch_bounds__(kBlock) void sgm_paths_lds_kernel(SgmLaunch a, int n_tasks) {
     constexpr int GPB = kBlock / G;
-    __shared__ uint16_t lds[GPB][2][G * K + 2];
+    __shared__ uint16_t lds[GPB][2][lds_row(G, K)];
     const int grp = threadIdx.x / G, lane = threadIdx.x % G;
     const int task = blockIdx.x * GPB + grp;
     if (task >= n_tasks) return;
     const Scan sc = scan_of(task, a.w, a.h);
     lds_scanline<G, K, WM, PF>(a, sc, lane, lds[grp][0], lds[grp][1]);
+}
+
+// Ragged windows, every scanline on registers (one wave per scanline).
+template <int K, int PF>
+__global__ __launch_bounds__(kBlock) void sgm_paths_reg_kernel(SgmLaunch a, int n_tasks) {
+    constexpr int WPB = kBlock / 64;
+    __shared__ uint16_t lds[WPB][lds_row(64, K)];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
+    const int task = (int)blockIdx.x * WPB + wv;
+    if (task >= n_tasks) return;
+    reg_scanline<K, kWinRagged, PF>(a, scan_of(task, a.w, a.h), lane, lds[wv]);
 }
 
 // Full range, D = 2*NP*G: every scanline on packed registers.
@@ -722,7 +882,7 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_ragged_kernel(SgmLaunch a, i
         packed_scanline_windowed<GP, NP, PF>(a, scan_of(task, a.w, a.h), lane);
     } else {
         constexpr int GPB = kBlock / GL;
-        __shared__ uint16_t lds[GPB][2][GL * K + 2];
+        __shared__ uint16_t lds[GPB][2][lds_row(GL, K)];
         const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
         const int task = n_packed_tasks + (blockIdx.x - n_packed_blocks) * GPB + grp;
         if (task >= n_tasks) return;
@@ -883,6 +1043,7 @@ __device__ inline const SgmLaunch& pair_of(const BatchTables& t, int i) {
 __global__ __launch_bounds__(kBlock) void census_batch_kernel(BatchTables t) {
     const int i = last_leq(t.census_prefix, t.n, (int)blockIdx.x);
     const SgmLaunch a = pair_of(t, i);
+    if (!a.active) return;
     const int local = (int)blockIdx.x - t.census_prefix[i];
     const int tiles_x = (a.w + kCtW - 1) / kCtW;
     const int tx = local % tiles_x, ty = local / tiles_x;
@@ -895,6 +1056,7 @@ __global__ __launch_bounds__(kBlock) void census_batch_kernel(BatchTables t) {
 __global__ __launch_bounds__(kBlock) void cost_batch_kernel(BatchTables t) {
     const int i = last_leq(t.seg_prefix, t.n, (int)blockIdx.x);
     const SgmLaunch a = pair_of(t, i);
+    if (!a.active) return;
     const int local = (int)blockIdx.x - t.seg_prefix[i];
     const int segs_x = (a.w + kSeg - 1) / kSeg;
     cost_segment<16, kWinAny>(a, local % segs_x, local / segs_x);
@@ -906,7 +1068,7 @@ __global__ __launch_bounds__(kBlock) void cost_batch_kernel(BatchTables t) {
 template <int G, int K, int PF>
 __global__ __launch_bounds__(kBlock) void paths_batch_kernel(BatchTables t) {
     constexpr int GPB = kBlock / G;
-    __shared__ uint16_t lds[GPB][2][G * K + 2];
+    __shared__ uint16_t lds[GPB][2][lds_row(G, K)];
     const int grp = threadIdx.x / G, lane = threadIdx.x % G;
     const int task = (int)blockIdx.x * GPB + grp;
     if (task >= t.n_tasks) return;
@@ -916,6 +1078,7 @@ __global__ __launch_bounds__(kBlock) void paths_batch_kernel(BatchTables t) {
     const int rel = task - t.task_start[r];
     if (rel >= t.task_count[r]) return;                 // padding
     const SgmLaunch a = pair_of(t, i);
+    if (!a.active) return;
     lds_scanline<G, K, kWinAny, PF>(a, scan_of(t.task_local[r] + rel, a.w, a.h), lane, lds[grp][0],
                                     lds[grp][1]);
 }
@@ -924,6 +1087,7 @@ template <int K>
 __global__ __launch_bounds__(kBlock) void select_batch_kernel(BatchTables t) {
     const int i = last_leq(t.seg_prefix, t.n, (int)blockIdx.x);
     const SgmLaunch a = pair_of(t, i);
+    if (!a.active) return;
     const int local = (int)blockIdx.x - t.seg_prefix[i];
     const int segs_x = (a.w + kSeg - 1) / kSeg;
     select_segment<16, K, kWinAny>(a, local % segs_x, local / segs_x);
@@ -933,7 +1097,22 @@ __global__ __launch_bounds__(kBlock) void lr_batch_kernel(BatchTables t) {
     const int g = (int)blockIdx.x * kBlock + (int)threadIdx.x;
     if (g >= t.pix_prefix[t.n]) return;
     const int i = last_leq(t.pix_prefix, t.n, g);
-    lr_pixel(pair_of(t, i), g - t.pix_prefix[i]);
+    const SgmLaunch& a = pair_of(t, i);
+    if (a.active) lr_pixel(a, g - t.pix_prefix[i]);
+}
+
+// Applies descriptor changes of a plan; one thread per change.
+__global__ void plan_patch_kernel(SgmLaunch* pairs, PlanPatches p) {
+    const int j = threadIdx.x;
+    if (j >= p.n) return;
+    const PlanPatch& c = p.p[j];
+    gmem<SgmLaunch>* a = gptr(pairs + c.index);
+    a->active = c.active;
+    a->left = c.left;
+    a->right = c.right;
+    a->win.lo = c.lo;
+    a->win.hi = c.hi;
+    a->win.off = c.off;
 }
 
 // ------------------------------------------------------------------ warp
@@ -1143,7 +1322,14 @@ hipError_t launch_sgm_paths(const SgmLaunch& a, hipStream_t s) {
     // packed part (rows, or everything) uses 32 lanes over D rounded up to
     // 64, 128 or 256.
     const int g = a.ragged_group;
-    const int sched = a.ragged_schedule;   // 0: all LDS, 1: rows packed, 2: all packed
+    const int sched = a.ragged_schedule;   // 0: all LDS, 1: rows packed, 2: all packed, 3: registers
+    if (sched == 3) {
+        const unsigned nb = blocks(n_tasks, 64);
+        if (D <= 64) sgm_paths_reg_kernel<1, 4><<<nb, kBlock, 0, s>>>(a, n_tasks);
+        else if (D <= 128) sgm_paths_reg_kernel<2, 4><<<nb, kBlock, 0, s>>>(a, n_tasks);
+        else sgm_paths_reg_kernel<4, 4><<<nb, kBlock, 0, s>>>(a, n_tasks);
+        return hipGetLastError();
+    }
     const int n_packed = sched == 0 ? 0 : (sched == 1 ? 2 * a.h : n_tasks);
 #define EGOSGM_RAG(NP, GL, KK)                                                                 \
     do {                                                                                       \
@@ -1201,6 +1387,12 @@ hipError_t launch_windows(const float* d_pred, const float* p_pred, int w, int h
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     windows_offset_kernel<<<h, kBlock, 0, s>>>(w, h, off, row_tot);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_patch(SgmLaunch* pairs, const PlanPatches& p, hipStream_t s) {
+    if (p.n <= 0) return hipSuccess;
+    plan_patch_kernel<<<1, kPatchBatch, 0, s>>>(pairs, p);
     return hipGetLastError();
 }
 

@@ -41,6 +41,7 @@ _SIGS = {
     "sgm_plan_create": ([_vp, _i, _vp, _vp, _sz, _vp], _i),
     "sgm_plan_run": ([_vp, _vp], _i),
     "sgm_plan_run_eager": ([_vp, _vp], _i),
+    "sgm_plan_update": ([_vp, _vp, _i, _vp], _i),
     "sgm_plan_destroy": ([_vp], _i),
     "egosgm_set_tuning": ([_vp], _i),
     "egosgm_get_tuning": ([_vp], _i),
@@ -378,6 +379,15 @@ class PairDesc(C.Structure):
                 ("disp_right", _vp)]
 
 
+class PairUpdate(C.Structure):
+    _fields_ = [("index", C.c_int32), ("active", C.c_int32), ("left", C.c_void_p),
+                ("right", C.c_void_p), ("lo", C.c_void_p), ("hi", C.c_void_p),
+                ("offsets", C.c_void_p)]
+
+
+KEEP = object()   # Plan.update: leave this part of the pair as it is
+
+
 class Plan:
     """Batched matching of many pairs in one captured graph.
 
@@ -411,6 +421,8 @@ class Plan:
                                 _ptr(o.get("disp_right")))
             self._keep += [L, R, lo, hi, off]
             self.outputs.append(o)
+        self._cur = [dict(left=q["left"], right=q["right"], windows=q.get("windows"), active=True)
+                     for q in pairs]
         self.n = len(pairs)
         nbytes = lib().egosgm_plan_workspace_bytes(descs, self.n)
         if nbytes == 0:
@@ -429,6 +441,44 @@ class Plan:
             _check(lib().sgm_plan_run_eager(self._plan, _stream()), "sgm_plan_run_eager")
         else:
             _check(lib().sgm_plan_run(self._plan, _stream()), "sgm_plan_run")
+
+    def update(self, changes):
+        """Enqueues per-pair changes on the current stream for the runs that
+        follow: dicts with index and any of active (bool), left, right (same
+        shape as at creation) and windows ((lo, hi, offsets), or None for the
+        full range).  Omitted parts stay as they are."""
+        ups = (PairUpdate * max(len(changes), 1))()
+        staged = []
+        for j, c in enumerate(changes):
+            i = int(c["index"])
+            if not 0 <= i < self.n:
+                raise EgoSgmError(f"plan update: pair index {i} out of range")
+            cur = dict(self._cur[i])
+            h, w = self._cur[i]["left"].shape
+            for k in ("left", "right"):
+                t = c.get(k, KEEP)
+                if t is not KEEP:
+                    _need(t, torch.uint8, name=k)
+                    if tuple(t.shape) != (h, w):
+                        raise EgoSgmError(f"plan update: {k} must be {h}x{w}")
+                    cur[k] = t
+            win = c.get("windows", KEEP)
+            if win is not KEEP:
+                if win is not None:
+                    lo, hi, off = win
+                    _need(lo, torch.int16, h * w, "lo")
+                    _need(hi, torch.int16, h * w, "hi")
+                    _need(off, torch.int32, h * w + 1, "offsets")
+                cur["windows"] = win
+            if "active" in c:
+                cur["active"] = bool(c["active"])
+            lo, hi, off = cur["windows"] if cur["windows"] is not None else (None, None, None)
+            ups[j] = PairUpdate(i, int(cur["active"]), _ptr(cur["left"]), _ptr(cur["right"]),
+                                _ptr(lo), _ptr(hi), _ptr(off))
+            staged.append((i, cur))
+        _check(lib().sgm_plan_update(self._plan, ups, len(changes), _stream()), "sgm_plan_update")
+        for i, cur in staged:
+            self._cur[i] = cur
 
     def close(self):
         if getattr(self, "_plan", None):

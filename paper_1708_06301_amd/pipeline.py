@@ -49,7 +49,11 @@ class FrameConfig:
 
 
 class StreamState:
-    def __init__(self, w: int, h: int, calib: Calib, cfg: FrameConfig, device="cuda"):
+    """own_matcher=False: the stream is matched through a batched plan (no
+    matcher workspace or outputs of its own; update() takes the plan's)."""
+
+    def __init__(self, w: int, h: int, calib: Calib, cfg: FrameConfig, device="cuda",
+                 own_matcher: bool = True):
         self.w, self.h, self.calib, self.cfg = w, h, calib, cfg
         dev = torch.device(device)
         self.device = dev
@@ -68,9 +72,11 @@ class StreamState:
         self.out = dict(disp_wta=torch.empty((h, w), dtype=torch.int16, device=dev),
                         disp_sub=torch.empty((h, w), **f32),
                         var_meas=torch.empty((h, w), **f32),
-                        disp_right=torch.empty((h, w), dtype=torch.int16, device=dev))
+                        disp_right=torch.empty((h, w), dtype=torch.int16, device=dev)) \
+            if own_matcher else {}
         self.ws = eg.Workspace(dev)
-        self.ws.sgm_bytes(w, h, cfg.max_disp)
+        if own_matcher:
+            self.ws.sgm_bytes(w, h, cfg.max_disp)
         self.ws.windows_bytes(w, h)
         self.ws.refine_bytes(w, h)
         self.invalid = torch.full((h, w), -1.0, **f32)
@@ -108,18 +114,28 @@ class StreamState:
         else:
             eg.sgm_reduced(left, right, *windows, prm, out=self.out, workspace=self.ws)
 
-    def update(self):
-        """Second half: the Kalman update of the prediction with self.out
+    def update(self, out=None):
+        """Second half: the Kalman update of the prediction with the
+        measurement (self.out, or the outputs dict `out` of a batched plan)
         (Sec. 2.4); the first frame takes the measurement as it is."""
         cfg = self.cfg
+        out = out or self.out
         if self.full_range_next():
-            eg.kalman_update(self.invalid, self.zeros, self.out["disp_sub"], self.out["var_meas"],
+            eg.kalman_update(self.invalid, self.zeros, out["disp_sub"], out["var_meas"],
                              cfg.keep_unmeasured, out=(self.d, self.p))
         else:
-            eg.kalman_update(self.d_pred, self.p_pred, self.out["disp_sub"], self.out["var_meas"],
+            eg.kalman_update(self.d_pred, self.p_pred, out["disp_sub"], out["var_meas"],
                              cfg.keep_unmeasured, out=(self.d, self.p))
         self.frame += 1
         return self.d, self.p
+
+    def resident_bytes(self) -> int:
+        """Device bytes this stream holds (maps, prediction buffers, windows,
+        outputs and workspaces)."""
+        ts = [self.d, self.p, self.d_warp, self.p_warp, self.d_pred, self.p_pred, self.zbuf,
+              self.lo, self.hi, self.off, self.invalid, self.zeros, *self.out.values(),
+              self.ws.sgm, self.ws.win, getattr(self.ws, "ref", None)]
+        return sum(t.numel() * t.element_size() for t in ts if t is not None)
 
     def step(self, left: torch.Tensor, right: torch.Tensor, R=None, t=None):
         """Processes one stereo frame; R, t map the previous camera frame to

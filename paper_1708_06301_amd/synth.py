@@ -298,11 +298,11 @@ def _raycast(scene: Scene, origin, dirs):
     is the camera depth) and the world hit points; torch float64."""
     import torch
     dev = dirs.device
-    o = torch.as_tensor(origin, dtype=torch.float64, device=dev)
+    o = torch.as_tensor(origin, dtype=torch.float64, device=dev)   # (3,) or one per ray (n, 3)
     n = dirs.shape[0]
     t_best = torch.full((n,), float("inf"), dtype=torch.float64, device=dev)
     dy = dirs[:, 1]
-    tg = (scene.cam_height - o[1]) / dy
+    tg = (scene.cam_height - (o[1] if o.dim() == 1 else o[:, 1])) / dy
     tg = torch.where((dy > 1e-12) & (tg > 0), tg, torch.full_like(tg, float("inf")))
     t_best = torch.minimum(t_best, tg)
     inv = 1.0 / dirs
@@ -319,12 +319,16 @@ def _raycast(scene: Scene, origin, dirs):
         t_best = torch.where(hit & (th < t_best), th, t_best)
     oc = o - torch.as_tensor(scene.backdrop_center, dtype=torch.float64, device=dev)
     a = (dirs * dirs).sum(1)
-    bq = 2.0 * (dirs @ oc)
-    cq = (oc @ oc) - scene.backdrop_radius ** 2
+    if oc.dim() == 1:
+        bq = 2.0 * (dirs @ oc)
+        cq = (oc @ oc) - scene.backdrop_radius ** 2
+    else:
+        bq = 2.0 * (dirs * oc).sum(1)
+        cq = (oc * oc).sum(1) - scene.backdrop_radius ** 2
     disc = torch.clamp(bq * bq - 4.0 * a * cq, min=0.0)
     ts = (-bq + torch.sqrt(disc)) / (2.0 * a)
     t_best = torch.minimum(t_best, ts)
-    return t_best, o[None, :] + t_best[:, None] * dirs
+    return t_best, (o[None, :] if o.dim() == 1 else o) + t_best[:, None] * dirs
 
 
 def render_view(scene: Scene, cam: Camera, Rwc: np.ndarray, centre: np.ndarray,
@@ -355,6 +359,44 @@ def render_frame(scene: Scene, cam: Camera, k: int, noise: bool = True, device="
     right, _ = render_view(scene, cam, Rwc, cr, nr, device)
     gt = cam.f * cam.baseline / zl
     return left, right, gt
+
+
+def render_frames_device(scene: Scene, cam: Camera, ks, device, noise: bool = True):
+    """Frames ks as (left, right) uint8 device tensors, all views of the
+    batch in one raycast and one texture evaluation.  The geometry and
+    texture are those of render_frame; the sensor noise is drawn on the
+    device (torch generator seeded per frame), so the images differ from
+    render_frame's in the noise only."""
+    import torch
+    yy, xx = torch.meshgrid(torch.arange(cam.h, dtype=torch.float64, device=device),
+                            torch.arange(cam.w, dtype=torch.float64, device=device),
+                            indexing="ij")
+    d_cam = torch.stack([(xx - cam.cx) / cam.f, (yy - cam.cy) / cam.f, torch.ones_like(xx)],
+                        -1).reshape(-1, 3)
+    n = cam.w * cam.h
+    dirs, orgs = [], []
+    for k in ks:
+        Rwc, c = scene.poses[k]
+        Rt = torch.as_tensor(Rwc, dtype=torch.float64, device=device).T
+        for cc in (c, c + Rwc @ np.array([cam.baseline, 0.0, 0.0])):
+            dirs.append(d_cam @ Rt)
+            orgs.append(torch.as_tensor(cc, dtype=torch.float64, device=device).expand(n, 3))
+    _, pts = _raycast(scene, torch.cat(orgs), torch.cat(dirs))
+    perm = rng(scene.tex_seed).permutation(256).astype(np.int64)
+    p = _perlin_torch(perm, device)
+    v = 128.0 + 180.0 * _fbm3_torch(p, pts[:, 0] / 0.6, pts[:, 1] / 0.6, pts[:, 2] / 0.6)
+    v = v.reshape(len(ks), 2, cam.h, cam.w)
+    out = []
+    for i, k in enumerate(ks):
+        vi = v[i]
+        if noise and scene.noise_sigma > 0:
+            g = torch.Generator(device=device)
+            g.manual_seed(int(splitmix64(scene.noise_seed + k) & 0x7FFFFFFFFFFFFFFF))
+            vi = vi + scene.noise_sigma * torch.randn(vi.shape, generator=g, dtype=torch.float64,
+                                                      device=device)
+        u8 = torch.clamp(torch.floor(vi + 0.5), 0, 255).to(torch.uint8)
+        out.append((u8[0].contiguous(), u8[1].contiguous()))
+    return out
 
 
 def relative_motion(scene: Scene, k: int):

@@ -116,7 +116,8 @@ def test_tuning_validation():
     assert lib.egosgm_set_tuning(C.byref(bad)) == -1
     assert lib.egosgm_set_tuning(None) == -1
     assert eg.get_tuning() == before
-    assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, 3, 16))) == -1
+    assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, 4, 16))) == -1
+    assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, 3, 16))) == 0
     assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, 0, 8))) == -1
     eg.set_tuning(16, 64, 0, 32)
     assert eg.get_tuning() == dict(full_group=16, ragged_group=64, ragged_schedule=0, batch_group=32)

@@ -87,27 +87,44 @@ def test_sgm_full_planes_config():
     _check_sgm(g, o, 320 * 96 * 64)
 
 
-def _random_windows(w, h, D, seed, rmax=6, frac_full=0.1):
+def _random_windows(w, h, D, seed, rmax=6, frac_full=0.1, kind="random"):
+    """Predictions for ragged-window tests.  "random": independent centres
+    (the window start moves at every step); "smooth": a slanted plane, so
+    runs of equal window starts alternate with small moves; "wide": smooth
+    with radii up to rmax (windows wider than 64)."""
     r = np.random.default_rng(seed)
-    d = r.uniform(0, D - 1, size=(h, w)).astype(np.float32)
+    if kind == "random":
+        d = r.uniform(0, D - 1, size=(h, w)).astype(np.float32)
+    else:
+        y, x = np.mgrid[0:h, 0:w]
+        d = (0.2 * D + 0.04 * x + 0.25 * y + r.normal(0, 0.2, (h, w))).astype(np.float32)
+        d = np.clip(d, 0, D - 1).astype(np.float32)
     d[r.random((h, w)) < frac_full] = -1.0
     p = r.uniform(0, (rmax / 3.0) ** 2, size=(h, w)).astype(np.float32)
     return d, p
 
 
-@pytest.mark.parametrize("w,h,D,seed", [(37, 19, 16, 1), (64, 20, 64, 2), (91, 27, 128, 3),
-                                        (33, 5, 256, 4)])
-def test_sgm_reduced_ragged(w, h, D, seed):
-    _say("sgm_reduced", w, h, D, seed)
+@pytest.mark.parametrize("sched", [0, 1, 2, 3])
+@pytest.mark.parametrize("w,h,D,seed,kind,rmax", [
+    (37, 19, 16, 1, "random", 6), (64, 20, 64, 2, "random", 6), (91, 27, 128, 3, "random", 6),
+    (33, 5, 256, 4, "random", 6), (150, 23, 128, 5, "smooth", 6), (97, 17, 256, 6, "wide", 60),
+    (80, 12, 64, 7, "wide", 40)])
+def test_sgm_reduced_ragged(w, h, D, seed, kind, rmax, sched):
+    _say("sgm_reduced", w, h, D, seed, kind, "schedule", sched)
     left, right = _random_pair(w, h, seed=seed + 7, max_shift=min(D - 1, 30))
-    d, p = _random_windows(w, h, D, seed)
-    lo, hi, off = eg.windows_from_prediction(_gpu(d), _gpu(p), D, r_min=0, r_max=12)
-    wo = orc.windows(d, p, D, r_min=0, r_max=12)
+    d, p = _random_windows(w, h, D, seed, rmax=rmax, kind=kind)
+    r_max = max(12, rmax)
+    lo, hi, off = eg.windows_from_prediction(_gpu(d), _gpu(p), D, r_min=0, r_max=r_max)
+    wo = orc.windows(d, p, D, r_min=0, r_max=r_max)
     assert np.array_equal(_np(lo).ravel(), wo[0])
     assert np.array_equal(_np(hi).ravel(), wo[1])
     assert np.array_equal(_np(off).view(np.uint32), wo[2])
     prm = eg.MatchParams(max_disp=D, p1=10, p2=120, s_max=80, lr_tol=1)
-    g = eg.sgm_reduced(_gpu(left), _gpu(right), lo, hi, off, prm, debug=True)
+    eg.set_tuning(**{**eg.DEFAULT_TUNING, "ragged_schedule": sched})
+    try:
+        g = eg.sgm_reduced(_gpu(left), _gpu(right), lo, hi, off, prm, debug=True)
+    finally:
+        eg.set_tuning(**eg.DEFAULT_TUNING)
     o = orc.sgm(left, right, D, windows=wo, want_debug=True)
     _check_sgm(g, o, int(wo[2][-1]))
 
@@ -256,7 +273,7 @@ def test_tuning_never_changes_results(D):
                    _gpu(wo[2].view(np.int32)))
     prm = eg.MatchParams(max_disp=D)
     try:
-        for fg, rg, pr in itertools.product((16, 32, 64), (16, 32, 64), (0, 1, 2)):
+        for fg, rg, pr in itertools.product((16, 32, 64), (16, 32, 64), (0, 1, 2, 3)):
             eg.set_tuning(fg, rg, pr)
             a = eg.sgm_full(L, R, prm)
             b = eg.sgm_reduced(L, R, lo, hi, off, prm)
