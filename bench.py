@@ -455,8 +455,11 @@ def main():
     kname = None
     if dom == "paths":
         g = tuning["ragged_group"]
-        np_ = max(1, (cfg.max_disp + 63) // 64)
-        kname = f"sgm_paths_ragged_kernel<32, {np_}, {g}, {np_ * 64 // g}, 4>"
+        np_ = 1 if cfg.max_disp <= 64 else (2 if cfg.max_disp <= 128 else 4)
+        if tuning["ragged_schedule"] == 3:
+            kname = f"sgm_paths_reg_kernel<{np_}, 4>"
+        else:
+            kname = f"sgm_paths_ragged_kernel<32, {np_}, {g}, {np_ * 64 // g}, 4>"
     elif dom == "select":
         kname = f"sgm_select_kernel<16, {max(1, cfg.max_disp // 16)}, false>"
     if alg_bytes is not None:

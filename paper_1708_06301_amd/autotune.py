@@ -62,9 +62,11 @@ def time_workload(run, reps=3):
     return ts[len(ts) // 2]
 
 
-def tune(run, w, h, max_disp, tag="", candidates=None, reps=3, use_cache=True, log=None):
-    """Picks the fastest tuning for run(), applies it and returns
-    (tuning dict, {candidate index: ms})."""
+def tune(run, w, h, max_disp, tag="", candidates=None, reps=3, use_cache=True, log=None,
+         margin=0.03):
+    """Picks the fastest tuning for run() (the library default when it is
+    within `margin` of the fastest), applies it and returns (tuning dict,
+    {candidate index: ms})."""
     key = _key(w, h, max_disp, tag)
     cache = _load() if use_cache else {}
     if use_cache and key in cache:
@@ -82,6 +84,12 @@ def tune(run, w, h, max_disp, tag="", candidates=None, reps=3, use_cache=True, l
         if log:
             log(f"tune {c}: {times[i]:.3f} ms")
     best_i = min(times, key=times.get)
+    # Hysteresis: the library default stays unless a candidate is clearly
+    # faster, so near-equal candidates do not flip from run to run.
+    dflt = {k: eg.DEFAULT_TUNING[k] for k in cands[0]}
+    d_i = next((i for i, c in enumerate(cands) if c == dflt), None)
+    if d_i is not None and times[d_i] <= times[best_i] * (1.0 + margin):
+        best_i = d_i
     best = cands[best_i]
     eg.set_tuning(**{**eg.get_tuning(), **best})
     if log:
