@@ -455,11 +455,12 @@ def main():
     kname = None
     if dom == "paths":
         g = tuning["ragged_group"]
-        np_ = 1 if cfg.max_disp <= 64 else (2 if cfg.max_disp <= 128 else 4)
+        D = cfg.max_disp
         if tuning["ragged_schedule"] == 3:
-            kname = f"sgm_paths_reg_kernel<{np_}, 4>"
+            kname = f"sgm_paths_reg_kernel<{1 if D <= 64 else (2 if D <= 128 else 4)}, 4>"
         else:
-            kname = f"sgm_paths_ragged_kernel<32, {np_}, {g}, {np_ * 64 // g}, 4>"
+            dr = 64 if D <= 64 else (128 if D <= 128 else 256)
+            kname = f"sgm_paths_ragged_kernel<{1 if D <= 128 else 2}, {g}, {dr // g}, 4>"
     elif dom == "select":
         kname = f"sgm_select_kernel<16, {max(1, cfg.max_disp // 16)}, false>"
     if alg_bytes is not None:

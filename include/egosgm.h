@@ -294,14 +294,15 @@ int sgm_plan_destroy(egosgm_plan* plan);
 /* ------------------------------------------------------------------ tuning
  * Launch shapes and schedules of the path kernels, process-wide (the second
  * piece of state the library keeps; set it before enqueueing work, e.g. from
- * an autotuner).  Results never depend on it.  Defaults: {64, 64, 0, 16}. */
+ * an autotuner).  Results never depend on it.  Defaults: {64, 32, 1, 16}. */
 typedef struct egosgm_tuning {
     int32_t full_group;      /* lanes per scanline, full-range kernel: 16, 32, 64             */
     int32_t ragged_group;    /* lanes per scanline, ragged windows through LDS: 16, 32, 64    */
-    int32_t ragged_schedule; /* 0: every scanline through LDS (work follows the windows);
+    int32_t ragged_schedule; /* 0: every scanline through LDS rows (work follows the windows);
                                 1: the image rows (the longest scanlines) on packed registers
-                                   over all disparities, the rest through LDS;
-                                2: every scanline on packed registers;
+                                   over all disparities, one wave each, branch-free steps;
+                                   the rest through LDS rows;
+                                2: every scanline as the rows of 1;
                                 3: every scanline on registers over its window, one wave
                                    per scanline (window-start moves by lane permutes)        */
     int32_t batch_group;     /* lanes per scanline in batched plans (fixed when a plan is

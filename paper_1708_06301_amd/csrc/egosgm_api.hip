@@ -58,7 +58,7 @@ hipError_t timed(int stage, hipStream_t s, F&& fn) {
 }
 
 // Launch-shape choices (set by egosgm_set_tuning; read at every launch).
-egosgm_tuning g_tuning = {64, 64, 0, 16};
+egosgm_tuning g_tuning = {64, 32, 1, 16};
 std::mutex g_tuning_mu;
 
 constexpr size_t kAlign = 256;
@@ -69,7 +69,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // Workspace: census codes of both images, right-map keys, the cost volume
 // and the eight path volumes (all sized for the full range).
 struct WsLayout {
-    size_t census_l, census_r, key_r, cost, vol, vol_stride, total;
+    size_t census_l, census_r, key_r, meta, cost, vol, vol_stride, total;
 };
 
 bool ws_layout(int w, int h, int D, WsLayout& L) {
@@ -79,7 +79,8 @@ bool ws_layout(int w, int h, int D, WsLayout& L) {
     L.census_l = 0;
     L.census_r = L.census_l + align_up(n * sizeof(uint64_t));
     L.key_r = L.census_r + align_up(n * sizeof(uint64_t));
-    L.cost = L.key_r + align_up(n * sizeof(uint32_t));
+    L.meta = L.key_r + align_up(n * sizeof(uint32_t));
+    L.cost = L.meta + align_up(n * sizeof(uint64_t));
     L.vol = L.cost + align_up(L.vol_stride);
     L.total = L.vol + align_up((size_t)kNumPaths * L.vol_stride);
     return true;
@@ -136,6 +137,7 @@ int run_sgm(const uint8_t* left, const uint8_t* right, int w, int h, int pitch, 
     }
     a.cost = base + L.cost;
     a.key_r = reinterpret_cast<uint32_t*>(base + L.key_r);
+    a.meta = reinterpret_cast<uint64_t*>(base + L.meta);
     a.vol = base + L.vol;
     a.vol_stride = L.vol_stride;
     a.disp_wta = disp_wta;
@@ -275,6 +277,7 @@ int sgm_plan_create(const egosgm_pair* pairs, int n, const egosgm_sgm_params* pa
         a.census_l = reinterpret_cast<uint64_t*>(base + o + L.census_l);
         a.census_r = reinterpret_cast<uint64_t*>(base + o + L.census_r);
         a.key_r = reinterpret_cast<uint32_t*>(base + o + L.key_r);
+        a.meta = reinterpret_cast<uint64_t*>(base + o + L.meta);
         a.cost = base + o + L.cost;
         a.vol = base + o + L.vol;
         a.vol_stride = L.vol_stride;

@@ -35,6 +35,8 @@ struct SgmLaunch {
     int ragged_schedule;     // 0: all scanlines via LDS, 1: rows on packed registers, 2: all packed
     uint8_t* cost;           // matching cost per search slot
     uint32_t* key_r;         // w*h right-map keys (S << 9 | d), cleared by the census pass
+    uint64_t* meta;          // w*h packed windows (offset | lo << 32 | width << 48), written by
+                             // the cost pass for ragged windows, read by the path kernels
     uint8_t* vol;            // 8 path volumes, direction-major
     size_t vol_stride;       // entries per direction block (w*h*D)
     int16_t* disp_wta;

@@ -193,6 +193,18 @@ __device__ inline void window_of(const Windows& win, int p, int& lo, int& hi, ui
     }
 }
 
+// Packed window of one pixel for the path kernels: offset | lo << 32 |
+// width << 48 (lo and width < 2^16).  The cost pass writes it for ragged
+// windows, so a scanline step loads one 8-byte word; the full range is
+// synthesised without a load.  Rings keep the raw word and unpack it where
+// it is used, so the unpacking never waits on a load early.
+__device__ inline uint64_t pack_meta(uint32_t off, int lo, int w) {
+    return (uint64_t)off | ((uint64_t)(uint16_t)lo << 32) | ((uint64_t)(uint16_t)w << 48);
+}
+__device__ inline int meta_lo(uint64_t v) { return (int)(uint16_t)(v >> 32); }
+__device__ inline int meta_w(uint64_t v) { return (int)(v >> 48); }
+__device__ inline uint32_t meta_off(uint64_t v) { return (uint32_t)v; }
+
 // Minimum over each 16-lane row, left in every lane of the row (DPP:
 // quad_perm xor 1, xor 2, then row_ror 4 and 8; each stage folds into one
 // v_min_i32_dpp).
@@ -256,6 +268,8 @@ __device__ inline void cost_segment(const SgmLaunch& a, int seg, int y) {
         int lo, hi;
         uint32_t off;
         window_of<WM>(a.win, y * W + x, lo, hi, off);
+        if (WM != kWinFull && lane == 0 && (WM != kWinAny || a.win.lo != nullptr))
+            gptr(a.meta)[y * W + x] = pack_meta(off, lo, hi - lo + 1);
         const uint64_t cl = cls[i];
         for (int sl = lane; sl <= hi - lo; sl += G) {
             const int d = lo + sl;
@@ -342,6 +356,13 @@ __device__ inline Scan scan_of(int task, int W, int H) {
     return Scan{dir, y * W + x, dy * W + dx, len};
 }
 
+template <int WM>
+__device__ inline uint64_t scan_meta(const SgmLaunch& a, int p) {
+    if (WM == kWinFull || (WM == kWinAny && a.win.lo == nullptr))
+        return pack_meta((uint32_t)p * (uint32_t)a.win.max_disp, 0, a.win.max_disp);
+    return gptr(a.meta)[p];
+}
+
 // Entries of one LDS row of a scanline: absolute disparity d at index d+1,
 // for D <= G*K, plus room for a whole chunk of G lanes past any window.
 constexpr int lds_row(int G, int K) { return 2 * G * K + 2; }
@@ -371,33 +392,28 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
     const int dp = sc.dp, len = sc.len, p0 = sc.p0;
     const int p_last = p0 + (len - 1) * dp;
 
-    int mlo[RM], mw[RM];
-    uint32_t moff[RM];
-    auto load_meta = [&](int j, int pix) {
-        int hi;
-        window_of<WM>(a.win, pix, mlo[j], hi, moff[j]);
-        mw[j] = hi - mlo[j] + 1;
-    };
+    uint64_t mm[RM];
+    auto load_meta = [&](int j, int pix) { mm[j] = scan_meta<WM>(a, pix); };
 #pragma unroll
     for (int j = 0; j < RM; ++j) load_meta(j, j < len ? p0 + j * dp : p_last);
     int cst[PF][K];
 #pragma unroll
-    for (int j = 0; j < PF; ++j) load_costs<G, K>(cost, moff[j], mw[j], lane, cst[j]);
+    for (int j = 0; j < PF; ++j) load_costs<G, K>(cost, meta_off(mm[j]), meta_w(mm[j]), lane, cst[j]);
 
     for (int e = lane; e < ROW; e += G) {
         b0[e] = kInf;
         b1[e] = kInf;
     }
     lds_order();
-    for (int e = lane; e < mw[0]; e += G) b1[mlo[0] + 1 + e] = 0;   // zero predecessor
+    for (int e = lane; e < meta_w(mm[0]); e += G) b1[meta_lo(mm[0]) + 1 + e] = 0;   // zero predecessor
     lds_order();
-    int lo_q = mlo[0], m_q = 0;
+    int lo_q = meta_lo(mm[0]), m_q = 0;
     // Chunks k (slots lane + G*k) written by the previous step: wave-uniform
     // bits, since a chunk runs when any lane group of the wave needs it.
     uint32_t done_q = 0;
 #pragma unroll
     for (int k = 0; k < K; ++k)
-        if (k == 0 || __builtin_amdgcn_ballot_w64(lane + G * k < mw[0]) != 0) done_q |= 1u << k;
+        if (k == 0 || __builtin_amdgcn_ballot_w64(lane + G * k < meta_w(mm[0])) != 0) done_q |= 1u << k;
     int p = p0;
 
     // One step.  A running chunk reads and writes all its lanes (the rows
@@ -407,8 +423,8 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
     // nothing of the previous step's minimum, so they can issue while its
     // reduction runs.
     auto step = [&](int ti, int tc, int parity) {
-        const int lo_c = mlo[ti], w_c = mw[ti];
-        const uint32_t off_c = moff[ti];
+        const int lo_c = meta_lo(mm[ti]), w_c = meta_w(mm[ti]);
+        const uint32_t off_c = meta_off(mm[ti]);
         uint16_t* cur = parity ? b1 : b0;
         uint16_t* prv = parity ? b0 : b1;
         const int m2 = m_q + p2;
@@ -443,7 +459,8 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
 #pragma unroll
         for (int u = 0; u < RM; ++u) {
             step(u, u % PF, u & 1);
-            load_costs<G, K>(cost, moff[(u + PF) % RM], mw[(u + PF) % RM], lane, cst[u % PF]);
+            load_costs<G, K>(cost, meta_off(mm[(u + PF) % RM]), meta_w(mm[(u + PF) % RM]), lane,
+                             cst[u % PF]);
             load_meta(u, (i + u + RM < len) ? p + RM * dp : p_last);
             p += dp;
         }
@@ -453,7 +470,7 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
         if (i + u < len) {
             step(u, u % PF, u & 1);
             if (u + PF < RM)
-                load_costs<G, K>(cost, moff[u + PF], mw[u + PF], lane, cst[u % PF]);
+                load_costs<G, K>(cost, meta_off(mm[u + PF]), meta_w(mm[u + PF]), lane, cst[u % PF]);
             p += dp;
         }
     }
@@ -618,88 +635,6 @@ __device__ inline void packed_scanline_full(const SgmLaunch& a, const Scan& sc, 
     }
 }
 
-// Ragged windows on the packed registers: the same recurrence over all D
-// disparities, slots outside the pixel's window [lo, hi] getting the
-// out-of-window marker cost (see packed_update), so the in-window results
-// equal those of the ragged recurrence exactly.  Costs are gathered byte by
-// byte from the ragged volume (clamped inside the window, masked on use);
-// only in-window path costs are stored.  Window metadata is prefetched 2*PF
-// steps ahead and cost bytes PF steps ahead, as in lds_scanline.
-template <int G, int NP, int PF>
-__device__ inline void packed_scanline_windowed(const SgmLaunch& a, const Scan& sc, int lane) {
-    constexpr int RM = 2 * PF;
-    constexpr int S = 2 * NP;      // slots per lane
-    const gmem<uint8_t>* __restrict__ cost = gptr(a.cost);
-    gmem<uint8_t>* __restrict__ vol = gptr(a.vol + (size_t)sc.dir * a.vol_stride);
-    const int dp = sc.dp, len = sc.len, p0 = sc.p0;
-    const int p_last = p0 + (len - 1) * dp;
-    const uint32_t p1pk = (uint32_t)a.p1 * 0x10001u;
-    const int p2 = a.p2;
-    const int d0 = S * lane;       // this lane's first disparity
-
-    int mlo[RM], mw[RM];
-    uint32_t moff[RM];
-    auto load_meta = [&](int j, int pix) {
-        int hi;
-        window_of<kWinRagged>(a.win, pix, mlo[j], hi, moff[j]);
-        mw[j] = hi - mlo[j] + 1;
-    };
-    auto load_bytes = [&](int j, uint32_t (&b)[S]) {
-#pragma unroll
-        for (int t = 0; t < S; ++t) {
-            const int s = min(max(d0 + t - mlo[j], 0), mw[j] - 1);
-            b[t] = cost[moff[j] + (uint32_t)s];
-        }
-    };
-#pragma unroll
-    for (int j = 0; j < RM; ++j) load_meta(j, j < len ? p0 + j * dp : p_last);
-    uint32_t cb[PF][S];
-#pragma unroll
-    for (int j = 0; j < PF; ++j) load_bytes(j, cb[j]);
-
-    uint32_t L[NP];
-#pragma unroll
-    for (int r = 0; r < NP; ++r) L[r] = 0u;
-    int m = 0;
-    int p = p0;
-    auto step = [&](int ti, int tc) {
-        const int lo = mlo[ti], w = mw[ti];
-        const uint32_t off = moff[ti];
-        uint32_t c[NP];
-#pragma unroll
-        for (int r = 0; r < NP; ++r) {
-            const bool in0 = (unsigned)(d0 + 2 * r - lo) < (unsigned)w;
-            const bool in1 = (unsigned)(d0 + 2 * r + 1 - lo) < (unsigned)w;
-            c[r] = (in0 ? cb[tc][2 * r] : 0x3fffu) | ((in1 ? cb[tc][2 * r + 1] : 0x3fffu) << 16);
-        }
-        packed_update<G, NP>(L, c, m, p1pk, p2);
-#pragma unroll
-        for (int t = 0; t < S; ++t) {
-            const int s = d0 + t - lo;
-            if ((unsigned)s < (unsigned)w)
-                vol[off + (uint32_t)s] = (uint8_t)((t & 1) ? (L[t >> 1] >> 16) : L[t >> 1]);
-        }
-    };
-    int i = 0;
-    for (; i + RM <= len; i += RM) {
-#pragma unroll
-        for (int u = 0; u < RM; ++u) {
-            step(u, u % PF);
-            load_bytes((u + PF) % RM, cb[u % PF]);
-            load_meta(u, (i + u + RM < len) ? p + RM * dp : p_last);
-            p += dp;
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < RM; ++u) {
-        if (i + u < len) {
-            step(u, u % PF);
-            if (u + PF < RM) load_bytes(u + PF, cb[u % PF]);
-            p += dp;
-        }
-    }
-}
-
 // ---- register scanline (ragged windows, one wave per scanline) ----
 // Lane j holds slot j + 64*k (chunk k < K) of the previous pixel's path
 // costs, counted from that pixel's window start lo_q.  Slots past a window
@@ -725,9 +660,9 @@ __device__ inline int lane_from(int v, int t) {
     return (unsigned)t < 64u ? r : kInf;
 }
 
-template <int K, int WM, int PF>
+template <int K, int WM, int PF, int RM = 2 * PF>
 __device__ inline void reg_scanline(const SgmLaunch& a, const Scan& sc, int lane, uint16_t* row) {
-    constexpr int RM = 2 * PF;
+    static_assert(RM % PF == 0 && RM >= 2 * PF, "ring sizes");
     constexpr int ROW = lds_row(64, K);
     const __amdgpu_buffer_rsrc_t vol =
         byte_buffer(a.vol + (size_t)sc.dir * a.vol_stride, (uint32_t)a.vol_stride);
@@ -736,44 +671,49 @@ __device__ inline void reg_scanline(const SgmLaunch& a, const Scan& sc, int lane
     const int dp = sc.dp, len = sc.len, p0 = sc.p0;
     const int p_last = p0 + (len - 1) * dp;
 
-    int mlo[RM], mw[RM];
-    uint32_t moff[RM];
-    auto load_meta = [&](int j, int pix) {
-        int hi;
-        window_of<WM>(a.win, pix, mlo[j], hi, moff[j]);
-        mw[j] = hi - mlo[j] + 1;
+    // Window words are loaded RM steps ahead (vector ring mm); when the
+    // costs of a pixel are requested, PF steps ahead, its word is moved to
+    // scalar registers (ring s_off / s_lw), which the step then uses.
+    uint64_t mm[RM];
+    uint32_t s_off[PF], s_lw[PF];
+    int cst[PF][K];
+    auto load_meta = [&](int j, int pix) { mm[j] = scan_meta<WM>(a, pix); };
+    auto load_cost = [&](int slot, int j) {
+        s_off[slot] = __builtin_amdgcn_readfirstlane((uint32_t)mm[j]);
+        s_lw[slot] = __builtin_amdgcn_readfirstlane((uint32_t)(mm[j] >> 32));
+        const int w = (int)(s_lw[slot] >> 16);
+        const gmem<uint8_t>* c = cost + s_off[slot];
+#pragma unroll
+        for (int k = 0; k < K; ++k) cst[slot][k] = c[min(lane + 64 * k, w - 1)];
     };
 #pragma unroll
     for (int j = 0; j < RM; ++j) load_meta(j, j < len ? p0 + j * dp : p_last);
-    int cst[PF][K];
 #pragma unroll
-    for (int j = 0; j < PF; ++j) load_costs<64, K>(cost, moff[j], mw[j], lane, cst[j]);
+    for (int j = 0; j < PF; ++j) load_cost(j, j);
 
     for (int e = lane; e < ROW; e += 64) row[e] = kInf;
     lds_order();
-    int lo_q = __builtin_amdgcn_readfirstlane(mlo[0]);
-    int w_q = __builtin_amdgcn_readfirstlane(mw[0]);
+    int lo_q = (int)(s_lw[0] & 0xffffu);
+    int w_q = (int)(s_lw[0] >> 16);
     int L[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) L[k] = lane + 64 * k < w_q ? 0 : kInf;   // zero predecessor
     int m_q = 0;
     int p = p0;
 
-    auto step = [&](int ti, int tc) {
-        const int lo_c = __builtin_amdgcn_readfirstlane(mlo[ti]);
-        const int w_c = __builtin_amdgcn_readfirstlane(mw[ti]);
-        const uint32_t off_c = __builtin_amdgcn_readfirstlane(moff[ti]);
+    auto step = [&](int tc) {
+        const int lo_c = (int)(s_lw[tc] & 0xffffu), w_c = (int)(s_lw[tc] >> 16);
+        const uint32_t off_c = s_off[tc];
         const int m2 = m_q + p2;
         int mn;
-        if (__builtin_expect(w_c <= 64 && w_q <= 64, 1)) {
-            const int dlt = lo_c - lo_q;
+        if (__builtin_expect((w_c <= 64) & (w_q <= 64), 1)) {
             int A, B, C;
-            if (__builtin_expect(dlt == 0, 1)) {
+            if (__builtin_expect(lo_c == lo_q, 1)) {
                 A = __builtin_amdgcn_update_dpp(kInf, L[0], 0x138, 0xF, 0xF, false);   // wave_shr:1
                 B = L[0];
                 C = __builtin_amdgcn_update_dpp(kInf, L[0], 0x130, 0xF, 0xF, false);   // wave_shl:1
             } else {
-                const int t = lane + dlt;
+                const int t = lane + (lo_c - lo_q);
                 A = lane_from(L[0], t - 1);
                 B = lane_from(L[0], t);
                 C = lane_from(L[0], t + 1);
@@ -815,8 +755,8 @@ __device__ inline void reg_scanline(const SgmLaunch& a, const Scan& sc, int lane
     for (; i + RM <= len; i += RM) {
 #pragma unroll
         for (int u = 0; u < RM; ++u) {
-            step(u, u % PF);
-            load_costs<64, K>(cost, moff[(u + PF) % RM], mw[(u + PF) % RM], lane, cst[u % PF]);
+            step(u % PF);
+            load_cost(u % PF, (u + PF) % RM);
             load_meta(u, (i + u + RM < len) ? p + RM * dp : p_last);
             p += dp;
         }
@@ -824,8 +764,97 @@ __device__ inline void reg_scanline(const SgmLaunch& a, const Scan& sc, int lane
 #pragma unroll
     for (int u = 0; u < RM; ++u) {
         if (i + u < len) {
-            step(u, u % PF);
-            if (u + PF < RM) load_costs<64, K>(cost, moff[u + PF], mw[u + PF], lane, cst[u % PF]);
+            step(u % PF);
+            if (u + PF < RM) load_cost(u % PF, u + PF);
+            p += dp;
+        }
+    }
+}
+
+// ---- windowed register scanline (ragged windows, branch-free steps) ----
+// One wave per scanline; lane l holds disparities 2*NP*l .. 2*NP*l+2*NP-1
+// of the whole range as packed u16 pairs (the full-range layout), so a step
+// never shifts lanes when the window moves.  Slots outside the pixel's
+// window take the marker cost kInf (packed_update keeps them out of every
+// minimum), costs are read with buffer loads clamped into the window, and
+// only in-window path costs are stored: the store offset of any other slot
+// is pushed out of the buffer's range, where the hardware drops it.  Every
+// step runs the same instructions, without a branch.  Window words: ring mm
+// (RM steps ahead), moved to scalar registers when the costs are requested
+// (PF steps ahead).
+template <int NP, int WM, int PF, int RM = 2 * PF>
+__device__ inline void win_scanline(const SgmLaunch& a, const Scan& sc, int lane) {
+    constexpr int S = 2 * NP;
+    static_assert(RM % PF == 0 && RM >= 2 * PF, "ring sizes");
+    const uint32_t span = (uint32_t)a.vol_stride;
+    const __amdgpu_buffer_rsrc_t vol = byte_buffer(a.vol + (size_t)sc.dir * a.vol_stride, span);
+    const __amdgpu_buffer_rsrc_t cbuf = byte_buffer(a.cost, span);
+    const int dp = sc.dp, len = sc.len, p0 = sc.p0;
+    const int p_last = p0 + (len - 1) * dp;
+    const uint32_t p1pk = (uint32_t)a.p1 * 0x10001u;
+    const int p2 = a.p2;
+    const uint32_t d0 = (uint32_t)(S * lane);
+
+    uint64_t mm[RM];
+    uint32_t s_off[PF], s_lw[PF];
+    uint32_t cb[PF][S];
+    auto load_meta = [&](int j, int pix) { mm[j] = scan_meta<WM>(a, pix); };
+    auto load_cost = [&](int slot, int j) {
+        s_off[slot] = __builtin_amdgcn_readfirstlane((uint32_t)mm[j]);
+        s_lw[slot] = __builtin_amdgcn_readfirstlane((uint32_t)(mm[j] >> 32));
+        const uint32_t lo = s_lw[slot] & 0xffffu, wm1 = (s_lw[slot] >> 16) - 1u;
+#pragma unroll
+        for (int t = 0; t < S; ++t)   // (unsigned) clamp: below or above the window -> inside it
+            cb[slot][t] = __builtin_amdgcn_raw_buffer_load_b8(cbuf, min(d0 + t - lo, wm1), s_off[slot], 0);
+    };
+#pragma unroll
+    for (int j = 0; j < RM; ++j) load_meta(j, j < len ? p0 + j * dp : p_last);
+#pragma unroll
+    for (int j = 0; j < PF; ++j) load_cost(j, j);
+
+    uint32_t L[NP];
+#pragma unroll
+    for (int r = 0; r < NP; ++r) L[r] = 0u;   // zero predecessor: the first step gives L = C
+    int m = 0;
+    int p = p0;
+    auto step = [&](int tc) {
+        const uint32_t lo = s_lw[tc] & 0xffffu, w = s_lw[tc] >> 16;
+        const uint32_t off = s_off[tc];
+        uint32_t sl[S];
+        bool in[S];
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            sl[t] = d0 + t - lo;
+            in[t] = sl[t] < w;
+        }
+        uint32_t c[NP];
+#pragma unroll
+        for (int r = 0; r < NP; ++r)
+            c[r] = (in[2 * r] ? (uint32_t)cb[tc][2 * r] : (uint32_t)kInf) |
+                   ((in[2 * r + 1] ? (uint32_t)cb[tc][2 * r + 1] : (uint32_t)kInf) << 16);
+        packed_update<64, NP>(L, c, m, p1pk, p2);
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            const uint32_t v = (t & 1) ? (L[t >> 1] >> 16) : L[t >> 1];
+            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)v, vol, in[t] ? off + sl[t] : kDropOffset, 0, 0);
+        }
+    };
+
+    int i = 0;
+    for (; i + RM <= len; i += RM) {
+#pragma unroll
+        for (int u = 0; u < RM; ++u) {
+            step(u % PF);
+            load_cost(u % PF, (u + PF) % RM);
+            load_meta(u, (i + u + RM < len) ? p + RM * dp : p_last);
+            p += dp;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < RM; ++u) {
+        if (i + u < len) {
+            step(u % PF);
+            if (u + PF < RM) load_cost(u % PF, u + PF);
             p += dp;
         }
     }
@@ -865,26 +894,24 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_full_kernel(SgmLaunch a, int
     packed_scanline_full<G, NP, PF>(a, scan_of(task, a.w, a.h), lane);
 }
 
-// Ragged windows, D = 2*NP*GP.  Blocks below n_packed_blocks take the first
-// scanline tasks (the rows, longest first) on windowed packed registers;
-// the other blocks take the remaining tasks through LDS rows (work
-// proportional to the window).  n_packed_blocks = 0: all LDS; covering all
-// tasks: all packed.
-template <int GP, int NP, int GL, int K, int PF>
+// Ragged windows.  Blocks below n_win_blocks take the first n_win_tasks
+// scanline tasks (the rows, longest first; or every task) one wave each on
+// windowed packed registers (D <= 128*NP); the other blocks take the rest
+// through LDS rows with GL lanes per scanline (work proportional to the
+// window).
+template <int NP, int GL, int K, int PF>
 __global__ __launch_bounds__(kBlock) void sgm_paths_ragged_kernel(SgmLaunch a, int n_tasks,
-                                                                   int n_packed_tasks,
-                                                                   int n_packed_blocks) {
-    if ((int)blockIdx.x < n_packed_blocks) {
-        constexpr int GPB = kBlock / GP;
-        const int grp = threadIdx.x / GP, lane = threadIdx.x % GP;
-        const int task = blockIdx.x * GPB + grp;
-        if (task >= n_packed_tasks) return;
-        packed_scanline_windowed<GP, NP, PF>(a, scan_of(task, a.w, a.h), lane);
+                                                                   int n_win_tasks, int n_win_blocks) {
+    if ((int)blockIdx.x < n_win_blocks) {
+        const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
+        const int task = (int)blockIdx.x * (kBlock / 64) + wv;
+        if (task >= n_win_tasks) return;
+        win_scanline<NP, kWinRagged, PF, 4 * PF>(a, scan_of(task, a.w, a.h), lane);
     } else {
         constexpr int GPB = kBlock / GL;
         __shared__ uint16_t lds[GPB][2][lds_row(GL, K)];
         const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
-        const int task = n_packed_tasks + (blockIdx.x - n_packed_blocks) * GPB + grp;
+        const int task = n_win_tasks + (blockIdx.x - n_win_blocks) * GPB + grp;
         if (task >= n_tasks) return;
         lds_scanline<GL, K, kWinRagged, PF>(a, scan_of(task, a.w, a.h), lane, lds[grp][0], lds[grp][1]);
     }
@@ -919,57 +946,126 @@ __device__ inline void select_segment(const SgmLaunch& a, int seg, int y) {
     __syncthreads();
     const gmem<uint8_t>* __restrict__ vol = gptr(a.vol);
     const size_t stride = a.vol_stride;
-    for (int i = grp; i < kSeg; i += GPB) {
-        const int x = x0 + i;
-        if (x >= W) break;
-        const int p = y * W + x;
-        int lo, hi;
-        uint32_t off;
-        window_of<WM>(a.win, p, lo, hi, off);
-        const int w = hi - lo + 1;
-        int kbest = 0x7fffffff;
+    // Pixels are taken NB at a time: their windows, then the path costs of
+    // their first PK chunks, are all requested before any is used, so a group
+    // waits for two memory latencies per NB pixels instead of per pixel.
+    constexpr int NPIX = kSeg / GPB;
+    constexpr int NB = NPIX < 4 ? NPIX : 4;
+    constexpr int PK = G == 16 ? 1 : (K < 2 ? K : 2);
+    for (int t0 = 0; t0 < NPIX; t0 += NB) {
+        uint64_t mt[NB];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int s = lane + G * k;
-            if (s < w) {
-                const int S = sum_paths(vol, stride, off + (uint32_t)s);
-                const int d = lo + s;
-                const int key = (S << 9) | d;
-                kbest = min(kbest, key);
-                sS[s] = (uint16_t)S;
-                if (a.agg) gptr(a.agg)[off + (uint32_t)s] = (uint16_t)S;
-                if (x - d >= 0) atomicMin(&keyR[i + (D - 1) - d], (uint32_t)key);
+        for (int b = 0; b < NB; ++b) {
+            const int x = min(x0 + grp + (t0 + b) * GPB, W - 1);   // past the row: not used
+            mt[b] = scan_meta<WM>(a, y * W + x);
+        }
+        int c[NB][PK][kNumPaths];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const uint32_t o = meta_off(mt[b]);
+            const int wb = meta_w(mt[b]);
+#pragma unroll
+            for (int k = 0; k < PK; ++k) {
+                const uint32_t j = o + (uint32_t)min(lane + G * k, max(wb - 1, 0));
+#pragma unroll
+                for (int r = 0; r < kNumPaths; ++r) c[b][k][r] = vol[(size_t)r * stride + j];
             }
         }
-        lds_order();
-        kbest = group_min<G>(kbest);
-        if (lane == 0) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int i = grp + (t0 + b) * GPB;
+            const int x = x0 + i;
+            if (x >= W) continue;
+            const int p = y * W + x;
+            const int lo = meta_lo(mt[b]);
+            const uint32_t off = meta_off(mt[b]);
+            const int hi = lo + meta_w(mt[b]) - 1;
+            const int w = hi - lo + 1;
+            int kbest = 0x7fffffff;
+            int S0 = 0;                      // this lane's S in chunk 0
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int s = lane + G * k;
+                if (s < w) {
+                    int S = 0;
+                    if (k < PK) {
+#pragma unroll
+                        for (int r = 0; r < kNumPaths; ++r) S += c[b][k < PK ? k : 0][r];
+                    } else {
+                        S = sum_paths(vol, stride, off + (uint32_t)s);
+                    }
+                    const int d = lo + s;
+                    const int key = (S << 9) | d;
+                    kbest = min(kbest, key);
+                    sS[s] = (uint16_t)S;
+                    if (k == 0) S0 = S;
+                    if (a.agg) gptr(a.agg)[off + (uint32_t)s] = (uint16_t)S;
+                    if (x - d >= 0) atomicMin(&keyR[i + (D - 1) - d], (uint32_t)key);
+                }
+            }
+            lds_order();
+            kbest = group_min<G>(kbest);
             const int ds = kbest & 511, sb = kbest >> 9;
             const int j0 = ds - lo;
-            float sub = (float)ds;
-            if (ds > lo && ds < hi) {
-                const int sa = sS[j0 - 1], sc = sS[j0 + 1];
-                const int den = sa - 2 * sb + sc;
-                if (den > 0) sub = (float)ds + (float)(sa - sc) / (float)(2 * den);
+            if (G == 16 && w <= 16) {
+                // Window in one 16-lane row: the walk of Eq. 9 in parallel.  The
+                // terms S - S_min are >= 0, so the running sums only grow and
+                // the serial walk's count equals the number of slots whose sum
+                // from the minimum outwards stays below S_max.  Q = inclusive
+                // prefix sum of the terms over the row (DPP row shifts).
+                const int e = lane < w ? S0 - sb : 0;
+                int q = e;
+                q += __builtin_amdgcn_update_dpp(0, q, 0x111, 0xF, 0xF, true);   // row_shr:1
+                q += __builtin_amdgcn_update_dpp(0, q, 0x112, 0xF, 0xF, true);   // row_shr:2
+                q += __builtin_amdgcn_update_dpp(0, q, 0x114, 0xF, 0xF, true);   // row_shr:4
+                q += __builtin_amdgcn_update_dpp(0, q, 0x118, 0xF, 0xF, true);   // row_shr:8
+                const int row0 = (int)(threadIdx.x & 63u) & ~15;
+                const int qa = __builtin_amdgcn_ds_bpermute((row0 + max(j0 - 1, 0)) << 2, q);
+                const int qb = __builtin_amdgcn_ds_bpermute((row0 + j0) << 2, q);
+                const int sa = __builtin_amdgcn_ds_bpermute((row0 + max(j0 - 1, 0)) << 2, S0);
+                const int sc = __builtin_amdgcn_ds_bpermute((row0 + min(j0 + 1, 15)) << 2, S0);
+                const bool left = lane < j0 && qa - q + e < a.s_max;
+                const bool right = lane > j0 && lane < w && q - qb < a.s_max;
+                const uint32_t sh = (uint32_t)row0;
+                const int n = __builtin_popcount((uint32_t)(__builtin_amdgcn_ballot_w64(left) >> sh) & 0xffffu) +
+                              __builtin_popcount((uint32_t)(__builtin_amdgcn_ballot_w64(right) >> sh) & 0xffffu);
+                if (lane == 0) {
+                    float sub = (float)ds;
+                    if (ds > lo && ds < hi) {
+                        const int den = sa - 2 * sb + sc;
+                        if (den > 0) sub = (float)ds + (float)(sa - sc) / (float)(2 * den);
+                    }
+                    gptr(a.disp_wta)[p] = (int16_t)ds;
+                    gptr(a.disp_sub)[p] = sub;
+                    gptr(a.var_meas)[p] = (float)n;
+                    if (a.wta_raw) gptr(a.wta_raw)[p] = (int16_t)ds;
+                }
+            } else if (lane == 0) {
+                float sub = (float)ds;
+                if (ds > lo && ds < hi) {
+                    const int sa = sS[j0 - 1], sc = sS[j0 + 1];
+                    const int den = sa - 2 * sb + sc;
+                    if (den > 0) sub = (float)ds + (float)(sa - sc) / (float)(2 * den);
+                }
+                int acc = 0, n = 0;
+                for (int j = 1; j0 - j >= 0; ++j) {
+                    acc += (int)sS[j0 - j] - sb;
+                    if (acc >= a.s_max) break;
+                    ++n;
+                }
+                acc = 0;
+                for (int j = 1; j0 + j < w; ++j) {
+                    acc += (int)sS[j0 + j] - sb;
+                    if (acc >= a.s_max) break;
+                    ++n;
+                }
+                gptr(a.disp_wta)[p] = (int16_t)ds;
+                gptr(a.disp_sub)[p] = sub;
+                gptr(a.var_meas)[p] = (float)n;
+                if (a.wta_raw) gptr(a.wta_raw)[p] = (int16_t)ds;
             }
-            int acc = 0, n = 0;
-            for (int j = 1; j0 - j >= 0; ++j) {
-                acc += (int)sS[j0 - j] - sb;
-                if (acc >= a.s_max) break;
-                ++n;
-            }
-            acc = 0;
-            for (int j = 1; j0 + j < w; ++j) {
-                acc += (int)sS[j0 + j] - sb;
-                if (acc >= a.s_max) break;
-                ++n;
-            }
-            gptr(a.disp_wta)[p] = (int16_t)ds;
-            gptr(a.disp_sub)[p] = sub;
-            gptr(a.var_meas)[p] = (float)n;
-            if (a.wta_raw) gptr(a.wta_raw)[p] = (int16_t)ds;
+            lds_order();
         }
-        lds_order();
     }
     __syncthreads();
     for (int i = threadIdx.x; i < kSeg + D - 1; i += kBlock) {
@@ -1318,11 +1414,12 @@ hipError_t launch_sgm_paths(const SgmLaunch& a, hipStream_t s) {
 #undef EGOSGM_LDSF
         return hipGetLastError();
     }
-    // ragged: the LDS kernel's lanes per scanline come from the tuning; the
-    // packed part (rows, or everything) uses 32 lanes over D rounded up to
-    // 64, 128 or 256.
+    // ragged: schedule 0 every scanline through LDS rows, 1 the rows on
+    // windowed registers and the rest through LDS, 2 every scanline on
+    // windowed registers, 3 every scanline on relative registers.  The LDS
+    // part takes its lanes per scanline from the tuning.
     const int g = a.ragged_group;
-    const int sched = a.ragged_schedule;   // 0: all LDS, 1: rows packed, 2: all packed, 3: registers
+    const int sched = a.ragged_schedule;
     if (sched == 3) {
         const unsigned nb = blocks(n_tasks, 64);
         if (D <= 64) sgm_paths_reg_kernel<1, 4><<<nb, kBlock, 0, s>>>(a, n_tasks);
@@ -1330,20 +1427,19 @@ hipError_t launch_sgm_paths(const SgmLaunch& a, hipStream_t s) {
         else sgm_paths_reg_kernel<4, 4><<<nb, kBlock, 0, s>>>(a, n_tasks);
         return hipGetLastError();
     }
-    const int n_packed = sched == 0 ? 0 : (sched == 1 ? 2 * a.h : n_tasks);
-#define EGOSGM_RAG(NP, GL, KK)                                                                 \
-    do {                                                                                       \
-        const int nb_p = blocks(n_packed, 32);                                                 \
-        const int nb = nb_p + blocks(n_tasks - n_packed, GL);                                  \
-        sgm_paths_ragged_kernel<32, NP, GL, KK, 4><<<nb, kBlock, 0, s>>>(a, n_tasks, n_packed, \
-                                                                          nb_p);               \
+    const int n_win = sched == 0 ? 0 : (sched == 1 ? 2 * a.h : n_tasks);
+#define EGOSGM_RAG(NP, GL, KK)                                                                   \
+    do {                                                                                         \
+        const int nb_w = blocks(n_win, 64);                                                      \
+        const int nb = nb_w + blocks(n_tasks - n_win, GL);                                       \
+        sgm_paths_ragged_kernel<NP, GL, KK, 4><<<nb, kBlock, 0, s>>>(a, n_tasks, n_win, nb_w);   \
     } while (0)
     if (D <= 64) {
         if (g == 16) EGOSGM_RAG(1, 16, 4); else if (g == 64) EGOSGM_RAG(1, 64, 1); else EGOSGM_RAG(1, 32, 2);
     } else if (D <= 128) {
-        if (g == 16) EGOSGM_RAG(2, 16, 8); else if (g == 32) EGOSGM_RAG(2, 32, 4); else EGOSGM_RAG(2, 64, 2);
+        if (g == 16) EGOSGM_RAG(1, 16, 8); else if (g == 32) EGOSGM_RAG(1, 32, 4); else EGOSGM_RAG(1, 64, 2);
     } else {
-        if (g == 16) EGOSGM_RAG(4, 16, 16); else if (g == 32) EGOSGM_RAG(4, 32, 8); else EGOSGM_RAG(4, 64, 4);
+        if (g == 16) EGOSGM_RAG(2, 16, 16); else if (g == 32) EGOSGM_RAG(2, 32, 8); else EGOSGM_RAG(2, 64, 4);
     }
 #undef EGOSGM_RAG
     return hipGetLastError();

@@ -94,7 +94,7 @@ class Tuning(C.Structure):
                 ("ragged_schedule", C.c_int32), ("batch_group", C.c_int32)]
 
 
-DEFAULT_TUNING = dict(full_group=64, ragged_group=64, ragged_schedule=0, batch_group=16)
+DEFAULT_TUNING = dict(full_group=64, ragged_group=32, ragged_schedule=1, batch_group=16)
 
 
 def set_tuning(full_group: int = 64, ragged_group: int = 64, ragged_schedule: int = 0,

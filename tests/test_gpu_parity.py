@@ -129,6 +129,26 @@ def test_sgm_reduced_ragged(w, h, D, seed, kind, rmax, sched):
     _check_sgm(g, o, int(wo[2][-1]))
 
 
+@pytest.mark.parametrize("s_max", [0, 7, 80, 600])
+@pytest.mark.parametrize("rmax,D", [(7, 64), (12, 128), (40, 128)])
+def test_selection_walk_every_pixel(s_max, rmax, D):
+    """Left-right check off, so the uncertainty count and subpixel of every
+    pixel are compared; windows up to 15 slots take the parallel walk, wider
+    ones the serial one."""
+    _say("selection walk, s_max", s_max, "rmax", rmax, "D", D)
+    w, h = 83, 21
+    left, right = _random_pair(w, h, seed=s_max + rmax, max_shift=min(D - 1, 30))
+    d, p = _random_windows(w, h, D, seed=rmax + 5, rmax=rmax, kind="smooth", frac_full=0.05)
+    wo = orc.windows(d, p, D, r_min=0, r_max=rmax)
+    lo, hi, off = (_gpu(wo[0].reshape(h, w)), _gpu(wo[1].reshape(h, w)), _gpu(wo[2].view(np.int32)))
+    prm = eg.MatchParams(max_disp=D, p1=10, p2=120, s_max=s_max, lr_tol=-1)
+    g = eg.sgm_reduced(_gpu(left), _gpu(right), lo, hi, off, prm)
+    o = orc.sgm(left, right, D, p1=10, p2=120, s_max=s_max, lr_tol=-1, windows=wo)
+    assert np.array_equal(_np(g["disp_wta"]), o["disp_wta"])
+    assert np.array_equal(_np(g["var_meas"]).astype(np.float64), o["var_meas"])
+    assert np.abs(_np(g["disp_sub"]).astype(np.float64) - o["disp_sub"]).max() <= TOL
+
+
 @pytest.mark.parametrize("D", [48, 128])
 def test_sgm_reduced_full_windows_equal_full(D):
     _say("reduced == full, 120x40", D)
