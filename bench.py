@@ -55,13 +55,14 @@ def build_sequence(n_frames, w, h, device):
     import torch
     from paper_1708_06301_amd import pipeline, synth
     seq = synth.street_sequence(w, h, n_frames, seed=synth.seed_for(1))
-    frames = []
+    frames, gts = [], []
     t0 = time.time()
     for k in range(n_frames):
-        left, right, _ = seq.frame(k, device=device)
+        left, right, gt = seq.frame(k, device=device)
         frames.append((torch.from_numpy(left).to(device), torch.from_numpy(right).to(device)))
+        gts.append(gt)
     log(f"rendered {n_frames} frames {w}x{h} in {time.time() - t0:.1f}s")
-    return seq, frames, pipeline.motions(seq)
+    return seq, frames, pipeline.motions(seq), gts
 
 
 def run_sequence(state, frames, motions, events=None, stage_timing=False):
@@ -269,6 +270,30 @@ def batch_section(dev, n_pairs, steps, log):
     return out
 
 
+def quality_section(red, full, frames, motions, gts, max_disp):
+    """Bad-pixel rates against the renderer's ground truth (Sec. 3's metric):
+    plain full-range SGM on every frame, the reduced pipeline's own
+    measurement, and its Kalman-filtered map D^k; frames 1.. (frame 0 is
+    the same full-range match for all three)."""
+    import torch
+    from paper_1708_06301_amd.quality import bad_pixels, summarise
+    out = {"full_sgm": [], "reduced_measurement": [], "reduced_filtered": []}
+    red.reset()
+    full.reset()
+    for k, (L, R) in enumerate(frames):
+        Rm, t = motions[k] if k > 0 else (None, None)
+        d_red, _ = red.step(L, R, Rm, t)
+        d_full, _ = full.step(L, R, Rm, t)
+        torch.cuda.synchronize()
+        if k == 0:
+            continue
+        out["full_sgm"].append(bad_pixels(full.out["disp_sub"], gts[k], max_disp))
+        out["reduced_measurement"].append(bad_pixels(red.out["disp_sub"], gts[k], max_disp))
+        out["reduced_filtered"].append(bad_pixels(d_red, gts[k], max_disp))
+    return {"frames": f"1..{len(frames) - 1}", "threshold": "3 px or/and 5% of the true disparity",
+            **{k: summarise(v) for k, v in out.items()}}
+
+
 def serve_section(dev, n_frames, log, budget_gib=32.0):
     """16 camera streams (8 at 1242x375 D=128, 8 at 640x192 D=64), n_frames
     synthetic street frames each, arriving at 30 fps with Poisson jitter,
@@ -397,7 +422,7 @@ def main():
         return 0
     eg.lib()
     w, h, nf = args.width, args.height, args.frames
-    seq, frames, motions = build_sequence(nf, w, h, dev)
+    seq, frames, motions, gts = build_sequence(nf, w, h, dev)
     calib = pipeline.camera_of(seq)
     cfg = pipeline.FrameConfig(max_disp=128, p1=10, p2=120, s_max=80, lr_tol=1, q=0.5,
                                r_fixed=4, r_min=0, r_max=256, edge_tol=2.0, fill_tol=1.0)
@@ -502,6 +527,7 @@ def main():
         "roofline": roof,
         "tuning": tuning,
     }
+    out["quality"] = quality_section(red, full, frames, motions, gts, cfg.max_disp)
     if not args.no_batch:
         out["batched"] = batch_section(dev, args.batch_pairs, args.steps, log)
     if not args.no_serve:
