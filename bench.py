@@ -485,7 +485,8 @@ def main():
             kname = f"sgm_paths_reg_kernel<{1 if D <= 64 else (2 if D <= 128 else 4)}, 4>"
         else:
             dr = 64 if D <= 64 else (128 if D <= 128 else 256)
-            kname = f"sgm_paths_ragged_kernel<{1 if D <= 128 else 2}, {g}, {dr // g}, 4>"
+            kname = (f"sgm_paths_ragged_kernel<{tuning['ragged_schedule']}, {1 if D <= 128 else 2}, {g}, "
+                     f"{dr // g}, 4>")
     elif dom == "select":
         kname = f"sgm_select_kernel<16, {max(1, cfg.max_disp // 16)}, false>"
     if alg_bytes is not None:

@@ -36,6 +36,14 @@ __device__ inline gmem<T>* gptr(T* p) {
     return (gmem<T>*)p;
 }
 
+// Raw buffer over n bytes: stores at offsets >= n are discarded by the
+// hardware, which masks a store without a branch.  Word 3 is the gfx9
+// family's raw-buffer format word.
+__device__ inline __amdgpu_buffer_rsrc_t byte_buffer(void* base, uint32_t n) {
+    return __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)n, 0x00020000);
+}
+constexpr uint32_t kDropOffset = 0xffffffffu;
+
 // One 64x4 output tile of one image; clear (nullable) gets 0xffffffff per
 // pixel (the right-map keys of the matcher, reset here so that no memset is
 // needed in a captured graph).
@@ -333,15 +341,15 @@ __device__ inline void dir_step(int dir, int& dx, int& dy) {
     dy = (dir == 2 || dir == 4 || dir == 5) ? 1 : ((dir == 3 || dir == 6 || dir == 7) ? -1 : 0);
 }
 
-// Costs of this lane's slots s = lane + G*k of one pixel's window.
+// Costs of this lane's slots s = lane + G*k of one pixel's window (clamped
+// into the window), through a raw buffer.  The window offset differs
+// between the lane groups of a wave, so it goes into the per-lane offset.
 template <int G, int K>
-__device__ inline void load_costs(const gmem<uint8_t>* __restrict__ cost, uint32_t off, int w, int lane,
-                                  int (&c)[K]) {
+__device__ inline void load_costs_buf(__amdgpu_buffer_rsrc_t cbuf, uint32_t off, int w, int lane,
+                                      int (&c)[K]) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int s = lane + G * k;
-        c[k] = (int)cost[off + (uint32_t)min(s, w - 1)];
-    }
+    for (int k = 0; k < K; ++k)
+        c[k] = __builtin_amdgcn_raw_buffer_load_b8(cbuf, off + (uint32_t)min(lane + G * k, w - 1), 0, 0);
 }
 
 // A scanline task: direction, first pixel, pixel step and length.
@@ -386,8 +394,11 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
                                     uint16_t* b0, uint16_t* b1) {
     constexpr int RM = 2 * PF;
     constexpr int ROW = lds_row(G, K);
+    // The cost buffer is the same for every lane group of the wave; the path
+    // volume is not (groups walk different directions), so it stays a global
+    // pointer.
     gmem<uint8_t>* __restrict__ vol = gptr(a.vol + (size_t)sc.dir * a.vol_stride);
-    const gmem<uint8_t>* __restrict__ cost = gptr(a.cost);
+    const __amdgpu_buffer_rsrc_t cbuf = byte_buffer(a.cost, (uint32_t)a.vol_stride);
     const int p1 = a.p1, p2 = a.p2;
     const int dp = sc.dp, len = sc.len, p0 = sc.p0;
     const int p_last = p0 + (len - 1) * dp;
@@ -398,7 +409,7 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
     for (int j = 0; j < RM; ++j) load_meta(j, j < len ? p0 + j * dp : p_last);
     int cst[PF][K];
 #pragma unroll
-    for (int j = 0; j < PF; ++j) load_costs<G, K>(cost, meta_off(mm[j]), meta_w(mm[j]), lane, cst[j]);
+    for (int j = 0; j < PF; ++j) load_costs_buf<G, K>(cbuf, meta_off(mm[j]), meta_w(mm[j]), lane, cst[j]);
 
     for (int e = lane; e < ROW; e += G) {
         b0[e] = kInf;
@@ -459,7 +470,7 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
 #pragma unroll
         for (int u = 0; u < RM; ++u) {
             step(u, u % PF, u & 1);
-            load_costs<G, K>(cost, meta_off(mm[(u + PF) % RM]), meta_w(mm[(u + PF) % RM]), lane,
+            load_costs_buf<G, K>(cbuf, meta_off(mm[(u + PF) % RM]), meta_w(mm[(u + PF) % RM]), lane,
                              cst[u % PF]);
             load_meta(u, (i + u + RM < len) ? p + RM * dp : p_last);
             p += dp;
@@ -470,7 +481,7 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
         if (i + u < len) {
             step(u, u % PF, u & 1);
             if (u + PF < RM)
-                load_costs<G, K>(cost, meta_off(mm[u + PF]), meta_w(mm[u + PF]), lane, cst[u % PF]);
+                load_costs_buf<G, K>(cbuf, meta_off(mm[u + PF]), meta_w(mm[u + PF]), lane, cst[u % PF]);
             p += dp;
         }
     }
@@ -647,13 +658,6 @@ __device__ inline void packed_scanline_full(const SgmLaunch& a, const Scan& sc, 
 // wider window goes through an LDS row indexed by absolute disparity (entry
 // d+1, +infinity outside the written range, erased after use), as in
 // lds_scanline.  Every branch depends on wave-uniform values only.
-// Raw buffer over n bytes: stores at offsets >= n are discarded by the
-// hardware, which masks a store without a branch.  Word 3 is the gfx9
-// family's raw-buffer format word.
-__device__ inline __amdgpu_buffer_rsrc_t byte_buffer(void* base, uint32_t n) {
-    return __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)n, 0x00020000);
-}
-constexpr uint32_t kDropOffset = 0xffffffffu;
 
 __device__ inline int lane_from(int v, int t) {
     const int r = __builtin_amdgcn_ds_bpermute(t << 2, v);
@@ -894,12 +898,13 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_full_kernel(SgmLaunch a, int
     packed_scanline_full<G, NP, PF>(a, scan_of(task, a.w, a.h), lane);
 }
 
-// Ragged windows.  Blocks below n_win_blocks take the first n_win_tasks
+// Ragged windows (SCHED names the ragged schedule, 0-2, so each has its own
+// kernel symbol).  Blocks below n_win_blocks take the first n_win_tasks
 // scanline tasks (the rows, longest first; or every task) one wave each on
 // windowed packed registers (D <= 128*NP); the other blocks take the rest
 // through LDS rows with GL lanes per scanline (work proportional to the
 // window).
-template <int NP, int GL, int K, int PF>
+template <int SCHED, int NP, int GL, int K, int PF>
 __global__ __launch_bounds__(kBlock) void sgm_paths_ragged_kernel(SgmLaunch a, int n_tasks,
                                                                    int n_win_tasks, int n_win_blocks) {
     if ((int)blockIdx.x < n_win_blocks) {
@@ -1428,11 +1433,16 @@ hipError_t launch_sgm_paths(const SgmLaunch& a, hipStream_t s) {
         return hipGetLastError();
     }
     const int n_win = sched == 0 ? 0 : (sched == 1 ? 2 * a.h : n_tasks);
-#define EGOSGM_RAG(NP, GL, KK)                                                                   \
-    do {                                                                                         \
-        const int nb_w = blocks(n_win, 64);                                                      \
-        const int nb = nb_w + blocks(n_tasks - n_win, GL);                                       \
-        sgm_paths_ragged_kernel<NP, GL, KK, 4><<<nb, kBlock, 0, s>>>(a, n_tasks, n_win, nb_w);   \
+#define EGOSGM_RAG(NP, GL, KK)                                                                      \
+    do {                                                                                            \
+        const int nb_w = blocks(n_win, 64);                                                         \
+        const int nb = nb_w + blocks(n_tasks - n_win, GL);                                          \
+        if (sched == 0)                                                                             \
+            sgm_paths_ragged_kernel<0, NP, GL, KK, 4><<<nb, kBlock, 0, s>>>(a, n_tasks, n_win, nb_w); \
+        else if (sched == 1)                                                                        \
+            sgm_paths_ragged_kernel<1, NP, GL, KK, 4><<<nb, kBlock, 0, s>>>(a, n_tasks, n_win, nb_w); \
+        else                                                                                        \
+            sgm_paths_ragged_kernel<2, NP, GL, KK, 4><<<nb, kBlock, 0, s>>>(a, n_tasks, n_win, nb_w); \
     } while (0)
     if (D <= 64) {
         if (g == 16) EGOSGM_RAG(1, 16, 4); else if (g == 64) EGOSGM_RAG(1, 64, 1); else EGOSGM_RAG(1, 32, 2);
