@@ -389,3 +389,39 @@ def test_plan_graph_replays_and_window_updates():
     assert _same(plan.outputs[1], ref) is None
     del x
     plan.close()
+
+
+# ---------------------------------------------------------------- full size
+def test_street_frames_full_size_default_launch():
+    """1242x375, D=128 in the default launch tuning (the bench's): frame 0
+    over the full range and frame 1 through the pipeline's prediction,
+    refinement and r=4 windows; the oracle gets the GPU's refined
+    prediction, so windows and matcher outputs must agree exactly."""
+    from paper_1708_06301_amd import pipeline
+    _say("street frames 1242x375 D=128, default tuning")
+    eg.set_tuning(**eg.DEFAULT_TUNING)
+    w, h, D = 1242, 375, 128
+    seq = synth.street_sequence(w, h, 2, seed=synth.seed_for(1))
+    (L0, R0, _), (L1, R1, _) = seq.frame(0, device=DEV), seq.frame(1, device=DEV)
+    cfg = pipeline.FrameConfig(max_disp=D, r_fixed=4)
+    st = pipeline.StreamState(w, h, pipeline.camera_of(seq), cfg, DEV)
+    st.step(_gpu(L0), _gpu(R0))
+    torch.cuda.synchronize()
+    o0 = orc.sgm(L0, R0, D, p1=cfg.p1, p2=cfg.p2, s_max=cfg.s_max, lr_tol=cfg.lr_tol)
+    assert np.array_equal(_np(st.out["disp_wta"]), o0["disp_wta"])
+    assert np.array_equal(_np(st.out["disp_right"]), o0["disp_right"])
+    assert np.array_equal(_np(st.out["var_meas"]).astype(np.float64), o0["var_meas"])
+    assert np.abs(_np(st.out["disp_sub"]).astype(np.float64) - o0["disp_sub"]).max() <= TOL
+    Rm, t = (np.asarray(a, np.float64) for a in seq.motion(1))
+    win = st.predict(Rm, t)
+    st.match(_gpu(L1), _gpu(R1), win)
+    torch.cuda.synchronize()
+    wo = orc.windows(_np(st.d_pred), _np(st.p_pred), D, r_fixed=4, r_min=cfg.r_min, r_max=cfg.r_max)
+    assert np.array_equal(_np(win[0]).ravel(), wo[0])
+    assert np.array_equal(_np(win[1]).ravel(), wo[1])
+    assert np.array_equal(_np(win[2]).view(np.uint32), wo[2])
+    o1 = orc.sgm(L1, R1, D, p1=cfg.p1, p2=cfg.p2, s_max=cfg.s_max, lr_tol=cfg.lr_tol, windows=wo)
+    assert np.array_equal(_np(st.out["disp_wta"]), o1["disp_wta"])
+    assert np.array_equal(_np(st.out["disp_right"]), o1["disp_right"])
+    assert np.array_equal(_np(st.out["var_meas"]).astype(np.float64), o1["var_meas"])
+    assert np.abs(_np(st.out["disp_sub"]).astype(np.float64) - o1["disp_sub"]).max() <= TOL
