@@ -66,6 +66,8 @@ typedef struct egosgm_sgm_params {
     int32_t p2;       /* penalty for larger changes, p2 <= 255 - 62 = 193      */
     int32_t s_max;    /* uncertainty threshold of Eq. 9, >= 0                  */
     int32_t lr_tol;   /* left-right tolerance in pixels; < 0 disables the check */
+    int32_t n_paths;  /* aggregated directions: 8 (0 means 8), or 4 for the cheaper
+                         variant along and against the rows and the columns       */
 } egosgm_sgm_params;
 
 /* Optional intermediate outputs for inspection (each member nullable; the

@@ -286,13 +286,14 @@ int orc_lr_check(const int16_t* disp_right, int w, int h, int lr_tol, int16_t* d
 
 int orc_sgm(const uint8_t* left, const uint8_t* right, int w, int h, int max_disp,
             const int16_t* lo_in, const int16_t* hi_in, const uint32_t* off_in,
-            int p1, int p2, int s_max, int lr_tol,
+            int p1, int p2, int s_max, int lr_tol, int n_paths,
             uint64_t* census_l, uint64_t* census_r,
             int32_t* cost_out, int32_t* paths_out, int32_t* agg_out,
             int16_t* wta_raw, int16_t* disp_wta, double* disp_sub,
             double* var_meas, int16_t* disp_right) {
     if (!left || !right || !disp_wta || w <= 0 || h <= 0) return -1;
     if (max_disp < 1 || max_disp > 256 || p1 < 0 || p2 < p1) return -1;
+    if (n_paths != 4 && n_paths != 8) return -1;
     if ((lo_in == NULL) != (hi_in == NULL) || (lo_in == NULL) != (off_in == NULL)) return -1;
     const size_t n = (size_t)w * (size_t)h;
     int rc = -2;
@@ -332,8 +333,10 @@ int orc_sgm(const uint8_t* left, const uint8_t* right, int w, int h, int max_dis
     orc_cost_volume(cl, cr, w, h, lo, hi, off, cost);
     if (cost_out) memcpy(cost_out, cost, total * sizeof(int32_t));
 
-    /* Aggregation: S(p,d) is the sum of the eight path costs. */
-    for (int dir = 0; dir < 8; ++dir) {
+    /* Aggregation: S(p,d) is the sum of the path costs over the directions
+     * used: all eight, or the four axis-aligned ones (0-3: along and against
+     * the rows and the columns) of the cheaper 4-path variant. */
+    for (int dir = 0; dir < n_paths; ++dir) {
         rc = orc_path(cost, w, h, lo, hi, off, p1, p2, dir, L);
         if (rc) goto done;
         for (size_t i = 0; i < total; ++i) S[i] += L[i];

@@ -68,12 +68,13 @@ int orc_right_map(const int32_t* S, int w, int h, int max_disp, const int16_t* l
 int orc_lr_check(const int16_t* disp_right, int w, int h, int lr_tol, int16_t* disp_wta,
                  double* disp_sub, double* var_meas);
 
-/* Whole matcher: census, cost, 8 paths, aggregation, WTA, subpixel,
- * uncertainty, right disparity map and left-right check.  lo/hi/off NULL
- * means full range.  Every output except disp_wta may be NULL. */
+/* Whole matcher: census, cost, n_paths (8, or 4 = directions 0-3) paths,
+ * aggregation, WTA, subpixel, uncertainty, right disparity map and
+ * left-right check.  lo/hi/off NULL means full range.  Every output except
+ * disp_wta may be NULL; paths_out holds n_paths volumes. */
 int orc_sgm(const uint8_t* left, const uint8_t* right, int w, int h, int max_disp,
             const int16_t* lo, const int16_t* hi, const uint32_t* off,
-            int p1, int p2, int s_max, int lr_tol,
+            int p1, int p2, int s_max, int lr_tol, int n_paths,
             uint64_t* census_l, uint64_t* census_r,
             int32_t* cost_out, int32_t* paths_out, int32_t* agg_out,
             int16_t* wta_raw, int16_t* disp_wta, double* disp_sub,

@@ -120,8 +120,9 @@ def pixel_epilogue(S_row, lo, hi, s_max):
 
 
 def sgm(left, right, max_disp, p1=10, p2=120, s_max=80, lr_tol=1, windows=None,
-        want_debug=False):
-    """Runs the whole matcher.  windows = (lo, hi, off) or None for full range.
+        want_debug=False, n_paths=8):
+    """Runs the whole matcher.  windows = (lo, hi, off) or None for full range;
+    n_paths 8, or 4 (directions 0-3).
 
     Returns a dict with disp_wta (int16, -1 invalid), disp_sub (float64),
     var_meas (float64), disp_right (int16), wta_raw (before the LR check) and,
@@ -144,10 +145,10 @@ def sgm(left, right, max_disp, p1=10, p2=120, s_max=80, lr_tol=1, windows=None,
     dbg = {}
     if want_debug:
         dbg = dict(census_l=np.zeros((h, w), np.uint64), census_r=np.zeros((h, w), np.uint64),
-                   cost=np.zeros(total, np.int32), paths=np.zeros((8, total), np.int32),
+                   cost=np.zeros(total, np.int32), paths=np.zeros((n_paths, total), np.int32),
                    agg=np.zeros(total, np.int32))
     rc = lib().orc_sgm(_p(left), _p(right), w, h, max_disp, _p(lo), _p(hi), _p(off),
-                       p1, p2, s_max, lr_tol,
+                       p1, p2, s_max, lr_tol, n_paths,
                        _p(dbg.get("census_l")), _p(dbg.get("census_r")), _p(dbg.get("cost")),
                        _p(dbg.get("paths")), _p(dbg.get("agg")),
                        _p(r["wta_raw"]), _p(r["disp_wta"]), _p(r["disp_sub"]),

@@ -98,6 +98,7 @@ int check_params(const egosgm_sgm_params* prm) {
     if (!prm) return EGOSGM_EINVAL;
     if (prm->p1 < 0 || prm->p2 < prm->p1 || prm->p2 > 255 - kCensusBits) return EGOSGM_EINVAL;
     if (prm->s_max < 0) return EGOSGM_EINVAL;
+    if (prm->n_paths != 0 && prm->n_paths != 4 && prm->n_paths != 8) return EGOSGM_EINVAL;
     return EGOSGM_OK;
 }
 
@@ -129,6 +130,7 @@ int run_sgm(const uint8_t* left, const uint8_t* right, int w, int h, int pitch, 
     a.p2 = prm->p2;
     a.s_max = prm->s_max;
     a.lr_tol = prm->lr_tol;
+    a.n_paths = prm->n_paths == 4 ? 4 : 8;
     {
         std::lock_guard<std::mutex> g(g_tuning_mu);
         a.full_group = g_tuning.full_group;
@@ -288,6 +290,7 @@ int sgm_plan_create(const egosgm_pair* pairs, int n, const egosgm_sgm_params* pa
         a.p2 = prm.p2;
         a.s_max = prm.s_max;
         a.lr_tol = prm.lr_tol;
+        a.n_paths = prm.n_paths == 4 ? 4 : 8;
         a.disp_wta = q.disp_wta;
         a.disp_sub = q.disp_sub;
         a.var_meas = q.var_meas;
@@ -309,7 +312,7 @@ int sgm_plan_create(const egosgm_pair* pairs, int n, const egosgm_sgm_params* pa
     for (int cls = 0; cls < 3; ++cls)
         for (int i = 0; i < n; ++i) {
             const int w = pairs[i].w, h = pairs[i].h;
-            const int cnt = cls == 0 ? 2 * h : (cls == 1 ? 2 * w : 4 * (w + h - 1));
+            const int cnt = cls == 0 ? 2 * h : (cls == 1 ? 2 * w : (prm.n_paths == 4 ? 0 : 4 * (w + h - 1)));
             ts[r] = (int)tasks;
             tp[r] = i;
             tl[r] = cls == 0 ? 0 : (cls == 1 ? 2 * h : 2 * h + 2 * w);
@@ -346,6 +349,7 @@ int sgm_plan_create(const egosgm_pair* pairs, int n, const egosgm_sgm_params* pa
         t.group = g_tuning.batch_group;
     }
     t.n = n;
+    t.n_paths = prm.n_paths == 4 ? 4 : 8;
     t.n_ranges = P.n_ranges;
     t.n_tasks = (int)tasks;
     t.host_census_blocks = (int)tiles;

@@ -30,6 +30,7 @@ struct SgmLaunch {
     int w, h;
     Windows win;
     int p1, p2, s_max, lr_tol;
+    int n_paths;             // aggregated directions: 8, or 4 (directions 0-3)
     int full_group;          // lanes per scanline, full-range path kernel (16, 32, 64)
     int ragged_group;        // lanes per scanline, ragged path kernel (16, 32, 64)
     int ragged_schedule;     // 0: all scanlines via LDS, 1: rows on packed registers, 2: all packed
@@ -77,6 +78,7 @@ struct BatchTables {
     const int* task_count;      // n_ranges: real tasks of each range (the rest is padding)
     int n, n_ranges, n_tasks;
     int group;                  // lanes per scanline of the path kernel (16, 32, 64)
+    int n_paths;                // 8, or 4 (no diagonal tasks, 4 volumes summed)
     int host_census_blocks, host_seg_blocks, host_pixels;
 };
 

@@ -923,10 +923,11 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_ragged_kernel(SgmLaunch a, i
 }
 
 // ------------------------------------------------------------------ selection
+template <int NPATH>
 __device__ inline int sum_paths(const gmem<uint8_t>* __restrict__ vol, size_t stride, uint32_t j) {
     int s = 0;
 #pragma unroll
-    for (int r = 0; r < kNumPaths; ++r) s += vol[(size_t)r * stride + j];
+    for (int r = 0; r < NPATH; ++r) s += vol[(size_t)r * stride + j];
     return s;
 }
 
@@ -937,7 +938,7 @@ __device__ inline int sum_paths(const gmem<uint8_t>* __restrict__ vol, size_t st
 // then one global atomicMin per touched right pixel.  The pixel's S row is
 // kept in LDS for the parabola and the uncertainty walk.  Results before the
 // left-right check go to disp_wta / disp_sub / var_meas.
-template <int G, int K, int WM>
+template <int G, int K, int WM, int NPATH>
 __device__ inline void select_segment(const SgmLaunch& a, int seg, int y) {
     constexpr int GPB = kBlock / G;
     __shared__ uint32_t keyR[kSeg + kMaxDisp];
@@ -964,7 +965,7 @@ __device__ inline void select_segment(const SgmLaunch& a, int seg, int y) {
             const int x = min(x0 + grp + (t0 + b) * GPB, W - 1);   // past the row: not used
             mt[b] = scan_meta<WM>(a, y * W + x);
         }
-        int c[NB][PK][kNumPaths];
+        int c[NB][PK][NPATH];
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const uint32_t o = meta_off(mt[b]);
@@ -973,7 +974,7 @@ __device__ inline void select_segment(const SgmLaunch& a, int seg, int y) {
             for (int k = 0; k < PK; ++k) {
                 const uint32_t j = o + (uint32_t)min(lane + G * k, max(wb - 1, 0));
 #pragma unroll
-                for (int r = 0; r < kNumPaths; ++r) c[b][k][r] = vol[(size_t)r * stride + j];
+                for (int r = 0; r < NPATH; ++r) c[b][k][r] = vol[(size_t)r * stride + j];
             }
         }
 #pragma unroll
@@ -995,9 +996,9 @@ __device__ inline void select_segment(const SgmLaunch& a, int seg, int y) {
                     int S = 0;
                     if (k < PK) {
 #pragma unroll
-                        for (int r = 0; r < kNumPaths; ++r) S += c[b][k < PK ? k : 0][r];
+                        for (int r = 0; r < NPATH; ++r) S += c[b][k < PK ? k : 0][r];
                     } else {
-                        S = sum_paths(vol, stride, off + (uint32_t)s);
+                        S = sum_paths<NPATH>(vol, stride, off + (uint32_t)s);
                     }
                     const int d = lo + s;
                     const int key = (S << 9) | d;
@@ -1082,9 +1083,9 @@ __device__ inline void select_segment(const SgmLaunch& a, int seg, int y) {
     }
 }
 
-template <int G, int K, int WM>
+template <int G, int K, int WM, int NPATH>
 __global__ __launch_bounds__(kBlock) void sgm_select_kernel(SgmLaunch a) {
-    select_segment<G, K, WM>(a, blockIdx.x, blockIdx.y);
+    select_segment<G, K, WM, NPATH>(a, blockIdx.x, blockIdx.y);
 }
 
 // Right map and left-right check (in place on the selection's outputs).
@@ -1184,14 +1185,14 @@ __global__ __launch_bounds__(kBlock) void paths_batch_kernel(BatchTables t) {
                                     lds[grp][1]);
 }
 
-template <int K>
+template <int K, int NPATH>
 __global__ __launch_bounds__(kBlock) void select_batch_kernel(BatchTables t) {
     const int i = last_leq(t.seg_prefix, t.n, (int)blockIdx.x);
     const SgmLaunch a = pair_of(t, i);
     if (!a.active) return;
     const int local = (int)blockIdx.x - t.seg_prefix[i];
     const int segs_x = (a.w + kSeg - 1) / kSeg;
-    select_segment<16, K, kWinAny>(a, local % segs_x, local / segs_x);
+    select_segment<16, K, kWinAny, NPATH>(a, local % segs_x, local / segs_x);
 }
 
 __global__ __launch_bounds__(kBlock) void lr_batch_kernel(BatchTables t) {
@@ -1391,7 +1392,7 @@ hipError_t launch_sgm_cost(const SgmLaunch& a, hipStream_t s) {
 }
 
 hipError_t launch_sgm_paths(const SgmLaunch& a, hipStream_t s) {
-    const int n_tasks = 2 * a.h + 2 * a.w + 4 * (a.w + a.h - 1);
+    const int n_tasks = 2 * a.h + 2 * a.w + (a.n_paths == 4 ? 0 : 4 * (a.w + a.h - 1));
     const int D = a.win.max_disp;
     const bool full = a.win.lo == nullptr;
     auto blocks = [&](int n, int G) { return (n + kBlock / G - 1) / (kBlock / G); };
@@ -1459,7 +1460,11 @@ hipError_t launch_sgm_select(const SgmLaunch& a, hipStream_t s) {
     const int D = a.win.max_disp;
     const bool full = a.win.lo == nullptr;
     dim3 grid((a.w + kSeg - 1) / kSeg, a.h);
-#define EGOSGM_SEL(GG, KK, FF) sgm_select_kernel<GG, KK, FF><<<grid, kBlock, 0, s>>>(a)
+#define EGOSGM_SEL(GG, KK, FF)                                            \
+    do {                                                                  \
+        if (a.n_paths == 4) sgm_select_kernel<GG, KK, FF, 4><<<grid, kBlock, 0, s>>>(a); \
+        else sgm_select_kernel<GG, KK, FF, 8><<<grid, kBlock, 0, s>>>(a);               \
+    } while (0)
     if (full) {
         if (D <= 64) EGOSGM_SEL(64, 1, kWinFull);
         else if (D <= 128) EGOSGM_SEL(64, 2, kWinFull);
@@ -1526,10 +1531,16 @@ hipError_t launch_batch_stage(const BatchTables& t, int max_disp, int stage, hip
             break;
         }
         case 3:
-            if (max_disp <= 16) select_batch_kernel<1><<<t.host_seg_blocks, kBlock, 0, s>>>(t);
-            else if (max_disp <= 64) select_batch_kernel<4><<<t.host_seg_blocks, kBlock, 0, s>>>(t);
-            else if (max_disp <= 128) select_batch_kernel<8><<<t.host_seg_blocks, kBlock, 0, s>>>(t);
-            else select_batch_kernel<16><<<t.host_seg_blocks, kBlock, 0, s>>>(t);
+#define EGOSGM_SB(KK)                                                                   \
+    do {                                                                                \
+        if (t.n_paths == 4) select_batch_kernel<KK, 4><<<t.host_seg_blocks, kBlock, 0, s>>>(t); \
+        else select_batch_kernel<KK, 8><<<t.host_seg_blocks, kBlock, 0, s>>>(t);               \
+    } while (0)
+            if (max_disp <= 16) EGOSGM_SB(1);
+            else if (max_disp <= 64) EGOSGM_SB(4);
+            else if (max_disp <= 128) EGOSGM_SB(8);
+            else EGOSGM_SB(16);
+#undef EGOSGM_SB
             break;
         default:
             lr_batch_kernel<<<grid_for((size_t)t.host_pixels), kBlock, 0, s>>>(t);

@@ -81,7 +81,7 @@ def _check(rc: int, what: str):
 
 class SgmParams(C.Structure):
     _fields_ = [("max_disp", C.c_int32), ("p1", C.c_int32), ("p2", C.c_int32),
-                ("s_max", C.c_int32), ("lr_tol", C.c_int32)]
+                ("s_max", C.c_int32), ("lr_tol", C.c_int32), ("n_paths", C.c_int32)]
 
 
 class SgmDebug(C.Structure):
@@ -120,9 +120,10 @@ class MatchParams:
     p2: int = 120
     s_max: int = 80
     lr_tol: int = 1
+    n_paths: int = 8       # or 4: along and against the rows and the columns only
 
     def c(self) -> SgmParams:
-        return SgmParams(self.max_disp, self.p1, self.p2, self.s_max, self.lr_tol)
+        return SgmParams(self.max_disp, self.p1, self.p2, self.s_max, self.lr_tol, self.n_paths)
 
 
 def _stream():

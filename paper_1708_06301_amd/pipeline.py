@@ -43,9 +43,11 @@ class FrameConfig:
     edge_tol: float = 2.0     # prediction edge rejection (Sec. 2.2.2); < 0 disables
     fill_tol: float = 1.0     # one-pixel hole filling, Eq. 7-8; <= 0 disables
     full_range_only: bool = False   # plain SGM every frame (the baseline)
+    n_paths: int = 8          # 4: the cheaper variant along rows and columns only
 
     def match(self) -> eg.MatchParams:
-        return eg.MatchParams(self.max_disp, self.p1, self.p2, self.s_max, self.lr_tol)
+        return eg.MatchParams(self.max_disp, self.p1, self.p2, self.s_max, self.lr_tol,
+                              self.n_paths)
 
 
 class StreamState:

@@ -42,14 +42,15 @@ FAKE = C.c_void_p(0x1000)   # never dereferenced: validation fails first
 
 
 def _prm(**kw):
-    base = dict(max_disp=64, p1=10, p2=120, s_max=80, lr_tol=1)
+    base = dict(max_disp=64, p1=10, p2=120, s_max=80, lr_tol=1, n_paths=8)
     base.update(kw)
     return eg.SgmParams(*base.values())
 
 
 @pytest.mark.parametrize("kw,code", [(dict(max_disp=0), -1), (dict(max_disp=257), -1),
                                      (dict(p1=-1), -1), (dict(p1=50, p2=40), -1),
-                                     (dict(p2=194), -1), (dict(s_max=-1), -1)])
+                                     (dict(p2=194), -1), (dict(s_max=-1), -1),
+                                     (dict(n_paths=5), -1), (dict(n_paths=16), -1)])
 def test_sgm_rejects_bad_params(kw, code):
     lib = eg.lib()
     prm = _prm(**kw)

@@ -129,6 +129,35 @@ def test_sgm_reduced_ragged(w, h, D, seed, kind, rmax, sched):
     _check_sgm(g, o, int(wo[2][-1]))
 
 
+@pytest.mark.parametrize("ragged", [False, True])
+@pytest.mark.parametrize("D", [64, 100, 128])
+def test_four_path_variant(ragged, D):
+    """n_paths = 4: directions 0-3 only (path volumes 0-3 and S bit-exact)."""
+    _say("4 paths, ragged" if ragged else "4 paths, full", D)
+    w, h = 91, 27
+    left, right = _random_pair(w, h, seed=D + 3, max_shift=min(D - 1, 30))
+    prm = eg.MatchParams(max_disp=D, p1=10, p2=120, s_max=40, lr_tol=1, n_paths=4)
+    if ragged:
+        d, p = _random_windows(w, h, D, seed=D + 4, kind="smooth")
+        wo = orc.windows(d, p, D, r_min=0, r_max=12)
+        lo, hi, off = (_gpu(wo[0].reshape(h, w)), _gpu(wo[1].reshape(h, w)), _gpu(wo[2].view(np.int32)))
+        g = eg.sgm_reduced(_gpu(left), _gpu(right), lo, hi, off, prm, debug=True)
+    else:
+        wo = None
+        g = eg.sgm_full(_gpu(left), _gpu(right), prm, debug=True)
+    o = orc.sgm(left, right, D, p1=10, p2=120, s_max=40, lr_tol=1, windows=wo, want_debug=True,
+                n_paths=4)
+    total = int(wo[2][-1]) if ragged else w * h * D
+    assert np.array_equal(_np(g["disp_wta"]), o["disp_wta"])
+    assert np.array_equal(_np(g["disp_right"]), o["disp_right"])
+    assert np.array_equal(_np(g["var_meas"]).astype(np.float64), o["var_meas"])
+    assert np.abs(_np(g["disp_sub"]).astype(np.float64) - o["disp_sub"]).max() <= TOL
+    assert np.array_equal(_np(g["agg"])[:total].view(np.uint16).astype(np.int32), o["agg"])
+    paths = _np(g["paths"])
+    for k in range(4):
+        assert np.array_equal(paths[k, :total].astype(np.int32), o["paths"][k]), f"path {k}"
+
+
 @pytest.mark.parametrize("s_max", [0, 7, 80, 600])
 @pytest.mark.parametrize("rmax,D", [(7, 64), (12, 128), (40, 128)])
 def test_selection_walk_every_pixel(s_max, rmax, D):
@@ -322,7 +351,7 @@ def _batch_cases():
 
 
 def _single(case, prm):
-    p = eg.MatchParams(case["max_disp"], prm.p1, prm.p2, prm.s_max, prm.lr_tol)
+    p = eg.MatchParams(case["max_disp"], prm.p1, prm.p2, prm.s_max, prm.lr_tol, prm.n_paths)
     if case["windows"] is None:
         return eg.sgm_full(case["left"], case["right"], p)
     return eg.sgm_reduced(case["left"], case["right"], *case["windows"], p)
@@ -335,11 +364,11 @@ def _same(a, b):
     return None
 
 
-@pytest.mark.parametrize("group", [16, 32, 64])
-def test_plan_matches_single_pairs(group):
-    _say("plan of 7 mixed pairs, lanes per scanline", group)
+@pytest.mark.parametrize("group,n_paths", [(16, 8), (32, 8), (64, 8), (16, 4)])
+def test_plan_matches_single_pairs(group, n_paths):
+    _say("plan of 7 mixed pairs, lanes per scanline", group, "paths", n_paths)
     cases = _batch_cases()
-    prm = eg.MatchParams(max_disp=256, p1=9, p2=110, s_max=70, lr_tol=1)
+    prm = eg.MatchParams(max_disp=256, p1=9, p2=110, s_max=70, lr_tol=1, n_paths=n_paths)
     eg.set_tuning(**{**eg.DEFAULT_TUNING, "batch_group": group})
     try:
         plan = eg.Plan(cases, prm)
@@ -355,7 +384,8 @@ def test_plan_matches_single_pairs(group):
     c = cases[2]
     h, w = c["left"].shape
     wo = tuple(t.cpu().numpy().ravel() for t in c["windows"][:2]) + (c["windows"][2].cpu().numpy().view(np.uint32),)
-    o = orc.sgm(c["left"].cpu().numpy(), c["right"].cpu().numpy(), 128, 9, 110, 70, 1, windows=wo)
+    o = orc.sgm(c["left"].cpu().numpy(), c["right"].cpu().numpy(), 128, 9, 110, 70, 1, windows=wo,
+                n_paths=n_paths)
     assert np.array_equal(_np(plan.outputs[2]["disp_wta"]), o["disp_wta"])
     plan.close()
 

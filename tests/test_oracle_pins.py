@@ -192,6 +192,23 @@ def test_sgm_zero_penalties_reduce_to_cost(orc):
     assert np.array_equal(r["disp_wta"], np.argmin(cost, axis=2))
 
 
+def test_four_path_variant_sums_the_axis_directions(orc):
+    """4 paths = directions 0-3 (along and against rows and columns); with
+    zero penalties S = 4C, and in general S is the sum of those four
+    single-direction volumes, each of which the Viterbi pins fix."""
+    left, right, _ = synth.planes_pair(64, 24, seed=13)
+    z = orc.sgm(left, right, 16, p1=0, p2=0, lr_tol=-1, want_debug=True, n_paths=4)
+    assert z["paths"].shape[0] == 4
+    assert np.array_equal(z["agg"], 4 * z["cost"])
+    r8 = orc.sgm(left, right, 16, p1=10, p2=120, want_debug=True)
+    r4 = orc.sgm(left, right, 16, p1=10, p2=120, want_debug=True, n_paths=4)
+    assert [orc.direction(k) for k in range(4)] == [(1, 0), (-1, 0), (0, 1), (0, -1)]
+    assert np.array_equal(r4["paths"], r8["paths"][:4])
+    assert np.array_equal(r4["agg"], r8["paths"][:4].sum(axis=0))
+    S = r4["agg"].reshape(24, 64, 16)
+    assert np.array_equal(r4["wta_raw"], np.argmin(S, axis=2))
+
+
 def test_sgm_bounds_and_sum(orc):
     left, right, _ = synth.planes_pair(48, 20, seed=12)
     r = orc.sgm(left, right, 24, p1=10, p2=120, want_debug=True)
