@@ -294,6 +294,42 @@ def quality_section(red, full, frames, motions, gts, max_disp):
             **{k: summarise(v) for k, v in out.items()}}
 
 
+def variants_section(w, h, calib, cfg, frames, motions, gts, dev, reps=3):
+    """The cheaper matchers of the survey's next steps on the same sequence:
+    4 paths (rows and columns only), and the SAD check (radius 2, at most
+    600, i.e. a mean absolute difference of 24 per pixel) after the
+    left-right check.  Time per 20-frame step (median of reps, HIP events)
+    and the filtered map's bad-pixel rates."""
+    import torch
+    from paper_1708_06301_amd import pipeline
+    from paper_1708_06301_amd.quality import bad_pixels, summarise
+    out = {}
+    for name, kw in (("paths4", dict(n_paths=4)), ("sad_check", dict(sad_radius=2, sad_max=600)),
+                     ("paths4_full_range", dict(n_paths=4, full_range_only=True))):
+        st = pipeline.StreamState(w, h, calib, pipeline.FrameConfig(**{**cfg.__dict__, **kw}), dev)
+        times = []
+        for _ in range(reps + 1):
+            a, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            st.reset()
+            a.record()
+            for k, (L, R) in enumerate(frames):
+                st.step(L, R, *(motions[k] if k > 0 else (None, None)))
+            b_.record()
+            b_.synchronize()
+            times.append(a.elapsed_time(b_))
+        ms = sorted(times[1:])[len(times[1:]) // 2]
+        q = []
+        st.reset()
+        for k, (L, R) in enumerate(frames):
+            d, _ = st.step(L, R, *(motions[k] if k > 0 else (None, None)))
+            if k > 0:
+                torch.cuda.synchronize()
+                q.append(bad_pixels(d, gts[k], cfg.max_disp))
+        out[name] = {"ms_per_step": round(ms, 3), "fps": round(len(frames) / (ms * 1e-3), 1),
+                     "quality_filtered": summarise(q)}
+    return out
+
+
 def serve_section(dev, n_frames, log, budget_gib=32.0):
     """16 camera streams (8 at 1242x375 D=128, 8 at 640x192 D=64), n_frames
     synthetic street frames each, arriving at 30 fps with Poisson jitter,
@@ -446,11 +482,18 @@ def main():
         run_sequence(full, frames, motions)
     torch.cuda.synchronize()
 
-    # main timed region: reduced pipeline, stage events on
+    # main timed region: exactly `steps` steps of the reduced pipeline with
+    # no instrumentation (the throughput figures), then the same for the
+    # full range; frame latencies come from a second pass with one event pair
+    # per frame, and the per-stage figures from a third pass with the
+    # library's stage events on (both add launch overhead of their own).
+    dt, _ = timed_steps(red, frames, motions, args.steps, with_events=False)
+    dt_full, _ = timed_steps(full, frames, motions, args.steps, with_events=False)
+    _, lat = timed_steps(red, frames, motions, args.steps)
+    _, lat_full = timed_steps(full, frames, motions, args.steps)
     eg.timing_read()
-    dt, lat = timed_steps(red, frames, motions, args.steps, stage_timing=True)
+    timed_steps(red, frames, motions, args.steps, with_events=False, stage_timing=True)
     stages = eg.timing_read()
-    dt_full, lat_full = timed_steps(full, frames, motions, args.steps)
 
     ms_step = dt / args.steps * 1e3
     gcups = upd_red * args.steps / dt / 1e9
@@ -529,6 +572,7 @@ def main():
         "tuning": tuning,
     }
     out["quality"] = quality_section(red, full, frames, motions, gts, cfg.max_disp)
+    out["variants"] = variants_section(w, h, calib, cfg, frames, motions, gts, dev)
     if not args.no_batch:
         out["batched"] = batch_section(dev, args.batch_pairs, args.steps, log)
     if not args.no_serve:

@@ -215,6 +215,19 @@ int refine_prediction(const float* d_in, const float* p_in, int w, int h, float 
                       float fill_tol, float* d_out, float* p_out, void* workspace,
                       size_t workspace_bytes, void* stream);
 
+/* ------------------------------------------------------------------ SAD check
+ * Second outlier filter of Sec. 2.4.1 (the paper names it beside the
+ * left-right check, without window or threshold): for every pixel with
+ * disp_wta >= 0, the sum of |left(x+i, y+j) - right(x+i-d, y+j)| over
+ * i, j in [-radius, radius], coordinates clamped into the image; a pixel
+ * whose sum exceeds sad_max is rejected in place like a left-right failure
+ * (disp_wta -1, disp_sub -1.0, var_meas 0).  Integer arithmetic.
+ * left, right: uint8 images with row pitch >= w; disp_wta, disp_sub,
+ * var_meas: w*h, the outputs of sgm_full / sgm_reduced.  radius 0..7,
+ * sad_max >= 0; EINVAL otherwise. */
+int sad_check(const uint8_t* left, const uint8_t* right, int w, int h, int pitch, int radius,
+              int sad_max, int16_t* disp_wta, float* disp_sub, float* var_meas, void* stream);
+
 /* ------------------------------------------------------------------ update
  * Pixel-wise Kalman update (Sec. 2.4, Eq. 10-12), float32 in this order:
  *   K = p/(p + r); d = d_pred + K (z - d_pred); p = (1 - K) p_pred.

@@ -579,3 +579,37 @@ int orc_kalman(const float* d_pred, const float* p_pred, const float* z,
     }
     return 0;
 }
+
+/* SAD check (Sec. 2.4.1 names it beside the left-right check as a filter of
+ * outliers before a map is propagated; it gives no window or threshold).
+ * For a pixel with a disparity d >= 0: the sum of |I_L(x+i, y+j) -
+ * I_R(x+i-d, y+j)| over i, j in [-radius, radius], coordinates clamped into
+ * the image (as the census does).  A pixel whose sum exceeds sad_max is
+ * rejected like a left-right failure (-1 / -1.0 / 0), in place. */
+int orc_sad_check(const uint8_t* left, const uint8_t* right, int w, int h, int radius,
+                  int sad_max, int16_t* disp_wta, double* disp_sub, double* var_meas) {
+    if (!left || !right || !disp_wta || w <= 0 || h <= 0 || radius < 0) return -1;
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x) {
+            const size_t p = (size_t)y * w + x;
+            const int d = disp_wta[p];
+            if (d < 0) continue;
+            long sad = 0;
+            for (int j = -radius; j <= radius; ++j) {
+                int yy = y + j;
+                yy = yy < 0 ? 0 : (yy >= h ? h - 1 : yy);
+                for (int i = -radius; i <= radius; ++i) {
+                    int xl = x + i, xr = x + i - d;
+                    xl = xl < 0 ? 0 : (xl >= w ? w - 1 : xl);
+                    xr = xr < 0 ? 0 : (xr >= w ? w - 1 : xr);
+                    sad += labs((long)left[(size_t)yy * w + xl] - (long)right[(size_t)yy * w + xr]);
+                }
+            }
+            if (sad > sad_max) {
+                disp_wta[p] = -1;
+                if (disp_sub) disp_sub[p] = -1.0;
+                if (var_meas) var_meas[p] = 0.0;
+            }
+        }
+    return 0;
+}

@@ -107,4 +107,9 @@ int orc_kalman(const float* d_pred, const float* p_pred, const float* z,
 #ifdef __cplusplus
 }
 #endif
+/* SAD check in place: pixels whose (2 radius + 1)^2 sum of absolute left /
+ * right differences at their disparity exceeds sad_max become invalid. */
+int orc_sad_check(const uint8_t* left, const uint8_t* right, int w, int h, int radius,
+                  int sad_max, int16_t* disp_wta, double* disp_sub, double* var_meas);
+
 #endif

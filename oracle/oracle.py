@@ -224,3 +224,16 @@ def refine(d_pred, p_pred, edge_tol=-1.0, fill_tol=1.0):
     _check(lib().orc_refine(_p(d), _p(p), w, h, C.c_float(edge_tol), C.c_float(fill_tol),
                             _p(od), _p(op)), "refine")
     return od, op
+
+
+def sad_check(left, right, disp_wta, radius, sad_max, disp_sub=None, var_meas=None):
+    """Returns (disp_wta, disp_sub, var_meas) after the SAD check (copies)."""
+    left = np.ascontiguousarray(left, dtype=np.uint8)
+    right = np.ascontiguousarray(right, dtype=np.uint8)
+    h, w = left.shape
+    wta = np.ascontiguousarray(disp_wta, dtype=np.int16).copy()
+    sub = None if disp_sub is None else np.ascontiguousarray(disp_sub, dtype=np.float64).copy()
+    var = None if var_meas is None else np.ascontiguousarray(var_meas, dtype=np.float64).copy()
+    _check(lib().orc_sad_check(_p(left), _p(right), w, h, radius, sad_max, _p(wta), _p(sub), _p(var)),
+           "sad_check")
+    return wta, sub, var

@@ -400,6 +400,18 @@ int sgm_plan_run_eager(egosgm_plan* plan, void* stream) {
                : EGOSGM_EDEVICE;
 }
 
+int sad_check(const uint8_t* left, const uint8_t* right, int w, int h, int pitch, int radius,
+              int sad_max, int16_t* disp_wta, float* disp_sub, float* var_meas, void* stream) {
+    if (!left || !right || !disp_wta || !disp_sub || !var_meas) return EGOSGM_EINVAL;
+    if (w <= 0 || h <= 0 || pitch < w || radius < 0 || radius > 7 || sad_max < 0)
+        return EGOSGM_EINVAL;
+    if ((long long)w * h >= (1ll << 31)) return EGOSGM_EUNSUPPORTED;
+    return launch_sad_check(left, right, w, h, pitch, radius, sad_max, disp_wta, disp_sub, var_meas,
+                            static_cast<hipStream_t>(stream)) == hipSuccess
+               ? EGOSGM_OK
+               : EGOSGM_EDEVICE;
+}
+
 int sgm_plan_update(egosgm_plan* plan, const egosgm_pair_update* upd, int n, void* stream) {
     if (!plan || !plan->exec || n < 0 || (n > 0 && !upd)) return EGOSGM_EINVAL;
     for (int j = 0; j < n; ++j) {

@@ -104,6 +104,9 @@ hipError_t launch_warp(const float* d_prev, const float* p_prev, int w, int h, c
                        unsigned long long* zbuf, hipStream_t s);
 hipError_t launch_refine(const float* d_in, const float* p_in, int w, int h, float edge_tol,
                          float fill_tol, float* d_out, float* p_out, float* tmp, hipStream_t s);
+hipError_t launch_sad_check(const uint8_t* left, const uint8_t* right, int w, int h, int pitch,
+                            int radius, int sad_max, int16_t* disp_wta, float* disp_sub,
+                            float* var_meas, hipStream_t s);
 hipError_t launch_kalman(const float* d_pred, const float* p_pred, const float* z,
                          const float* r, int n, int keep, float* d_out, float* p_out,
                          hipStream_t s);

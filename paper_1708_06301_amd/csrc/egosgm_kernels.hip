@@ -1217,6 +1217,37 @@ __global__ void plan_patch_kernel(SgmLaunch* pairs, PlanPatches p) {
     a->win.off = c.off;
 }
 
+// ------------------------------------------------------------------ SAD check
+// Sum of |I_L - I_R| over a (2r+1)^2 patch at the pixel's disparity,
+// coordinates clamped into the image; above sad_max the pixel is rejected
+// like a left-right failure.  Integer arithmetic.
+__global__ __launch_bounds__(kBlock) void sad_check_kernel(const uint8_t* __restrict__ left,
+                                                           const uint8_t* __restrict__ right, int w,
+                                                           int h, int pitch, int radius, int sad_max,
+                                                           int16_t* disp_wta, float* disp_sub,
+                                                           float* var_meas) {
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= w * h) return;
+    const int d = gptr(disp_wta)[p];
+    if (d < 0) return;
+    const int x = p % w, y = p / w;
+    const gmem<const uint8_t>* L = gptr(left);
+    const gmem<const uint8_t>* R = gptr(right);
+    int sad = 0;
+    for (int j = -radius; j <= radius; ++j) {
+        const size_t row = (size_t)min(max(y + j, 0), h - 1) * pitch;
+        for (int i = -radius; i <= radius; ++i) {
+            const int xl = min(max(x + i, 0), w - 1), xr = min(max(x + i - d, 0), w - 1);
+            sad += abs((int)L[row + xl] - (int)R[row + xr]);
+        }
+    }
+    if (sad > sad_max) {
+        gptr(disp_wta)[p] = -1;
+        gptr(disp_sub)[p] = -1.0f;
+        gptr(var_meas)[p] = 0.0f;
+    }
+}
+
 // ------------------------------------------------------------------ warp
 struct Mat4 {
     float m[16];
@@ -1498,6 +1529,14 @@ hipError_t launch_windows(const float* d_pred, const float* p_pred, int w, int h
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     windows_offset_kernel<<<h, kBlock, 0, s>>>(w, h, off, row_tot);
+    return hipGetLastError();
+}
+
+hipError_t launch_sad_check(const uint8_t* left, const uint8_t* right, int w, int h, int pitch,
+                            int radius, int sad_max, int16_t* disp_wta, float* disp_sub,
+                            float* var_meas, hipStream_t s) {
+    sad_check_kernel<<<grid_for((size_t)w * h), kBlock, 0, s>>>(left, right, w, h, pitch, radius,
+                                                                 sad_max, disp_wta, disp_sub, var_meas);
     return hipGetLastError();
 }
 

@@ -42,6 +42,7 @@ _SIGS = {
     "sgm_plan_run": ([_vp, _vp], _i),
     "sgm_plan_run_eager": ([_vp, _vp], _i),
     "sgm_plan_update": ([_vp, _vp, _i, _vp], _i),
+    "sad_check": ([_vp, _vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp], _i),
     "sgm_plan_destroy": ([_vp], _i),
     "egosgm_set_tuning": ([_vp], _i),
     "egosgm_get_tuning": ([_vp], _i),
@@ -344,6 +345,19 @@ def refine_prediction(d_in, p_in, edge_tol=2.0, fill_tol=1.0, out=None,
     rc = lib().refine_prediction(_ptr(d_in), _ptr(p_in), w, h, edge_tol, fill_tol, _ptr(out[0]),
                                  _ptr(out[1]), _ptr(ws), nbytes, _stream())
     _check(rc, "refine_prediction")
+    return out
+
+
+def sad_check(left, right, out, radius: int = 2, sad_max: int = 600):
+    """SAD check in place on a matcher's outputs dict (disp_wta, disp_sub,
+    var_meas), Sec. 2.4.1."""
+    _need(left, torch.uint8, name="left")
+    _need(right, torch.uint8, name="right")
+    h, w = left.shape
+    for k, dt in (("disp_wta", torch.int16), ("disp_sub", torch.float32), ("var_meas", torch.float32)):
+        _need(out[k], dt, h * w, k)
+    _check(lib().sad_check(_ptr(left), _ptr(right), w, h, w, radius, sad_max, _ptr(out["disp_wta"]),
+                           _ptr(out["disp_sub"]), _ptr(out["var_meas"]), _stream()), "sad_check")
     return out
 
 

@@ -44,6 +44,8 @@ class FrameConfig:
     fill_tol: float = 1.0     # one-pixel hole filling, Eq. 7-8; <= 0 disables
     full_range_only: bool = False   # plain SGM every frame (the baseline)
     n_paths: int = 8          # 4: the cheaper variant along rows and columns only
+    sad_radius: int = 0       # > 0: SAD check on (2r+1)^2 patches after matching (Sec. 2.4.1)
+    sad_max: int = 600
 
     def match(self) -> eg.MatchParams:
         return eg.MatchParams(self.max_disp, self.p1, self.p2, self.s_max, self.lr_tol,
@@ -115,6 +117,12 @@ class StreamState:
             eg.sgm_full(left, right, prm, out=self.out, workspace=self.ws)
         else:
             eg.sgm_reduced(left, right, *windows, prm, out=self.out, workspace=self.ws)
+        self.filter(left, right, self.out)
+
+    def filter(self, left, right, out):
+        """Outlier filters after matching besides the left-right check."""
+        if self.cfg.sad_radius > 0:
+            eg.sad_check(left, right, out, self.cfg.sad_radius, self.cfg.sad_max)
 
     def update(self, out=None):
         """Second half: the Kalman update of the prediction with the

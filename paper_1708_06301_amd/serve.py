@@ -380,6 +380,7 @@ class GpuExecutor:
             outs = []
             for r, f in zip(group, full):
                 st = self.streams[r.sid]["state"]
+                st.filter(r.left, r.right, plan.outputs[slot["index"][r.sid]])
                 d, p = st.update(out=plan.outputs[slot["index"][r.sid]])
                 o = dict(full_range=f)
                 if self.keep:

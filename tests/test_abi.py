@@ -142,3 +142,13 @@ def test_plan_validation():
     assert lib.sgm_plan_create(P, 0, C.byref(prm), FAKE, n, C.byref(out)) == -1
     assert lib.sgm_plan_run(None, None) == -1
     assert lib.sgm_plan_destroy(None) == 0
+
+
+def test_sad_check_validation():
+    lib = eg.lib()
+    f = FAKE
+    assert lib.sad_check(None, f, 10, 10, 10, 2, 100, f, f, f, None) == -1
+    assert lib.sad_check(f, f, 10, 10, 9, 2, 100, f, f, f, None) == -1     # pitch < w
+    assert lib.sad_check(f, f, 10, 10, 10, 8, 100, f, f, f, None) == -1    # radius > 7
+    assert lib.sad_check(f, f, 10, 10, 10, 2, -1, f, f, f, None) == -1     # sad_max < 0
+    assert lib.sad_check(f, f, 0, 10, 10, 2, 100, f, f, f, None) == -1

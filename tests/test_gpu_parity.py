@@ -455,3 +455,22 @@ def test_street_frames_full_size_default_launch():
     assert np.array_equal(_np(st.out["disp_right"]), o1["disp_right"])
     assert np.array_equal(_np(st.out["var_meas"]).astype(np.float64), o1["var_meas"])
     assert np.abs(_np(st.out["disp_sub"]).astype(np.float64) - o1["disp_sub"]).max() <= TOL
+
+
+
+@pytest.mark.parametrize("radius,sad_max", [(0, 5), (1, 60), (2, 300), (3, 900)])
+def test_sad_check(radius, sad_max):
+    _say("sad check", radius, sad_max)
+    w, h, D = 97, 31, 64
+    left, right = _random_pair(w, h, seed=radius + 50, max_shift=30)
+    o = orc.sgm(left, right, D, lr_tol=-1)
+    L, R = _gpu(left), _gpu(right)
+    out = dict(disp_wta=_gpu(o["disp_wta"]), disp_sub=_gpu(o["disp_sub"].astype(np.float32)),
+               var_meas=_gpu(o["var_meas"].astype(np.float32)))
+    eg.sad_check(L, R, out, radius, sad_max)
+    wta, sub, var = orc.sad_check(left, right, o["disp_wta"], radius, sad_max,
+                                  o["disp_sub"].astype(np.float32), o["var_meas"].astype(np.float32))
+    assert np.array_equal(_np(out["disp_wta"]), wta)
+    assert np.array_equal(_np(out["disp_sub"]).astype(np.float64), sub)
+    assert np.array_equal(_np(out["var_meas"]).astype(np.float64), var)
+    assert 0 < (wta < 0).sum() < wta.size or radius == 0

@@ -504,3 +504,43 @@ def test_refine_properties(orc):
     assert (od[:, [3, 4]] == -1).all() and (od[:, [0, 1, 2, 5, 6, 7]] >= 0).all()
     od, _ = orc.refine(step, np.ones_like(step), edge_tol=4.0, fill_tol=0.0)
     assert np.array_equal(od, step)
+
+
+# ------------------------------------------------------------- SAD check
+def test_sad_check_window_and_threshold_by_hand(orc):
+    """Left all 10, right all 13, radius 1, d = 0: every 3x3 sum is 9 * 3 = 27;
+    the check rejects strictly above sad_max."""
+    left = np.full((3, 5), 10, np.uint8)
+    right = np.full((3, 5), 13, np.uint8)
+    d = np.zeros((3, 5), np.int16)
+    wta, sub, var = orc.sad_check(left, right, d, 1, 27, np.zeros((3, 5)), np.ones((3, 5)))
+    assert (wta == 0).all() and (var == 1).all()
+    wta, sub, var = orc.sad_check(left, right, d, 1, 26, np.zeros((3, 5)), np.ones((3, 5)))
+    assert (wta == -1).all() and (sub == -1).all() and (var == 0).all()
+
+
+def test_sad_check_clamps_coordinates_into_the_image(orc):
+    """Right column 0 holds 50, the rest 0; left all 50.  At x = 0 with d = 2
+    every right tap falls left of the image and is clamped to column 0, so
+    the sum is 0 (zero padding would give 50 per tap)."""
+    left = np.full((4, 4), 50, np.uint8)
+    right = np.zeros((4, 4), np.uint8)
+    right[:, 0] = 50
+    d = np.full((4, 4), -1, np.int16)
+    d[1, 0] = 2
+    wta, _, _ = orc.sad_check(left, right, d, 1, 0)
+    assert wta[1, 0] == 2
+    d2 = d.copy()
+    d2[1, 0], d2[2, 3] = -1, 1          # x=3, d=1: taps x+i-1 in 1..3, right there is 0
+    wta, _, _ = orc.sad_check(left, right, d2, 1, 450)
+    assert wta[2, 3] == 1               # 9 taps * |50 - 0| = 450, not above 450: kept
+    wta, _, _ = orc.sad_check(left, right, d2, 1, 449)
+    assert wta[2, 3] == -1              # above 449: rejected
+    assert (wta[d2 < 0] == -1).all()    # pixels without a disparity are left alone
+
+
+def test_sad_check_exact_shift_keeps_interior(orc):
+    left, right = synth.shifted_pair(60, 20, 7, seed=21)
+    d = np.full((20, 60), 7, np.int16)
+    wta, _, _ = orc.sad_check(left, right, d, 2, 0)
+    assert (wta[2:-2, 9:-2] == 7).all()      # x - d - r >= 0 and inside the rows
