@@ -295,16 +295,17 @@ def quality_section(red, full, frames, motions, gts, max_disp):
 
 
 def variants_section(w, h, calib, cfg, frames, motions, gts, dev, reps=3):
-    """The cheaper matchers of the survey's next steps on the same sequence:
-    4 paths (rows and columns only), and the SAD check (radius 2, at most
-    600, i.e. a mean absolute difference of 24 per pixel) after the
-    left-right check.  Time per 20-frame step (median of reps, HIP events)
+    """Variants on the same sequence: 4 paths (rows and columns only), the
+    SAD check (radius 2, at most 600, i.e. a mean absolute difference of 24
+    per pixel) after the left-right check, and the left-right check of the
+    prediction (the warped right map, tolerance 1 px) before the windows.  Time per 20-frame step (median of reps, HIP events)
     and the filtered map's bad-pixel rates."""
     import torch
     from paper_1708_06301_amd import pipeline
     from paper_1708_06301_amd.quality import bad_pixels, summarise
     out = {}
     for name, kw in (("paths4", dict(n_paths=4)), ("sad_check", dict(sad_radius=2, sad_max=600)),
+                     ("lr_predict", dict(lr_predict=True, lr_predict_tol=1.0)),
                      ("paths4_full_range", dict(n_paths=4, full_range_only=True))):
         st = pipeline.StreamState(w, h, calib, pipeline.FrameConfig(**{**cfg.__dict__, **kw}), dev)
         times = []

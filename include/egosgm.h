@@ -215,6 +215,27 @@ int refine_prediction(const float* d_in, const float* p_in, int w, int h, float 
                       float fill_tol, float* d_out, float* p_out, void* workspace,
                       size_t workspace_bytes, void* stream);
 
+/* ------------------------------------------------------------------ prediction LR check
+ * Left-right check of the *prediction* (Sec. 2.4.1; Fig. 4 orders it after
+ * the warp and the zoom filling): the previous right disparity map is
+ * warped like the left one, with the right camera's motion (for a rectified
+ * rig M_R = M_L - (b, 0, 0), so R_R = R and t_R = t + R (b, 0, 0) - (b, 0, 0),
+ * then warp_disparity with the same f, cx, cy, b).  A left prediction
+ * d >= 0 is kept when d_right at xr = x - floorf(d + 0.5f) is >= 0 and
+ * within tol of d (float32); otherwise it becomes (-1, 0), so the pixel is
+ * searched over the full range.  d_pred, p_pred: w*h float, in place;
+ * d_right: w*h float (negative = none).  EINVAL on NULL, bad sizes or a
+ * tol that is negative or NaN; EUNSUPPORTED when w*h >= 2^31. */
+int lr_check_prediction(float* d_pred, float* p_pred, const float* d_right, int w, int h, float tol,
+                        void* stream);
+/* Host helper, no device work: t_right = t + R (b, 0, 0) - (b, 0, 0), the
+ * right camera's translation (R_R = R); R row-major 3x3, t and t_right 3
+ * doubles, caller-owned.  EINVAL on NULL. */
+int egosgm_right_motion(const double* R, const double* t, double baseline, double* t_right);
+/* n int16 disparities (e.g. the matcher's disp_right; -1 = none) converted
+ * to float, device arrays of n elements.  EINVAL on NULL or n <= 0. */
+int disparity_to_float(const int16_t* d, float* out, int n, void* stream);
+
 /* ------------------------------------------------------------------ SAD check
  * Second outlier filter of Sec. 2.4.1 (the paper names it beside the
  * left-right check, without window or threshold): for every pixel with

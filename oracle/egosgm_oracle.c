@@ -613,3 +613,42 @@ int orc_sad_check(const uint8_t* left, const uint8_t* right, int w, int h, int r
         }
     return 0;
 }
+
+/* Left-right check of a *prediction* (Sec. 2.4.1 and the processing order
+ * of Fig. 4: warp, zoom filling, then this check).  The right map of frame
+ * k-1 is warped like the left one (with the right camera's motion); a left
+ * prediction d >= 0 is kept when the right prediction at
+ * xr = x - floorf(d + 0.5f) exists (xr >= 0, value >= 0) and differs from d
+ * by at most tol (float32 comparison); otherwise the pixel becomes invalid
+ * (d = -1, p = 0), so it is searched over the full range.  In place. */
+int orc_lr_check_prediction(float* d_pred, float* p_pred, const float* d_right, int w, int h,
+                            float tol) {
+    if (!d_pred || !p_pred || !d_right || w <= 0 || h <= 0) return -1;
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x) {
+            const size_t p = (size_t)y * w + x;
+            const float d = d_pred[p];
+            if (!(d >= 0.0f)) continue;
+            /* d >= w points left of the image anyway; the test keeps the cast in range */
+            const int xr = d < (float)w ? x - (int)floorf(d + 0.5f) : -1;
+            int ok = 0;
+            if (xr >= 0) {
+                const float e = d_right[(size_t)y * w + xr];
+                ok = e >= 0.0f && fabsf(e - d) <= tol;
+            }
+            if (!ok) {
+                d_pred[p] = -1.0f;
+                p_pred[p] = 0.0f;
+            }
+        }
+    return 0;
+}
+
+/* Motion of the right camera of a rectified rig from the left one's: with
+ * M_R = M_L - (b, 0, 0), M_L^k = R M_L^{k-1} + t gives
+ * M_R^k = R M_R^{k-1} + t + R (b, 0, 0) - (b, 0, 0). */
+int orc_right_motion(const double* R, const double* t, double b, double* t_right) {
+    if (!R || !t || !t_right) return -1;
+    for (int i = 0; i < 3; ++i) t_right[i] = t[i] + R[3 * i] * b - (i == 0 ? b : 0.0);
+    return 0;
+}

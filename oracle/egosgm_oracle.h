@@ -112,4 +112,10 @@ int orc_kalman(const float* d_pred, const float* p_pred, const float* z,
 int orc_sad_check(const uint8_t* left, const uint8_t* right, int w, int h, int radius,
                   int sad_max, int16_t* disp_wta, double* disp_sub, double* var_meas);
 
+/* Left-right check of a prediction against the warped right map (in place). */
+int orc_lr_check_prediction(float* d_pred, float* p_pred, const float* d_right, int w, int h,
+                            float tol);
+/* Translation of the right camera's motion (same rotation). */
+int orc_right_motion(const double* R, const double* t, double b, double* t_right);
+
 #endif

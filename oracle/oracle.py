@@ -237,3 +237,22 @@ def sad_check(left, right, disp_wta, radius, sad_max, disp_sub=None, var_meas=No
     _check(lib().orc_sad_check(_p(left), _p(right), w, h, radius, sad_max, _p(wta), _p(sub), _p(var)),
            "sad_check")
     return wta, sub, var
+
+
+def lr_check_prediction(d_pred, p_pred, d_right, tol=1.0):
+    """Returns float32 (d, p) after the left-right check of a prediction."""
+    d = np.ascontiguousarray(d_pred, dtype=np.float32).copy()
+    pp = np.ascontiguousarray(p_pred, dtype=np.float32).copy()
+    dr = np.ascontiguousarray(d_right, dtype=np.float32)
+    h, w = d.shape
+    _check(lib().orc_lr_check_prediction(_p(d), _p(pp), _p(dr), w, h, C.c_float(tol)),
+           "lr_check_prediction")
+    return d, pp
+
+
+def right_motion(R, t, b):
+    R = np.ascontiguousarray(R, dtype=np.float64).ravel()
+    t = np.ascontiguousarray(t, dtype=np.float64).ravel()
+    out = np.zeros(3)
+    _check(lib().orc_right_motion(_p(R), _p(t), C.c_double(b), _p(out)), "right_motion")
+    return out

@@ -400,6 +400,29 @@ int sgm_plan_run_eager(egosgm_plan* plan, void* stream) {
                : EGOSGM_EDEVICE;
 }
 
+int egosgm_right_motion(const double* R, const double* t, double baseline, double* t_right) {
+    if (!R || !t || !t_right) return EGOSGM_EINVAL;
+    for (int i = 0; i < 3; ++i) t_right[i] = t[i] + R[3 * i] * baseline - (i == 0 ? baseline : 0.0);
+    return EGOSGM_OK;
+}
+
+int lr_check_prediction(float* d_pred, float* p_pred, const float* d_right, int w, int h, float tol,
+                        void* stream) {
+    if (!d_pred || !p_pred || !d_right || w <= 0 || h <= 0 || !(tol >= 0.0f)) return EGOSGM_EINVAL;
+    if ((long long)w * h >= (1ll << 31)) return EGOSGM_EUNSUPPORTED;
+    return launch_lr_check_prediction(d_pred, p_pred, d_right, w, h, tol,
+                                      static_cast<hipStream_t>(stream)) == hipSuccess
+               ? EGOSGM_OK
+               : EGOSGM_EDEVICE;
+}
+
+int disparity_to_float(const int16_t* d, float* out, int n, void* stream) {
+    if (!d || !out || n <= 0) return EGOSGM_EINVAL;
+    return launch_disparity_to_float(d, out, n, static_cast<hipStream_t>(stream)) == hipSuccess
+               ? EGOSGM_OK
+               : EGOSGM_EDEVICE;
+}
+
 int sad_check(const uint8_t* left, const uint8_t* right, int w, int h, int pitch, int radius,
               int sad_max, int16_t* disp_wta, float* disp_sub, float* var_meas, void* stream) {
     if (!left || !right || !disp_wta || !disp_sub || !var_meas) return EGOSGM_EINVAL;

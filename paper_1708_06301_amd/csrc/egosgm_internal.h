@@ -107,6 +107,9 @@ hipError_t launch_refine(const float* d_in, const float* p_in, int w, int h, flo
 hipError_t launch_sad_check(const uint8_t* left, const uint8_t* right, int w, int h, int pitch,
                             int radius, int sad_max, int16_t* disp_wta, float* disp_sub,
                             float* var_meas, hipStream_t s);
+hipError_t launch_lr_check_prediction(float* d_pred, float* p_pred, const float* d_right, int w,
+                                      int h, float tol, hipStream_t s);
+hipError_t launch_disparity_to_float(const int16_t* d, float* out, int n, hipStream_t s);
 hipError_t launch_kalman(const float* d_pred, const float* p_pred, const float* z,
                          const float* r, int n, int keep, float* d_out, float* p_out,
                          hipStream_t s);

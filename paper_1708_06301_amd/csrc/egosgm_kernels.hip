@@ -1248,6 +1248,37 @@ __global__ __launch_bounds__(kBlock) void sad_check_kernel(const uint8_t* __rest
     }
 }
 
+// ------------------------------------------------------------------ prediction LR check
+// A left prediction d >= 0 survives when the warped right map at
+// xr = x - floorf(d + 0.5f) holds e >= 0 with |e - d| <= tol (float32);
+// otherwise (-1, 0).  In place.
+__global__ __launch_bounds__(kBlock) void lr_check_prediction_kernel(float* d_pred, float* p_pred,
+                                                                     const float* d_right, int w,
+                                                                     int h, float tol) {
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= w * h) return;
+    const float d = gptr(d_pred)[p];
+    if (!(d >= 0.0f)) return;
+    const int x = p % w;
+    /* d >= w points left of the image anyway; the test keeps the cast in range */
+    const int xr = d < (float)w ? x - (int)floorf(d + 0.5f) : -1;
+    bool ok = false;
+    if (xr >= 0) {
+        const float e = gptr(d_right)[p - (x - xr)];
+        ok = e >= 0.0f && fabsf(e - d) <= tol;
+    }
+    if (!ok) {
+        gptr(d_pred)[p] = -1.0f;
+        gptr(p_pred)[p] = 0.0f;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void disparity_to_float_kernel(const int16_t* d, float* out,
+                                                                    int n) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) gptr(out)[i] = (float)gptr(d)[i];
+}
+
 // ------------------------------------------------------------------ warp
 struct Mat4 {
     float m[16];
@@ -1537,6 +1568,18 @@ hipError_t launch_sad_check(const uint8_t* left, const uint8_t* right, int w, in
                             float* var_meas, hipStream_t s) {
     sad_check_kernel<<<grid_for((size_t)w * h), kBlock, 0, s>>>(left, right, w, h, pitch, radius,
                                                                  sad_max, disp_wta, disp_sub, var_meas);
+    return hipGetLastError();
+}
+
+hipError_t launch_lr_check_prediction(float* d_pred, float* p_pred, const float* d_right, int w,
+                                      int h, float tol, hipStream_t s) {
+    lr_check_prediction_kernel<<<grid_for((size_t)w * h), kBlock, 0, s>>>(d_pred, p_pred, d_right, w,
+                                                                          h, tol);
+    return hipGetLastError();
+}
+
+hipError_t launch_disparity_to_float(const int16_t* d, float* out, int n, hipStream_t s) {
+    disparity_to_float_kernel<<<grid_for((size_t)n), kBlock, 0, s>>>(d, out, n);
     return hipGetLastError();
 }
 

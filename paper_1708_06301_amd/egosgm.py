@@ -43,6 +43,9 @@ _SIGS = {
     "sgm_plan_run_eager": ([_vp, _vp], _i),
     "sgm_plan_update": ([_vp, _vp, _i, _vp], _i),
     "sad_check": ([_vp, _vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp], _i),
+    "lr_check_prediction": ([_vp, _vp, _vp, _i, _i, C.c_float, _vp], _i),
+    "disparity_to_float": ([_vp, _vp, _i, _vp], _i),
+    "egosgm_right_motion": ([_vp, _vp, C.c_double, _vp], _i),
     "sgm_plan_destroy": ([_vp], _i),
     "egosgm_set_tuning": ([_vp], _i),
     "egosgm_get_tuning": ([_vp], _i),
@@ -359,6 +362,35 @@ def sad_check(left, right, out, radius: int = 2, sad_max: int = 600):
     _check(lib().sad_check(_ptr(left), _ptr(right), w, h, w, radius, sad_max, _ptr(out["disp_wta"]),
                            _ptr(out["disp_sub"]), _ptr(out["var_meas"]), _stream()), "sad_check")
     return out
+
+
+def lr_check_prediction(d_pred, p_pred, d_right, tol: float = 1.0):
+    """Left-right check of a prediction in place (Sec. 2.4.1, Fig. 4)."""
+    h, w = d_pred.shape
+    for t, name in ((d_pred, "d_pred"), (p_pred, "p_pred"), (d_right, "d_right")):
+        _need(t, torch.float32, h * w, name)
+    _check(lib().lr_check_prediction(_ptr(d_pred), _ptr(p_pred), _ptr(d_right), w, h, float(tol),
+                                     _stream()), "lr_check_prediction")
+    return d_pred, p_pred
+
+
+def disparity_to_float(d, out=None):
+    _need(d, torch.int16, name="disparity")
+    out = out if out is not None else torch.empty(d.shape, dtype=torch.float32, device=d.device)
+    _need(out, torch.float32, d.numel(), "out")
+    _check(lib().disparity_to_float(_ptr(d), _ptr(out), d.numel(), _stream()), "disparity_to_float")
+    return out
+
+
+def right_motion(R, t, baseline: float):
+    """Motion (R, t_R) of the right camera of a rectified rig from the left
+    camera's (egosgm_right_motion)."""
+    R = np.ascontiguousarray(R, np.float64).reshape(3, 3)
+    t = np.ascontiguousarray(t, np.float64).reshape(3)
+    tr = np.zeros(3)
+    _check(lib().egosgm_right_motion(R.ctypes.data_as(_vp), t.ctypes.data_as(_vp), float(baseline),
+                                     tr.ctypes.data_as(_vp)), "egosgm_right_motion")
+    return R, tr
 
 
 def kalman_update(d_pred, p_pred, d_meas, r_meas, keep_unmeasured=0, out=None):

@@ -46,6 +46,8 @@ class FrameConfig:
     n_paths: int = 8          # 4: the cheaper variant along rows and columns only
     sad_radius: int = 0       # > 0: SAD check on (2r+1)^2 patches after matching (Sec. 2.4.1)
     sad_max: int = 600
+    lr_predict: bool = False  # left-right check of the prediction against the warped right map
+    lr_predict_tol: float = 1.0
 
     def match(self) -> eg.MatchParams:
         return eg.MatchParams(self.max_disp, self.p1, self.p2, self.s_max, self.lr_tol,
@@ -85,6 +87,12 @@ class StreamState:
         self.ws.refine_bytes(w, h)
         self.invalid = torch.full((h, w), -1.0, **f32)
         self.zeros = torch.zeros((h, w), **f32)
+        if cfg.lr_predict:   # right map of the previous frame and its prediction
+            self.d_r = torch.full((h, w), -1.0, **f32)
+            self.d_rwarp = torch.empty((h, w), **f32)
+            self.p_rwarp = torch.empty((h, w), **f32)
+            self.d_rpred = torch.empty((h, w), **f32)
+            self.p_rpred = torch.empty((h, w), **f32)
         self.frame = 0
 
     def reset(self):
@@ -105,6 +113,15 @@ class StreamState:
                           out=(self.d_warp, self.p_warp), zbuf=self.zbuf)
         eg.refine_prediction(self.d_warp, self.p_warp, cfg.edge_tol, cfg.fill_tol,
                              out=(self.d_pred, self.p_pred), workspace=self.ws)
+        if cfg.lr_predict:
+            # Fig. 4 (d): the right map is predicted the same way, with the
+            # right camera's motion, and the left prediction checked against it
+            Rr, tr = eg.right_motion(R, t, c.baseline)
+            eg.warp_disparity(self.d_r, self.zeros, Rr, tr, c.f, c.cx, c.cy, c.baseline, cfg.q,
+                              out=(self.d_rwarp, self.p_rwarp), zbuf=self.zbuf)
+            eg.refine_prediction(self.d_rwarp, self.p_rwarp, cfg.edge_tol, cfg.fill_tol,
+                                 out=(self.d_rpred, self.p_rpred), workspace=self.ws)
+            eg.lr_check_prediction(self.d_pred, self.p_pred, self.d_rpred, cfg.lr_predict_tol)
         eg.windows_from_prediction(self.d_pred, self.p_pred, cfg.max_disp, cfg.r_fixed,
                                    cfg.r_min, cfg.r_max, cfg.k_sigma,
                                    out=(self.lo, self.hi, self.off), workspace=self.ws)
@@ -136,6 +153,8 @@ class StreamState:
         else:
             eg.kalman_update(self.d_pred, self.p_pred, out["disp_sub"], out["var_meas"],
                              cfg.keep_unmeasured, out=(self.d, self.p))
+        if cfg.lr_predict:
+            eg.disparity_to_float(out["disp_right"], self.d_r)
         self.frame += 1
         return self.d, self.p
 
@@ -144,6 +163,7 @@ class StreamState:
         outputs and workspaces)."""
         ts = [self.d, self.p, self.d_warp, self.p_warp, self.d_pred, self.p_pred, self.zbuf,
               self.lo, self.hi, self.off, self.invalid, self.zeros, *self.out.values(),
+              *[getattr(self, k, None) for k in ("d_r", "d_rwarp", "p_rwarp", "d_rpred", "p_rpred")],
               self.ws.sgm, self.ws.win, getattr(self.ws, "ref", None)]
         return sum(t.numel() * t.element_size() for t in ts if t is not None)
 

@@ -152,3 +152,24 @@ def test_sad_check_validation():
     assert lib.sad_check(f, f, 10, 10, 10, 8, 100, f, f, f, None) == -1    # radius > 7
     assert lib.sad_check(f, f, 10, 10, 10, 2, -1, f, f, f, None) == -1     # sad_max < 0
     assert lib.sad_check(f, f, 0, 10, 10, 2, 100, f, f, f, None) == -1
+
+
+def test_prediction_lr_check_validation(orc):
+    lib = eg.lib()
+    f = FAKE
+    assert lib.lr_check_prediction(None, f, f, 10, 10, C.c_float(1.0), None) == -1
+    assert lib.lr_check_prediction(f, f, f, 0, 10, C.c_float(1.0), None) == -1
+    assert lib.lr_check_prediction(f, f, f, 10, 10, C.c_float(-0.5), None) == -1
+    assert lib.lr_check_prediction(f, f, f, 10, 10, C.c_float(float("nan")), None) == -1
+    assert lib.lr_check_prediction(f, f, f, 1 << 16, 1 << 15, C.c_float(1.0), None) == -4
+    assert lib.disparity_to_float(f, f, 0, None) == -1
+    assert lib.disparity_to_float(None, f, 10, None) == -1
+    r = np.random.default_rng(3)
+    for _ in range(20):
+        a, b = r.normal(0, 0.1, 2)
+        R = (np.array([[np.cos(a), 0, np.sin(a)], [0, 1, 0], [-np.sin(a), 0, np.cos(a)]]) @
+             np.array([[1, 0, 0], [0, np.cos(b), -np.sin(b)], [0, np.sin(b), np.cos(b)]]))
+        t, base = r.normal(0, 1, 3), r.uniform(0.1, 1.0)
+        Rr, tr = eg.right_motion(R, t, base)
+        assert np.array_equal(Rr, R)
+        assert np.allclose(tr, orc.right_motion(R, t, base), rtol=0, atol=1e-15)

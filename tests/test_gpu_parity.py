@@ -474,3 +474,70 @@ def test_sad_check(radius, sad_max):
     assert np.array_equal(_np(out["disp_sub"]).astype(np.float64), sub)
     assert np.array_equal(_np(out["var_meas"]).astype(np.float64), var)
     assert 0 < (wta < 0).sum() < wta.size or radius == 0
+
+
+def test_lr_check_prediction_and_float_maps():
+    _say("lr check of a prediction, 211x57")
+    r = np.random.default_rng(77)
+    h, w = 57, 211
+    d = r.uniform(0, 60, size=(h, w)).astype(np.float32)
+    d[r.random((h, w)) < 0.1] = -1.0
+    d[:, :3] = 50.0                       # references left of the image
+    d[0, 10] = 9.5                        # rounds to 10: x - 10 = 0 is inside
+    p = r.uniform(0.1, 4, size=(h, w)).astype(np.float32)
+    dr = np.full((h, w), -1.0, np.float32)
+    for y in range(h):                    # half of the pixels near agreement, the rest noise
+        for x in range(w):
+            if d[y, x] >= 0 and r.random() < 0.5:
+                xr = x - int(np.floor(d[y, x] + 0.5))
+                if xr >= 0:
+                    dr[y, xr] = d[y, x] + (0.0 if r.random() < 0.3 else r.uniform(-1.5, 1.5))
+    holes = dr < 0
+    dr[holes] = np.where(r.random(holes.sum()) < 0.5, -1.0, r.uniform(0, 60, holes.sum())).astype(np.float32)
+    for tol in (0.0, 0.5, 1.0, 2.0):
+        gd, gp = _gpu(d), _gpu(p)
+        eg.lr_check_prediction(gd, gp, _gpu(dr), tol)
+        od, op = orc.lr_check_prediction(d, p, dr, tol)
+        assert np.array_equal(_np(gd), od) and np.array_equal(_np(gp), op), tol
+        kept = od >= 0
+        assert 0 < kept.sum() < (d >= 0).sum()
+    i16 = r.integers(-1, 128, size=(h, w)).astype(np.int16)
+    out = torch.empty((h, w), dtype=torch.float32, device=DEV)
+    eg.disparity_to_float(_gpu(i16), out)
+    assert np.array_equal(_np(out), i16.astype(np.float32))
+
+
+def test_prediction_with_lr_check_follows_the_oracle():
+    """The pipeline's prediction with the left-right check on: the right
+    map kept from frame 0 equals the matcher's, its warp with the right
+    camera's motion matches the oracle's, and the checked left prediction
+    equals the oracle's check of the unchecked one against the GPU's
+    refined right prediction."""
+    from paper_1708_06301_amd import pipeline
+    _say("prediction lr check, street 320x96")
+    w, h, D = 320, 96, 64
+    seq = synth.street_sequence(w, h, 2, seed=synth.seed_for(2))
+    (L0, R0, _), = [seq.frame(0, device=DEV)]
+    Rm, t = (np.asarray(a, np.float64) for a in seq.motion(1))
+    states = []
+    for lr in (False, True):
+        cfg = pipeline.FrameConfig(max_disp=D, r_fixed=4, lr_predict=lr, lr_predict_tol=1.0)
+        st = pipeline.StreamState(w, h, pipeline.camera_of(seq), cfg, DEV)
+        st.step(_gpu(L0), _gpu(R0))
+        st.predict(Rm, t)
+        states.append(st)
+    off, on = states
+    c = pipeline.camera_of(seq)
+    assert np.array_equal(_np(on.d_r), _np(on.out["disp_right"]).astype(np.float32))
+    tr = orc.right_motion(Rm, t, c.baseline)
+    o = orc.warp(_np(on.d_r), np.zeros((h, w), np.float32), Rm, tr, c.f, c.cx, c.cy, c.baseline,
+                 q=on.cfg.q)
+    gd = _np(on.d_rwarp)
+    valid = o["winner"] >= 0
+    assert np.array_equal(gd >= 0, valid) and _close(gd[valid], o["d_pred"][valid])
+    rd, rp = orc.refine(gd, _np(on.p_rwarp), on.cfg.edge_tol, on.cfg.fill_tol)
+    assert np.array_equal(_np(on.d_rpred), rd) and np.array_equal(_np(on.p_rpred), rp)
+    od, op = orc.lr_check_prediction(_np(off.d_pred), _np(off.p_pred), rd, on.cfg.lr_predict_tol)
+    assert np.array_equal(_np(on.d_pred), od) and np.array_equal(_np(on.p_pred), op)
+    n_off, n_on = int((_np(off.d_pred) >= 0).sum()), int((od >= 0).sum())
+    assert 0.5 * n_off < n_on < n_off

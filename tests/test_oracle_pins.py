@@ -544,3 +544,71 @@ def test_sad_check_exact_shift_keeps_interior(orc):
     d = np.full((20, 60), 7, np.int16)
     wta, _, _ = orc.sad_check(left, right, d, 2, 0)
     assert (wta[2:-2, 9:-2] == 7).all()      # x - d - r >= 0 and inside the rows
+
+
+# ------------------------------------------- left-right check of a prediction
+def test_right_camera_motion_moves_points_like_the_left_one(orc):
+    """M_R = M_L - (b,0,0): moving points with (R, t) in the left frame equals
+    moving them with (R, t_R) in the right frame."""
+    g = np.random.default_rng(3)
+    R = np.eye(3) + g.normal(0, 0.1, (3, 3))   # the relation is linear: any matrix will do
+    t = g.normal(0, 1, 3)
+    b = 0.54
+    tr = orc.right_motion(R, t, b)
+    M = g.normal(0, 5, (3, 20))
+    bv = np.array([[b], [0.0], [0.0]])
+    lhs = (R @ M + t[:, None]) - bv
+    rhs = R @ (M - bv) + tr[:, None]
+    assert np.allclose(lhs, rhs, atol=1e-12)
+
+
+def test_lr_check_prediction_by_hand(orc):
+    #   x:        0     1     2     3     4     5
+    d = np.array([[0.4, 2.6, 1.0, -1.0, 3.49, 5.0]], np.float32)
+    p = np.ones_like(d)
+    dr = np.array([[0.0, 9.0, 1.9, -1.0, 7.0, 6.0]], np.float32)
+    # x=0: xr = 0 - 0 = 0, |0 - 0.4| <= 1 keep; x=1: xr = 1 - 3 < 0 reject;
+    # x=2: xr = 1, |9 - 1| > 1 reject; x=3: no prediction (left alone);
+    # x=4: xr = 4 - 3 = 1, |9 - 3.49| > 1 reject; x=5: xr = 0, |0 - 5| reject.
+    out_d, out_p = orc.lr_check_prediction(d, p, dr, 1.0)
+    assert out_d.tolist() == [[np.float32(0.4), -1.0, -1.0, -1.0, -1.0, -1.0]]
+    assert out_p.tolist() == [[1.0, 0.0, 0.0, 1.0, 0.0, 0.0]]
+    dr2 = dr.copy()
+    dr2[0, 1] = 1.9                          # x=2 (xr=1): |1.9 - 1| <= 1 now kept
+    out_d, _ = orc.lr_check_prediction(d, p, dr2, 1.0)
+    assert out_d[0, 2] == np.float32(1.0)
+    out_d, _ = orc.lr_check_prediction(d, p, dr2, 0.8)
+    assert out_d[0, 2] == -1.0               # tolerance is a float32 <=
+
+
+def test_warped_maps_of_a_plane_stay_consistent(orc):
+    """A fronto-parallel plane at Z: left and right maps are the constant
+    fb/Z; after moving forward both warped predictions are the same constant
+    where defined, so the check keeps every left pixel whose partner is in
+    the image."""
+    w, h, f, b = 90, 30, 60.0, 0.5
+    cx, cy = (w - 1) / 2, (h - 1) / 2
+    d0 = f * b / 10.0
+    dl = np.full((h, w), d0, np.float32)
+    dr = np.full((h, w), d0, np.float32)
+    dr[:, w - int(np.floor(d0 + 0.5)):] = -1.0            # right pixels whose left partner is outside
+    R, t = np.eye(3), np.array([0.0, 0.0, -1.0])
+    wl = orc.warp(dl, np.ones_like(dl), R, t, f, cx, cy, b, 0.5)
+    wr = orc.warp(dr, np.ones_like(dr), R, orc.right_motion(R, t, b), f, cx, cy, b, 0.5)
+    d1 = f * b / 9.0
+    okl = wl["d_pred"] >= 0
+    assert np.allclose(wl["d_pred"][okl], d1, atol=1e-9)
+    assert np.allclose(wr["d_pred"][wr["d_pred"] >= 0], d1, atol=1e-9)
+    out_d, _ = orc.lr_check_prediction(wl["d_pred"].astype(np.float32), wl["p_pred"].astype(np.float32),
+                                       wr["d_pred"].astype(np.float32), 1.0)
+    kept = out_d >= 0
+    xs = np.arange(w)[None, :].repeat(h, 0)
+    inner = okl & (xs - np.floor(d1 + 0.5) >= 0)
+    inner &= np.take_along_axis(wr["d_pred"] >= 0, np.clip(xs - int(np.floor(d1 + 0.5)), 0, w - 1), 1)
+    assert np.array_equal(kept, inner)
+    # the zoom leaves one-pixel holes in both maps; filled first (the order of
+    # Fig. 4), the interior is kept entirely
+    fl, pl = orc.refine(wl["d_pred"].astype(np.float32), wl["p_pred"].astype(np.float32), -1.0, 1.0)
+    fr, _ = orc.refine(wr["d_pred"].astype(np.float32), wr["p_pred"].astype(np.float32), -1.0, 1.0)
+    out_d, _ = orc.lr_check_prediction(fl, pl, fr, 1.0)
+    assert (out_d[3:-3, 6:-6] >= 0).all()
