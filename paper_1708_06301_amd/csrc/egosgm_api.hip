@@ -300,7 +300,7 @@ int sgm_plan_create(const egosgm_pair* pairs, int n, const egosgm_sgm_params* pa
         cen[i] = (int)tiles;
         seg[i] = (int)segs;
         pix[i] = (int)pixels;
-        tiles += (long long)((q.w + 63) / 64) * ((q.h + 3) / 4);
+        tiles += (long long)((q.w + kCensusTileW - 1) / kCensusTileW) * ((q.h + kCensusTileH - 1) / kCensusTileH);
         segs += (long long)((q.w + 63) / 64) * q.h;
         pixels += (long long)q.w * q.h;
     }

@@ -14,6 +14,12 @@ constexpr int kNumPaths = 8;
 
 // Views of the search windows: either the full range (lo = 0, hi = D-1,
 // offset = p*D) or the ragged arrays of sgm_windows_from_prediction.
+// Census tiles: kCensusTileW x kCensusTileH pixels per 256-thread block,
+// kCensusPx pixels per thread (the plan's block counts use the same shape).
+constexpr int kCensusPx = 4;
+constexpr int kCensusTileW = 64 * kCensusPx;
+constexpr int kCensusTileH = 4;
+
 struct Windows {
     const int16_t* lo;       // nullptr: full range
     const int16_t* hi;

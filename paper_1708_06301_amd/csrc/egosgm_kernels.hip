@@ -19,11 +19,6 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kInf = 0x3fff;
 
-// ------------------------------------------------------------------ census
-constexpr int kCtW = 64;          // output tile width  (one wave per row)
-constexpr int kCtH = kBlock / kCtW;  // output tile height
-constexpr int kHaloX = 4, kHaloY = 3;
-
 // Every buffer the kernels touch is global memory.  Accesses go through
 // explicitly global pointers so that the compiler emits global (not flat)
 // instructions also where a pointer comes from a descriptor read from
@@ -44,40 +39,74 @@ __device__ inline __amdgpu_buffer_rsrc_t byte_buffer(void* base, uint32_t n) {
 }
 constexpr uint32_t kDropOffset = 0xffffffffu;
 
-// One 64x4 output tile of one image; clear (nullable) gets 0xffffffff per
-// pixel (the right-map keys of the matcher, reset here so that no memset is
-// needed in a captured graph).
-__device__ inline void census_tile(const uint8_t* __restrict__ img, int w, int h, int pitch,
+// ------------------------------------------------------------------ census
+// A block computes a kCensusTileW x kCensusTileH output tile; each thread
+// takes kCensusPx neighbouring pixels of one row, so a tile row of 12 bytes
+// (x-4 .. x+7) per census row serves four pixels.
+constexpr int kCtPx = kCensusPx;
+constexpr int kCtW = kCensusTileW;
+constexpr int kCtH = kCensusTileH;
+constexpr int kHaloX = 4, kHaloY = 3;
+static_assert(kCtW == 64 * kCtPx && kCtH * 64 == kBlock && kCtPx == 4, "census tile shape");
+
+// One census tile of one image; clear (nullable) gets 0xffffffff per pixel
+// (the right-map keys of the matcher, reset here so that no memset is needed
+// in a captured graph).  Bit k of a code is [I(q_k) < I(p)] over the 9x7
+// offsets row by row, centre skipped; the bits are shifted in from the
+// highest k down, two words per pixel, one subtract and one funnel shift
+// per bit.
+__device__ __attribute__((always_inline)) inline void census_tile(const uint8_t* __restrict__ img, int w, int h, int pitch,
                                    uint64_t* __restrict__ out, uint32_t* __restrict__ clear,
                                    int tx, int ty) {
     constexpr int TW = kCtW + 2 * kHaloX, TH = kCtH + 2 * kHaloY;
-    __shared__ uint8_t tile[TH][TW];
+    static_assert(TW % 4 == 0, "tile rows are whole words");
+    __shared__ uint32_t tile[TH][TW / 4];
+    uint8_t* tb = reinterpret_cast<uint8_t*>(&tile[0][0]);
     const gmem<const uint8_t>* __restrict__ gimg = gptr(img);
     const int x0 = tx * kCtW, y0 = ty * kCtH;
     for (int i = threadIdx.x; i < TW * TH; i += kBlock) {
         const int r = i / TW, c = i - r * TW;
         const int gx = min(max(x0 + c - kHaloX, 0), w - 1);
         const int gy = min(max(y0 + r - kHaloY, 0), h - 1);
-        tile[r][c] = gimg[(size_t)gy * pitch + gx];
+        tb[i] = gimg[(size_t)gy * pitch + gx];
     }
     __syncthreads();
-    const int lx = threadIdx.x % kCtW, ly = threadIdx.x / kCtW;
-    const int x = x0 + lx, y = y0 + ly;
+    const int lx = threadIdx.x % 64, ly = threadIdx.x / 64;
+    const int x = x0 + kCtPx * lx, y = y0 + ly;
     if (x >= w || y >= h) return;
-    const int c = tile[ly + kHaloY][lx + kHaloX];
-    uint64_t code = 0;
-    int k = 0;
+    // tile column 4*lx is image column x - 4: words lx .. lx+2 of a row
+    // hold x-4 .. x+7, the centre row's word lx+1 the four centres.
+    const uint32_t cw = tile[ly + kHaloY][lx + 1];
+    uint32_t hi[kCtPx], lo[kCtPx];
 #pragma unroll
-    for (int dy = 0; dy < 2 * kHaloY + 1; ++dy) {
+    for (int i = 0; i < kCtPx; ++i) hi[i] = lo[i] = 0u;
 #pragma unroll
-        for (int dx = 0; dx < 2 * kHaloX + 1; ++dx) {
+    for (int dy = 2 * kHaloY; dy >= 0; --dy) {
+        const uint32_t rw[3] = {tile[ly + dy][lx], tile[ly + dy][lx + 1], tile[ly + dy][lx + 2]};
+#pragma unroll
+        for (int dx = 2 * kHaloX; dx >= 0; --dx) {
             if (dy == kHaloY && dx == kHaloX) continue;
-            code |= (uint64_t)(tile[ly + dy][lx + dx] < c) << k;
-            ++k;
+            const int k = dy * (2 * kHaloX + 1) + dx - (dy * (2 * kHaloX + 1) + dx > kHaloY * (2 * kHaloX + 1) + kHaloX ? 1 : 0);
+#pragma unroll
+            for (int i = 0; i < kCtPx; ++i) {
+                const int b = i + dx;
+                const uint32_t n = (rw[b >> 2] >> (8 * (b & 3))) & 0xffu;
+                const uint32_t c = (cw >> (8 * i)) & 0xffu;
+                const uint32_t diff = n - c;   // bit 31 set iff n < c
+                if (k >= 32)
+                    hi[i] = __builtin_amdgcn_alignbit(hi[i], diff, 31);
+                else
+                    lo[i] = __builtin_amdgcn_alignbit(lo[i], diff, 31);
+            }
         }
     }
-    gptr(out)[(size_t)y * w + x] = code;
-    if (clear) gptr(clear)[(size_t)y * w + x] = 0xffffffffu;
+    gmem<uint64_t>* o = gptr(out) + (size_t)y * w + x;
+#pragma unroll
+    for (int i = 0; i < kCtPx; ++i)
+        if (x + i < w) {
+            o[i] = (uint64_t)hi[i] << 32 | lo[i];
+            if (clear) gptr(clear)[(size_t)y * w + x + i] = 0xffffffffu;
+        }
 }
 
 __global__ __launch_bounds__(kBlock) void census_kernel(const uint8_t* __restrict__ img0,
@@ -255,14 +284,29 @@ constexpr int kSeg = 64;
 template <int G, int WM>
 __device__ inline void cost_segment(const SgmLaunch& a, int seg, int y) {
     constexpr int GPB = kBlock / G;
+    static_assert(kSeg <= kBlock, "one thread per pixel of a segment");
     __shared__ uint64_t crs[kSeg + kMaxDisp];
     __shared__ uint64_t cls[kSeg];
+    __shared__ int s_lo[kSeg], s_w[kSeg];
+    __shared__ uint32_t s_off[kSeg];
     const int W = a.w, D = a.win.max_disp;
     const int x0 = seg * kSeg;
     const int base = x0 - (D - 1);
     const gmem<const uint64_t>* rowl = gptr(a.census_l + (size_t)y * W);
     const gmem<const uint64_t>* rowr = gptr(a.census_r + (size_t)y * W);
     gmem<uint8_t>* __restrict__ cost = gptr(a.cost);
+    // windows of the segment's pixels are read once, next to the codes,
+    // so the slot loop below waits on no global load
+    if (WM != kWinFull && threadIdx.x < kSeg && x0 + (int)threadIdx.x < W) {
+        const int p = y * W + x0 + (int)threadIdx.x;
+        int lo, hi;
+        uint32_t off;
+        window_of<WM>(a.win, p, lo, hi, off);
+        s_lo[threadIdx.x] = lo;
+        s_w[threadIdx.x] = hi - lo + 1;
+        s_off[threadIdx.x] = off;
+        if (WM == kWinRagged || a.win.lo != nullptr) gptr(a.meta)[p] = pack_meta(off, lo, hi - lo + 1);
+    }
     for (int i = threadIdx.x; i < kSeg + D - 1; i += kBlock) {
         const int xr = base + i;
         crs[i] = (xr >= 0 && xr < W) ? rowr[xr] : 0ull;
@@ -273,13 +317,19 @@ __device__ inline void cost_segment(const SgmLaunch& a, int seg, int y) {
     for (int i = grp; i < kSeg; i += GPB) {
         const int x = x0 + i;
         if (x >= W) break;
-        int lo, hi;
+        int lo, wd;
         uint32_t off;
-        window_of<WM>(a.win, y * W + x, lo, hi, off);
-        if (WM != kWinFull && lane == 0 && (WM != kWinAny || a.win.lo != nullptr))
-            gptr(a.meta)[y * W + x] = pack_meta(off, lo, hi - lo + 1);
+        if (WM == kWinFull) {
+            lo = 0;
+            wd = D;
+            off = (uint32_t)(y * W + x) * (uint32_t)D;
+        } else {
+            lo = s_lo[i];
+            wd = s_w[i];
+            off = s_off[i];
+        }
         const uint64_t cl = cls[i];
-        for (int sl = lane; sl <= hi - lo; sl += G) {
+        for (int sl = lane; sl < wd; sl += G) {
             const int d = lo + sl;
             const int c = (x - d >= 0) ? __popcll(cl ^ crs[i + (D - 1) - d]) : kCensusBits;
             cost[off + (uint32_t)sl] = (uint8_t)c;
