@@ -1395,57 +1395,85 @@ __global__ __launch_bounds__(kBlock) void warp_decode_kernel(const unsigned long
 }
 
 // ------------------------------------------------------------------ refinement
-// Edge rejection: a valid prediction is dropped when a valid pixel of its
-// 3x3 neighbourhood differs from it by more than edge_tol (edge_tol < 0:
-// plain copy).
-__global__ __launch_bounds__(kBlock) void refine_edge_kernel(const float* __restrict__ d_in,
-                                                             const float* __restrict__ p_in,
-                                                             int w, int h, float edge_tol,
-                                                             float* __restrict__ d_out,
-                                                             float* __restrict__ p_out) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= w * h) return;
-    const int x = i % w, y = i / w;
-    const float d = d_in[i];
-    bool keep = d >= 0.0f;
-    if (keep && edge_tol >= 0.0f) {
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int xx = x + dx, yy = y + dy;
-                if (xx < 0 || xx >= w || yy < 0 || yy >= h) continue;
-                const float e = d_in[yy * w + xx];
-                if (e >= 0.0f && fabsf(d - e) > edge_tol) keep = false;
-            }
-    }
-    d_out[i] = keep ? d : -1.0f;
-    p_out[i] = keep ? p_in[i] : 0.0f;
-}
+// The three refinement passes in one kernel.  Edge rejection: a valid
+// prediction is dropped when a valid pixel of its 3x3 neighbourhood differs
+// from it by more than edge_tol (edge_tol < 0: plain copy).  One-pixel
+// "zoom" hole filling along rows, then along columns: an invalid pixel
+// between two valid neighbours with |a - b| < fill_tol takes their means
+// ((a + b) * 0.5f is the correctly rounded mean: the sum is rounded once and
+// halving is exact); each pass reads the previous pass's result.  A block
+// stages its 64x4 output tile with a halo of two pixels, runs the edge test
+// on the tile plus one pixel, the row fill on the tile plus one row, and the
+// column fill on the tile, each from the previous pass's values in LDS.
+// Pixels outside the image are staged as invalid, which the edge test skips
+// as it skips invalid neighbours; the fills never read them.
+constexpr int kRfW = 64, kRfH = kBlock / kRfW;
 
-// One-pixel "zoom" hole filling along rows (step 1) or columns (step w): an
-// invalid pixel between two valid neighbours with |a - b| < fill_tol takes
-// their means.  (a + b) * 0.5f is the correctly rounded mean: the sum is
-// rounded once and halving is exact.
-__global__ __launch_bounds__(kBlock) void refine_fill_kernel(const float* __restrict__ d_in,
-                                                             const float* __restrict__ p_in,
-                                                             int w, int h, float fill_tol,
-                                                             int vertical,
-                                                             float* __restrict__ d_out,
-                                                             float* __restrict__ p_out) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= w * h) return;
-    const int x = i % w, y = i / w;
-    float d = d_in[i], p = p_in[i];
-    const bool inside = vertical ? (y >= 1 && y + 1 < h) : (x >= 1 && x + 1 < w);
-    if (d < 0.0f && inside) {
-        const int st = vertical ? w : 1;
-        const float a = d_in[i - st], b = d_in[i + st];
+__global__ __launch_bounds__(kBlock) void refine_fused_kernel(const float* __restrict__ d_in,
+                                                              const float* __restrict__ p_in,
+                                                              int w, int h, float edge_tol,
+                                                              float fill_tol,
+                                                              float* __restrict__ d_out,
+                                                              float* __restrict__ p_out) {
+    constexpr int AW = kRfW + 4, AH = kRfH + 4;   // input, halo 2
+    constexpr int EW = kRfW + 2, EH = kRfH + 2;   // after the edge test, halo 1
+    __shared__ float sd[AH][AW], sp[AH][AW], ed[EH][EW], ep[EH][EW], hd[EH][kRfW], hp[EH][kRfW];
+    const int x0 = blockIdx.x * kRfW, y0 = blockIdx.y * kRfH;
+    const gmem<const float>* gd = gptr(d_in);
+    const gmem<const float>* gp = gptr(p_in);
+    for (int t = threadIdx.x; t < AW * AH; t += kBlock) {
+        const int r = t / AW, c = t - r * AW;
+        const int gx = x0 + c - 2, gy = y0 + r - 2;
+        const bool in = gx >= 0 && gx < w && gy >= 0 && gy < h;
+        sd[r][c] = in ? gd[(size_t)gy * w + gx] : -1.0f;
+        sp[r][c] = in ? gp[(size_t)gy * w + gx] : 0.0f;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < EW * EH; t += kBlock) {
+        const int r = t / EW, c = t - r * EW;
+        const float d = sd[r + 1][c + 1];
+        bool keep = d >= 0.0f;
+        if (keep && edge_tol >= 0.0f) {
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) {
+                    const float e = sd[r + dy][c + dx];
+                    if (e >= 0.0f && fabsf(d - e) > edge_tol) keep = false;
+                }
+        }
+        ed[r][c] = keep ? d : -1.0f;
+        ep[r][c] = keep ? sp[r + 1][c + 1] : 0.0f;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kRfW * EH; t += kBlock) {
+        const int r = t / kRfW, c = t - r * kRfW;
+        const int gx = x0 + c;
+        float d = ed[r][c + 1], p = ep[r][c + 1];
+        if (d < 0.0f && gx >= 1 && gx + 1 < w) {
+            const float a = ed[r][c], b = ed[r][c + 2];
+            if (a >= 0.0f && b >= 0.0f && fabsf(a - b) < fill_tol) {
+                d = (a + b) * 0.5f;
+                p = (ep[r][c] + ep[r][c + 2]) * 0.5f;
+            }
+        }
+        hd[r][c] = d;
+        hp[r][c] = p;
+    }
+    __syncthreads();
+    const int c = threadIdx.x % kRfW, r = threadIdx.x / kRfW;
+    const int gx = x0 + c, gy = y0 + r;
+    if (gx >= w || gy >= h) return;
+    float d = hd[r + 1][c], p = hp[r + 1][c];
+    if (d < 0.0f && gy >= 1 && gy + 1 < h) {
+        const float a = hd[r][c], b = hd[r + 2][c];
         if (a >= 0.0f && b >= 0.0f && fabsf(a - b) < fill_tol) {
             d = (a + b) * 0.5f;
-            p = (p_in[i - st] + p_in[i + st]) * 0.5f;
+            p = (hp[r][c] + hp[r + 2][c]) * 0.5f;
         }
     }
-    d_out[i] = d;
-    p_out[i] = p;
+    gptr(d_out)[(size_t)gy * w + gx] = d;
+    gptr(p_out)[(size_t)gy * w + gx] = p;
 }
 
 // ------------------------------------------------------------------ Kalman
@@ -1712,14 +1740,9 @@ hipError_t launch_warp(const float* d_prev, const float* p_prev, int w, int h, c
 
 hipError_t launch_refine(const float* d_in, const float* p_in, int w, int h, float edge_tol,
                          float fill_tol, float* d_out, float* p_out, float* tmp, hipStream_t s) {
-    const size_t n = (size_t)w * h;
-    refine_edge_kernel<<<grid_for(n), kBlock, 0, s>>>(d_in, p_in, w, h, edge_tol, d_out, p_out);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !(fill_tol > 0.0f)) return e;
-    refine_fill_kernel<<<grid_for(n), kBlock, 0, s>>>(d_out, p_out, w, h, fill_tol, 0, tmp, tmp + n);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    refine_fill_kernel<<<grid_for(n), kBlock, 0, s>>>(tmp, tmp + n, w, h, fill_tol, 1, d_out, p_out);
+    (void)tmp;   // the fused kernel keeps its intermediate maps in LDS
+    dim3 grid((w + kRfW - 1) / kRfW, (h + kRfH - 1) / kRfH);
+    refine_fused_kernel<<<grid, kBlock, 0, s>>>(d_in, p_in, w, h, edge_tol, fill_tol, d_out, p_out);
     return hipGetLastError();
 }
 
