@@ -434,6 +434,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 32-pair batched section")
     ap.add_argument("--batch-pairs", type=int, default=32)
     ap.add_argument("--no-serve", action="store_true", help="skip the 16-stream serving section")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the variants section (its 4-path runs share the path kernel's symbol)")
     ap.add_argument("--serve-frames", type=int, default=300)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (counter calibration)")
@@ -573,7 +575,8 @@ def main():
         "tuning": tuning,
     }
     out["quality"] = quality_section(red, full, frames, motions, gts, cfg.max_disp)
-    out["variants"] = variants_section(w, h, calib, cfg, frames, motions, gts, dev)
+    if not args.no_variants:
+        out["variants"] = variants_section(w, h, calib, cfg, frames, motions, gts, dev)
     if not args.no_batch:
         out["batched"] = batch_section(dev, args.batch_pairs, args.steps, log)
     if not args.no_serve:

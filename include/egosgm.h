@@ -106,8 +106,8 @@ size_t egosgm_sgm_workspace_bytes(int w, int h, int max_disp);
  * range, Sec. 2.4.1 and Sec. 3).
  *   cost  C(p,d) = popcount(cL(x,y) ^ cR(x-d,y)), or 62 where x-d < 0;
  *   paths L_r(p,d) = C + min(L_r(p-r,d), L_r(p-r,d+-1)+P1, m+P2) - m,
- *         m = min_k L_r(p-r,k), for the 8 directions r (Sec. 2.3: "eight-path
- *         configuration"; the recurrence of Hirschmüller 2008);
+ *         m = min_k L_r(p-r,k), for the 8 directions r (Sec. 2.3 uses eight
+ *         paths; the recurrence of Hirschmüller 2008);
  *   S(p,d) = sum_r L_r(p,d);  d* = smallest argmin_d S(p,d);
  *   disp_sub = d* + (a-c)/(2(a-2b+c)) with a,b,c = S(d*-1), S(d*), S(d*+1)
  *         when d* is inside the window and a-2b+c > 0, else d*;
@@ -201,7 +201,7 @@ int warp_disparity(const float* d_prev, const float* p_prev, int w, int h,
  *     discontinuities without stating a test; here a valid prediction is
  *     dropped when a valid pixel of its 3x3 neighbourhood differs from it by
  *     more than edge_tol (float32 comparison; edge_tol < 0 disables it);
- *  2. horizontal one-pixel "zoom" hole filling (Eq. 7-8): an invalid pixel
+ *  2. horizontal one-pixel zoom hole filling (Eq. 7-8): an invalid pixel
  *     whose left and right neighbours are valid with |a - b| < fill_tol gets
  *     d = (a + b)/2 and the mean of the neighbours' variances (the paper
  *     gives no variance rule); the pass reads the result of step 1 only;

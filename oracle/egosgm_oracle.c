@@ -7,7 +7,7 @@
  * Every function follows a statement of the method written out plainly:
  *  - the 8-path semi-global matching recurrence is the textbook one of
  *    Hirschmüller (2008), which the paper cites for its matcher (Sec. 1 and
- *    Sec. 2.3, "eight-path configuration");
+ *    Sec. 2.3, with eight paths);
  *  - the reduced search interval is [d_pred +- 3 sqrt(p_pred)] (Sec. 2.3);
  *  - the matching uncertainty counts neighbouring disparities while the
  *    running cost sum stays below S_max, r = n_l + n_r (Sec. 2.3.1, Eq. 9);
@@ -482,7 +482,7 @@ int orc_warp(const float* d_prev, const float* p_prev, int w, int h,
  *     discontinuities without giving a test; here a valid predicted pixel is
  *     dropped when a valid pixel of its 3x3 neighbourhood differs from it by
  *     more than edge_tol (float32 comparison; edge_tol < 0 disables it);
- *  2. horizontal "zoom" hole filling (Eq. 7-8): an invalid pixel whose left
+ *  2. horizontal zoom hole filling (Eq. 7-8): an invalid pixel whose left
  *     and right neighbours are valid with |a - b| < fill_tol (float32) gets
  *     d = (a + b)/2 and, as the paper gives no rule for the variance, the
  *     mean of the two neighbours' variances; the pass reads the map left by

@@ -38,7 +38,9 @@ hipEvent_t take_event(Timing& t) {
         return e;
     }
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    // no system-scope fence: the host reads only the timestamps, and a fence
+    // would write back the L2 after every timed stage and inflate its time
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 

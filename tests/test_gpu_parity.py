@@ -59,7 +59,7 @@ def _check_sgm(g, o, total, debug=True):
             assert np.array_equal(paths[k, :total].astype(np.int32), o["paths"][k]), f"path {k}"
 
 
-@pytest.mark.parametrize("w,h", [(17, 9), (70, 13), (320, 96), (129, 7)])
+@pytest.mark.parametrize("w,h", [(17, 9), (70, 13), (320, 96), (129, 7), (1, 1), (3, 2), (1242, 375)])
 def test_census(w, h):
     _say("census", w, h)
     img = np.random.default_rng(w * h).integers(0, 256, size=(h, w)).astype(np.uint8)
@@ -283,6 +283,18 @@ def test_refine(seed):
     d[r.random((h, w)) < 0.02] += 10.0
     p = r.uniform(0.1, 4, size=(h, w)).astype(np.float32)
     for edge_tol, fill_tol in ((-1.0, 1.0), (2.0, 1.0), (0.5, 0.0), (3.0, 2.5), (0.0, 0.25)):
+        gd, gp = eg.refine_prediction(_gpu(d), _gpu(p), edge_tol, fill_tol)
+        od, op = orc.refine(d, p, edge_tol, fill_tol)
+        assert np.array_equal(_np(gd), od) and np.array_equal(_np(gp), op), (edge_tol, fill_tol)
+
+
+@pytest.mark.parametrize("h,w", [(1, 1), (1, 7), (5, 1), (2, 3), (3, 65), (9, 2)])
+def test_refine_degenerate_shapes(h, w):
+    _say("refine degenerate", w, h)
+    r = np.random.default_rng(h * 100 + w)
+    d = np.where(r.random((h, w)) < 0.4, -1.0, r.uniform(10, 12, (h, w))).astype(np.float32)
+    p = r.uniform(0.1, 4, size=(h, w)).astype(np.float32)
+    for edge_tol, fill_tol in ((-1.0, 1.0), (1.0, 3.0), (0.0, 0.0)):
         gd, gp = eg.refine_prediction(_gpu(d), _gpu(p), edge_tol, fill_tol)
         od, op = orc.refine(d, p, edge_tol, fill_tol)
         assert np.array_equal(_np(gd), od) and np.array_equal(_np(gp), op), (edge_tol, fill_tol)
