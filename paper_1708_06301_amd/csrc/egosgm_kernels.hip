@@ -439,10 +439,15 @@ constexpr int lds_row(int G, int K) { return 2 * G * K + 2; }
 // slots named at compile time, so a step waits only on memory operations
 // issued PF steps earlier.  A zero predecessor row over the first window
 // makes the first step L = C.
-template <int G, int K, int WM, int PF>
+// ODW: chunk 0's costs are prefetched for every pixel, the other chunks'
+// only for pixels where some lane group of the wave has a window wider than
+// G (a wave-uniform test on the prefetched window words), into a ring of
+// their own.  Narrow windows then cost one load per step instead of K.
+template <int G, int K, int WM, int PF, bool ODW = false>
 __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane,
                                     uint16_t* b0, uint16_t* b1) {
     constexpr int RM = 2 * PF;
+    constexpr int KP = ODW ? 1 : K;   // prefetched chunks
     constexpr int ROW = lds_row(G, K);
     // The cost buffer is the same for every lane group of the wave; the path
     // volume is not (groups walk different directions), so it stays a global
@@ -457,9 +462,19 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
     auto load_meta = [&](int j, int pix) { mm[j] = scan_meta<WM>(a, pix); };
 #pragma unroll
     for (int j = 0; j < RM; ++j) load_meta(j, j < len ? p0 + j * dp : p_last);
-    int cst[PF][K];
+    int cst[PF][KP];
+    int wst[PF][K > KP ? K - KP : 1];   // chunks KP.. of wide pixels (ODW)
+    auto load_costs = [&](int slot, uint64_t m) {
+        load_costs_buf<G, KP>(cbuf, meta_off(m), meta_w(m), lane, cst[slot]);
+        if (K > KP && __builtin_amdgcn_ballot_w64(meta_w(m) > G) != 0) {
 #pragma unroll
-    for (int j = 0; j < PF; ++j) load_costs_buf<G, K>(cbuf, meta_off(mm[j]), meta_w(mm[j]), lane, cst[j]);
+            for (int k = KP; k < K; ++k)
+                wst[slot][k - KP] = __builtin_amdgcn_raw_buffer_load_b8(
+                    cbuf, meta_off(m) + (uint32_t)min(lane + G * k, meta_w(m) - 1), 0, 0);
+        }
+    };
+#pragma unroll
+    for (int j = 0; j < PF; ++j) load_costs(j, mm[j]);
 
     for (int e = lane; e < ROW; e += G) {
         b0[e] = kInf;
@@ -491,14 +506,16 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
         const int m2 = m_q + p2;
         int mn = kInf;
         uint32_t done_c = 0;
+        const bool wide = K > 1 && __builtin_amdgcn_ballot_w64(w_c > G) != 0;   // wave-uniform
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int s = lane + G * k;
-            if (k == 0 || __builtin_amdgcn_ballot_w64(s < w_c) != 0) {
+            if (k == 0 || (wide && __builtin_amdgcn_ballot_w64(s < w_c) != 0)) {
                 done_c |= 1u << k;
                 const uint16_t* q = prv + lo_c + s;   // q[0] = d-1, q[1] = d, q[2] = d+1
                 const int best = min(min((int)q[1], min((int)q[0], (int)q[2]) + p1), m2);
-                const int L = cst[tc][k] + best - m_q;
+                const int ck = k < KP ? cst[tc][k < KP ? k : 0] : wst[tc][k >= KP ? k - KP : 0];
+                const int L = ck + best - m_q;
                 const bool in = s < w_c;
                 const int Lm = in ? L : kInf;
                 cur[lo_c + s + 1] = (uint16_t)Lm;
@@ -520,8 +537,7 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
 #pragma unroll
         for (int u = 0; u < RM; ++u) {
             step(u, u % PF, u & 1);
-            load_costs_buf<G, K>(cbuf, meta_off(mm[(u + PF) % RM]), meta_w(mm[(u + PF) % RM]), lane,
-                             cst[u % PF]);
+            load_costs(u % PF, mm[(u + PF) % RM]);
             load_meta(u, (i + u + RM < len) ? p + RM * dp : p_last);
             p += dp;
         }
@@ -531,7 +547,7 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
         if (i + u < len) {
             step(u, u % PF, u & 1);
             if (u + PF < RM)
-                load_costs_buf<G, K>(cbuf, meta_off(mm[u + PF]), meta_w(mm[u + PF]), lane, cst[u % PF]);
+                load_costs(u % PF, mm[u + PF]);
             p += dp;
         }
     }
@@ -968,7 +984,9 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_ragged_kernel(SgmLaunch a, i
         const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
         const int task = n_win_tasks + (blockIdx.x - n_win_blocks) * GPB + grp;
         if (task >= n_tasks) return;
-        lds_scanline<GL, K, kWinRagged, PF>(a, scan_of(task, a.w, a.h), lane, lds[grp][0], lds[grp][1]);
+        // wide chunks on demand at 32 lanes (measured faster there; slower at 16 and 64)
+        lds_scanline<GL, K, kWinRagged, PF, GL == 32>(a, scan_of(task, a.w, a.h), lane, lds[grp][0],
+                                                      lds[grp][1]);
     }
 }
 
