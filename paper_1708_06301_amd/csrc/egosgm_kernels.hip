@@ -974,11 +974,16 @@ template <int SCHED, int NP, int GL, int K, int PF>
 __global__ __launch_bounds__(kBlock) void sgm_paths_ragged_kernel(SgmLaunch a, int n_tasks,
                                                                    int n_win_tasks, int n_win_blocks) {
     if ((int)blockIdx.x < n_win_blocks) {
+        // The long register scanlines are latency-bound, one wave each; the
+        // higher issue priority lets them run at close to their own speed
+        // while the LDS scanlines fill the remaining issue slots.
+        __builtin_amdgcn_s_setprio(2);
         const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
         const int task = (int)blockIdx.x * (kBlock / 64) + wv;
         if (task >= n_win_tasks) return;
         win_scanline<NP, kWinRagged, PF, 4 * PF>(a, scan_of(task, a.w, a.h), lane);
     } else {
+        __builtin_amdgcn_s_setprio(1);
         constexpr int GPB = kBlock / GL;
         __shared__ uint16_t lds[GPB][2][lds_row(GL, K)];
         const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
@@ -1249,8 +1254,8 @@ __global__ __launch_bounds__(kBlock) void paths_batch_kernel(BatchTables t) {
     if (rel >= t.task_count[r]) return;                 // padding
     const SgmLaunch a = pair_of(t, i);
     if (!a.active) return;
-    lds_scanline<G, K, kWinAny, PF>(a, scan_of(t.task_local[r] + rel, a.w, a.h), lane, lds[grp][0],
-                                    lds[grp][1]);
+    lds_scanline<G, K, kWinAny, PF, G == 32>(a, scan_of(t.task_local[r] + rel, a.w, a.h), lane, lds[grp][0],
+                                              lds[grp][1]);
 }
 
 template <int K, int NPATH>
