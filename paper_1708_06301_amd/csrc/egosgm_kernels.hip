@@ -1016,6 +1016,8 @@ __device__ inline void select_segment(const SgmLaunch& a, int seg, int y) {
     constexpr int GPB = kBlock / G;
     __shared__ uint32_t keyR[kSeg + kMaxDisp];
     __shared__ uint16_t sS_all[GPB][G * K];
+    __shared__ float s_sub[kSeg], s_var[kSeg];   // results, stored coalesced at the end
+    __shared__ int16_t s_wta[kSeg];
     const int W = a.w, D = a.win.max_disp;
     const int x0 = seg * kSeg;
     const int base = x0 - (D - 1);
@@ -1055,7 +1057,6 @@ __device__ inline void select_segment(const SgmLaunch& a, int seg, int y) {
             const int i = grp + (t0 + b) * GPB;
             const int x = x0 + i;
             if (x >= W) continue;
-            const int p = y * W + x;
             const int lo = meta_lo(mt[b]);
             const uint32_t off = meta_off(mt[b]);
             const int hi = lo + meta_w(mt[b]) - 1;
@@ -1114,10 +1115,9 @@ __device__ inline void select_segment(const SgmLaunch& a, int seg, int y) {
                         const int den = sa - 2 * sb + sc;
                         if (den > 0) sub = (float)ds + (float)(sa - sc) / (float)(2 * den);
                     }
-                    gptr(a.disp_wta)[p] = (int16_t)ds;
-                    gptr(a.disp_sub)[p] = sub;
-                    gptr(a.var_meas)[p] = (float)n;
-                    if (a.wta_raw) gptr(a.wta_raw)[p] = (int16_t)ds;
+                    s_wta[i] = (int16_t)ds;
+                    s_sub[i] = sub;
+                    s_var[i] = (float)n;
                 }
             } else if (lane == 0) {
                 float sub = (float)ds;
@@ -1138,15 +1138,21 @@ __device__ inline void select_segment(const SgmLaunch& a, int seg, int y) {
                     if (acc >= a.s_max) break;
                     ++n;
                 }
-                gptr(a.disp_wta)[p] = (int16_t)ds;
-                gptr(a.disp_sub)[p] = sub;
-                gptr(a.var_meas)[p] = (float)n;
-                if (a.wta_raw) gptr(a.wta_raw)[p] = (int16_t)ds;
+                s_wta[i] = (int16_t)ds;
+                s_sub[i] = sub;
+                s_var[i] = (float)n;
             }
             lds_order();
         }
     }
     __syncthreads();
+    if (threadIdx.x < kSeg && x0 + (int)threadIdx.x < W) {
+        const int i = (int)threadIdx.x, p = y * W + x0 + i;
+        gptr(a.disp_wta)[p] = s_wta[i];
+        gptr(a.disp_sub)[p] = s_sub[i];
+        gptr(a.var_meas)[p] = s_var[i];
+        if (a.wta_raw) gptr(a.wta_raw)[p] = s_wta[i];
+    }
     for (int i = threadIdx.x; i < kSeg + D - 1; i += kBlock) {
         const int xr = base + i;
         const uint32_t k = keyR[i];
