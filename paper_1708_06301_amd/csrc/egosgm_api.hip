@@ -516,7 +516,8 @@ int sgm_reduced(const uint8_t* left, const uint8_t* right, int w, int h, int pit
 
 size_t egosgm_windows_workspace_bytes(int w, int h) {
     if (w <= 0 || h <= 0) return 0;
-    return align_up((size_t)h * sizeof(uint32_t));
+    const size_t chunks_per_row = ((size_t)w + kWindowChunk - 1) / kWindowChunk;
+    return align_up((size_t)h * chunks_per_row * sizeof(uint32_t));
 }
 
 int sgm_windows_from_prediction(const float* d_pred, const float* p_pred, int w, int h,

@@ -14,6 +14,10 @@ constexpr int kNumPaths = 8;
 
 // Views of the search windows: either the full range (lo = 0, hi = D-1,
 // offset = p*D) or the ragged arrays of sgm_windows_from_prediction.
+// Windows are computed in chunks of kWindowChunk pixels of a row; the
+// workspace holds one total per chunk.
+constexpr int kWindowChunk = 256;
+
 // Census tiles: kCensusTileW x kCensusTileH pixels per 256-thread block,
 // kCensusPx pixels per thread (the plan's block counts use the same shape).
 constexpr int kCensusPx = 4;
@@ -103,7 +107,7 @@ hipError_t launch_sgm_select(const SgmLaunch& a, hipStream_t s);
 hipError_t launch_copy_slots(const SgmLaunch& a, const uint8_t* src, uint8_t* dst, hipStream_t s);
 hipError_t launch_windows(const float* d_pred, const float* p_pred, int w, int h,
                           float k_sigma, int r_fixed, int r_min, int r_max, int max_disp,
-                          int16_t* lo, int16_t* hi, uint32_t* off, uint32_t* row_tot,
+                          int16_t* lo, int16_t* hi, uint32_t* off, uint32_t* chunk_tot,
                           hipStream_t s);
 hipError_t launch_warp(const float* d_prev, const float* p_prev, int w, int h, const float* H,
                        const double* Hd, double q, float* d_pred, float* p_pred,

@@ -172,44 +172,46 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t& excl, uint
     return total;
 }
 
-__global__ __launch_bounds__(kBlock) void windows_row_kernel(
+// Windows in two passes over chunks of kBlock pixels of a row (chunk c of
+// row y is chunk index y*nc + c in raster order).  Pass 1: each chunk's
+// windows, its offsets relative to the chunk start, and the chunk total.
+// Pass 2: each chunk adds the sum of the totals of all earlier chunks.
+static_assert(kWindowChunk == kBlock, "one thread per pixel of a window chunk");
+
+__global__ __launch_bounds__(kBlock) void windows_chunk_kernel(
     const float* __restrict__ d_pred, const float* __restrict__ p_pred, int w, float k_sigma,
     int r_fixed, int r_min, int r_max, int D, int16_t* __restrict__ lo, int16_t* __restrict__ hi,
-    uint32_t* __restrict__ off, uint32_t* __restrict__ row_tot) {
+    uint32_t* __restrict__ off, uint32_t* __restrict__ chunk_tot) {
     __shared__ uint32_t ws[kBlock / 64];
-    const int y = blockIdx.x;
-    uint32_t running = 0;
-    for (int base = 0; base < w; base += kBlock) {
-        const int x = base + threadIdx.x;
-        uint32_t width = 0;
-        const size_t p = (size_t)y * w + x;
-        if (x < w) {
-            int l, u;
-            window_from_prediction(d_pred[p], p_pred, (int)p, k_sigma, r_fixed, r_min, r_max, D,
-                                   l, u);
-            lo[p] = (int16_t)l;
-            hi[p] = (int16_t)u;
-            width = (uint32_t)(u - l + 1);
-        }
-        uint32_t excl;
-        const uint32_t tot = block_exclusive_scan(width, excl, ws);
-        if (x < w) off[p] = running + excl;
-        running += tot;
+    const int y = blockIdx.y, c = blockIdx.x;
+    const int x = c * kBlock + (int)threadIdx.x;
+    const size_t p = (size_t)y * w + x;
+    uint32_t width = 0;
+    if (x < w) {
+        int l, u;
+        window_from_prediction(gptr(d_pred)[p], p_pred, (int)p, k_sigma, r_fixed, r_min, r_max, D, l, u);
+        gptr(lo)[p] = (int16_t)l;
+        gptr(hi)[p] = (int16_t)u;
+        width = (uint32_t)(u - l + 1);
     }
-    if (threadIdx.x == 0) row_tot[y] = running;
+    uint32_t excl;
+    const uint32_t tot = block_exclusive_scan(width, excl, ws);
+    if (x < w) gptr(off)[p] = excl;
+    if (threadIdx.x == 0) gptr(chunk_tot)[(size_t)y * gridDim.x + c] = tot;
 }
 
-__global__ __launch_bounds__(kBlock) void windows_offset_kernel(int w, int h,
-                                                                uint32_t* __restrict__ off,
-                                                                const uint32_t* __restrict__ row_tot) {
+__global__ __launch_bounds__(kBlock) void windows_base_kernel(int w, int h, uint32_t* __restrict__ off,
+                                                              const uint32_t* __restrict__ chunk_tot) {
     __shared__ uint32_t ws[kBlock / 64];
-    const int y = blockIdx.x;
+    const int y = blockIdx.y, c = blockIdx.x, nc = gridDim.x;
+    const int q = y * nc + c;   // this chunk's raster index
     uint32_t part = 0;
-    for (int i = threadIdx.x; i < y; i += kBlock) part += row_tot[i];
+    for (int i = threadIdx.x; i < q; i += kBlock) part += gptr(chunk_tot)[i];
     uint32_t excl;
     const uint32_t base = block_exclusive_scan(part, excl, ws);
-    for (int x = threadIdx.x; x < w; x += kBlock) off[(size_t)y * w + x] += base;
-    if (y == h - 1 && threadIdx.x == 0) off[(size_t)h * w] = base + row_tot[h - 1];
+    const int x = c * kBlock + (int)threadIdx.x;
+    if (x < w) gptr(off)[(size_t)y * w + x] += base;
+    if (q == nc * h - 1 && threadIdx.x == 0) gptr(off)[(size_t)h * w] = base + gptr(chunk_tot)[q];
 }
 
 // ------------------------------------------------------------------ SGM common
@@ -1661,12 +1663,13 @@ hipError_t launch_copy_slots(const SgmLaunch& a, const uint8_t* src, uint8_t* ds
 
 hipError_t launch_windows(const float* d_pred, const float* p_pred, int w, int h, float k_sigma,
                           int r_fixed, int r_min, int r_max, int max_disp, int16_t* lo,
-                          int16_t* hi, uint32_t* off, uint32_t* row_tot, hipStream_t s) {
-    windows_row_kernel<<<h, kBlock, 0, s>>>(d_pred, p_pred, w, k_sigma, r_fixed, r_min, r_max,
-                                            max_disp, lo, hi, off, row_tot);
+                          int16_t* hi, uint32_t* off, uint32_t* chunk_tot, hipStream_t s) {
+    const dim3 grid((w + kBlock - 1) / kBlock, h);
+    windows_chunk_kernel<<<grid, kBlock, 0, s>>>(d_pred, p_pred, w, k_sigma, r_fixed, r_min, r_max,
+                                                 max_disp, lo, hi, off, chunk_tot);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    windows_offset_kernel<<<h, kBlock, 0, s>>>(w, h, off, row_tot);
+    windows_base_kernel<<<grid, kBlock, 0, s>>>(w, h, off, chunk_tot);
     return hipGetLastError();
 }
 
