@@ -983,8 +983,7 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_ragged_kernel(SgmLaunch a, i
         const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
         const int task = (int)blockIdx.x * (kBlock / 64) + wv;
         if (task >= n_win_tasks) return;
-        // costs 6 steps ahead (measured 2% faster than 4 or 8 with the LDS scanlines running)
-        win_scanline<NP, kWinRagged, 6, 24>(a, scan_of(task, a.w, a.h), lane);
+        win_scanline<NP, kWinRagged, PF, 4 * PF>(a, scan_of(task, a.w, a.h), lane);
     } else {
         __builtin_amdgcn_s_setprio(1);
         constexpr int GPB = kBlock / GL;
