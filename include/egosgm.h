@@ -209,11 +209,27 @@ int warp_disparity(const float* d_prev, const float* p_prev, int w, int h,
  * fill_tol <= 0 disables steps 2 and 3.  Means are correctly rounded floats.
  * d_in, p_in: w*h float (a predicted map, e.g. from warp_disparity);
  * d_out, p_out: w*h float, must not alias the inputs; workspace: device
- * memory of egosgm_refine_workspace_bytes(w, h). */
+ * memory of egosgm_refine_workspace_bytes(w, h) (reserved: the current
+ * kernel keeps its intermediate maps on chip). */
 size_t egosgm_refine_workspace_bytes(int w, int h);
 int refine_prediction(const float* d_in, const float* p_in, int w, int h, float edge_tol,
                       float fill_tol, float* d_out, float* p_out, void* workspace,
                       size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------ fused prediction
+ * warp_disparity followed by refine_prediction (Sec. 2.2 and 2.2.2) in three
+ * kernels instead of four: the refinement decodes the warp's z-buffer itself,
+ * so the unrefined prediction never goes through memory.  d_pred / p_pred are
+ * bit-identical to refine_prediction(warp_disparity(...)) with the same
+ * arguments.  d_prev, p_prev: w*h float; R, t, f, cx, cy, baseline, q as
+ * warp_disparity; edge_tol, fill_tol as refine_prediction; d_pred, p_pred:
+ * w*h float, must not alias the inputs; zbuf: w*h uint64 scratch owned by the
+ * caller (contents on entry ignored, on return undefined).  EINVAL on NULL,
+ * bad sizes, aliasing, q <= 0 or not finite, or NaN tolerances. */
+int predict_disparity(const float* d_prev, const float* p_prev, int w, int h, const double* R,
+                      const double* t, double f, double cx, double cy, double baseline, float q,
+                      float edge_tol, float fill_tol, float* d_pred, float* p_pred, uint64_t* zbuf,
+                      void* stream);
 
 /* ------------------------------------------------------------------ prediction LR check
  * Left-right check of the *prediction* (Sec. 2.4.1; Fig. 4 orders it after

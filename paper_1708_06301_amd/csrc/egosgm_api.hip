@@ -610,6 +610,32 @@ int warp_disparity(const float* d_prev, const float* p_prev, int w, int h, const
                : EGOSGM_EDEVICE;
 }
 
+int predict_disparity(const float* d_prev, const float* p_prev, int w, int h, const double* R,
+                      const double* t, double f, double cx, double cy, double baseline, float q,
+                      float edge_tol, float fill_tol, float* d_pred, float* p_pred, uint64_t* zbuf,
+                      void* stream) {
+    if (!d_prev || !p_prev || !d_pred || !p_pred || !zbuf) return EGOSGM_EINVAL;
+    if (w <= 0 || h <= 0 || (long long)w * h >= (1ll << 31)) return EGOSGM_EINVAL;
+    if (!(q > 0.0f) || !std::isfinite(q)) return EGOSGM_EINVAL;
+    if (std::isnan(edge_tol) || std::isnan(fill_tol)) return EGOSGM_EINVAL;
+    if (d_pred == d_prev || d_pred == p_prev || p_pred == d_prev || p_pred == p_prev) return EGOSGM_EINVAL;
+    double Hd[16];
+    float H[16];
+    const int rc = warp_matrix_d(R, t, f, cx, cy, baseline, Hd);
+    if (rc) return rc;
+    for (int i = 0; i < 16; ++i) H[i] = (float)Hd[i];
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned long long* z = reinterpret_cast<unsigned long long*>(zbuf);
+    if (timed(EGOSGM_STAGE_WARP, s, [&] { return launch_warp_scatter(d_prev, w, h, H, z, s); }) != hipSuccess)
+        return EGOSGM_EDEVICE;
+    return timed(EGOSGM_STAGE_REFINE, s, [&] {
+               return launch_refine_from_zbuf(z, d_prev, p_prev, w, h, Hd, (double)q, edge_tol,
+                                              fill_tol, d_pred, p_pred, s);
+           }) == hipSuccess
+               ? EGOSGM_OK
+               : EGOSGM_EDEVICE;
+}
+
 size_t egosgm_refine_workspace_bytes(int w, int h) {
     if (w <= 0 || h <= 0) return 0;
     return align_up((size_t)w * h * 2 * sizeof(float));

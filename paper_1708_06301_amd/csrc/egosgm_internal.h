@@ -112,6 +112,12 @@ hipError_t launch_windows(const float* d_pred, const float* p_pred, int w, int h
 hipError_t launch_warp(const float* d_prev, const float* p_prev, int w, int h, const float* H,
                        const double* Hd, double q, float* d_pred, float* p_pred,
                        unsigned long long* zbuf, hipStream_t s);
+hipError_t launch_warp_scatter(const float* d_prev, int w, int h, const float* H,
+                               unsigned long long* zbuf, hipStream_t s);
+hipError_t launch_refine_from_zbuf(const unsigned long long* zbuf, const float* d_prev,
+                                   const float* p_prev, int w, int h, const double* Hd, double q,
+                                   float edge_tol, float fill_tol, float* d_out, float* p_out,
+                                   hipStream_t s);
 hipError_t launch_refine(const float* d_in, const float* p_in, int w, int h, float edge_tol,
                          float fill_tol, float* d_out, float* p_out, float* tmp, hipStream_t s);
 hipError_t launch_sad_check(const uint8_t* left, const uint8_t* right, int w, int h, int pitch,

@@ -1399,7 +1399,27 @@ __global__ __launch_bounds__(kBlock) void warp_scatter_kernel(const float* __res
 }
 
 // Value pass: the winner's d' = d/omega_3 and p' = (d'/d)^2 p + q in double
-// (row 2 of H is exactly (0,0,1,0), so omega_2 = d), rounded once to float.
+// (row 2 of H is exactly (0,0,1,0), so omega_2 = d), rounded once to float;
+// a target without a winner is (-1, 0).
+__device__ inline void warp_value(unsigned long long k, const float* __restrict__ d_prev,
+                                  const float* __restrict__ p_prev, int w, const Mat4d& H, double q,
+                                  float& d_out, float& p_out) {
+    if (k == ~0ull) {
+        d_out = -1.0f;
+        p_out = 0.0f;
+        return;
+    }
+    const int src = (int)(uint32_t)k;
+    const double x = (double)(src % w), y = (double)(src / w);
+    const double d = (double)gptr(d_prev)[src], p = (double)gptr(p_prev)[src];
+    const double* m = H.m;
+    const double o3 = m[12] * x + m[13] * y + m[14] * d + m[15];
+    const double dn = d / o3;
+    const double phi = dn / d;
+    d_out = (float)dn;
+    p_out = (float)(phi * phi * p + q);
+}
+
 __global__ __launch_bounds__(kBlock) void warp_decode_kernel(const unsigned long long* zbuf,
                                                              const float* __restrict__ d_prev,
                                                              const float* __restrict__ p_prev,
@@ -1408,21 +1428,10 @@ __global__ __launch_bounds__(kBlock) void warp_decode_kernel(const unsigned long
                                                              float* __restrict__ p_pred) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    const unsigned long long k = zbuf[i];
-    if (k == ~0ull) {
-        d_pred[i] = -1.0f;
-        p_pred[i] = 0.0f;
-        return;
-    }
-    const int src = (int)(uint32_t)k;
-    const double x = (double)(src % w), y = (double)(src / w);
-    const double d = (double)d_prev[src], p = (double)p_prev[src];
-    const double* m = H.m;
-    const double o3 = m[12] * x + m[13] * y + m[14] * d + m[15];
-    const double dn = d / o3;
-    const double phi = dn / d;
-    d_pred[i] = (float)dn;
-    p_pred[i] = (float)(phi * phi * p + q);
+    float d, p;
+    warp_value(gptr(zbuf)[i], d_prev, p_prev, w, H, q, d, p);
+    gptr(d_pred)[i] = d;
+    gptr(p_pred)[i] = p;
 }
 
 // ------------------------------------------------------------------ refinement
@@ -1440,24 +1449,44 @@ __global__ __launch_bounds__(kBlock) void warp_decode_kernel(const unsigned long
 // as it skips invalid neighbours; the fills never read them.
 constexpr int kRfW = 64, kRfH = kBlock / kRfW;
 
-__global__ __launch_bounds__(kBlock) void refine_fused_kernel(const float* __restrict__ d_in,
-                                                              const float* __restrict__ p_in,
-                                                              int w, int h, float edge_tol,
-                                                              float fill_tol,
+// Input of the refinement: a predicted map (d_in, p_in), or, with
+// FROM_ZBUF, the warp's z-buffer decoded on the fly (warp_value), so the
+// prediction itself never goes through memory.
+struct RefineSrc {
+    const float* d_in;
+    const float* p_in;
+    const unsigned long long* zbuf;   // FROM_ZBUF: winners; d_in / p_in are the previous map
+    Mat4d H;
+    double q;
+};
+
+template <bool FROM_ZBUF>
+__global__ __launch_bounds__(kBlock) void refine_fused_kernel(RefineSrc src, int w, int h,
+                                                              float edge_tol, float fill_tol,
                                                               float* __restrict__ d_out,
                                                               float* __restrict__ p_out) {
     constexpr int AW = kRfW + 4, AH = kRfH + 4;   // input, halo 2
     constexpr int EW = kRfW + 2, EH = kRfH + 2;   // after the edge test, halo 1
     __shared__ float sd[AH][AW], sp[AH][AW], ed[EH][EW], ep[EH][EW], hd[EH][kRfW], hp[EH][kRfW];
     const int x0 = blockIdx.x * kRfW, y0 = blockIdx.y * kRfH;
-    const gmem<const float>* gd = gptr(d_in);
-    const gmem<const float>* gp = gptr(p_in);
+    const gmem<const float>* gd = gptr(src.d_in);
+    const gmem<const float>* gp = gptr(src.p_in);
     for (int t = threadIdx.x; t < AW * AH; t += kBlock) {
         const int r = t / AW, c = t - r * AW;
         const int gx = x0 + c - 2, gy = y0 + r - 2;
         const bool in = gx >= 0 && gx < w && gy >= 0 && gy < h;
-        sd[r][c] = in ? gd[(size_t)gy * w + gx] : -1.0f;
-        sp[r][c] = in ? gp[(size_t)gy * w + gx] : 0.0f;
+        float dv = -1.0f, pv = 0.0f;
+        if (in) {
+            const size_t i = (size_t)gy * w + gx;
+            if (FROM_ZBUF) {
+                warp_value(gptr(src.zbuf)[i], src.d_in, src.p_in, w, src.H, src.q, dv, pv);
+            } else {
+                dv = gd[i];
+                pv = gp[i];
+            }
+        }
+        sd[r][c] = dv;
+        sp[r][c] = pv;
     }
     __syncthreads();
     for (int t = threadIdx.x; t < EW * EH; t += kBlock) {
@@ -1770,11 +1799,41 @@ hipError_t launch_warp(const float* d_prev, const float* p_prev, int w, int h, c
     return hipGetLastError();
 }
 
+hipError_t launch_warp_scatter(const float* d_prev, int w, int h, const float* H,
+                               unsigned long long* zbuf, hipStream_t s) {
+    const size_t n = (size_t)w * h;
+    Mat4 m;
+    for (int i = 0; i < 16; ++i) m.m[i] = H[i];
+    fill_u64_kernel<<<grid_for(n), kBlock, 0, s>>>(zbuf, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    warp_scatter_kernel<<<grid_for(n), kBlock, 0, s>>>(d_prev, w, h, m, zbuf);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_from_zbuf(const unsigned long long* zbuf, const float* d_prev,
+                                   const float* p_prev, int w, int h, const double* Hd, double q,
+                                   float edge_tol, float fill_tol, float* d_out, float* p_out,
+                                   hipStream_t s) {
+    dim3 grid((w + kRfW - 1) / kRfW, (h + kRfH - 1) / kRfH);
+    RefineSrc src{};
+    src.d_in = d_prev;
+    src.p_in = p_prev;
+    src.zbuf = zbuf;
+    for (int i = 0; i < 16; ++i) src.H.m[i] = Hd[i];
+    src.q = q;
+    refine_fused_kernel<true><<<grid, kBlock, 0, s>>>(src, w, h, edge_tol, fill_tol, d_out, p_out);
+    return hipGetLastError();
+}
+
 hipError_t launch_refine(const float* d_in, const float* p_in, int w, int h, float edge_tol,
                          float fill_tol, float* d_out, float* p_out, float* tmp, hipStream_t s) {
     (void)tmp;   // the fused kernel keeps its intermediate maps in LDS
     dim3 grid((w + kRfW - 1) / kRfW, (h + kRfH - 1) / kRfH);
-    refine_fused_kernel<<<grid, kBlock, 0, s>>>(d_in, p_in, w, h, edge_tol, fill_tol, d_out, p_out);
+    RefineSrc src{};
+    src.d_in = d_in;
+    src.p_in = p_in;
+    refine_fused_kernel<false><<<grid, kBlock, 0, s>>>(src, w, h, edge_tol, fill_tol, d_out, p_out);
     return hipGetLastError();
 }
 

@@ -34,6 +34,7 @@ _SIGS = {
                      _sz, _vp], _i),
     "egosgm_warp_matrix": ([_vp, _vp, _d, _d, _d, _d, _vp], _i),
     "warp_disparity": ([_vp, _vp, _i, _i, _vp, _vp, _d, _d, _d, _d, _f, _vp, _vp, _vp, _vp], _i),
+    "predict_disparity": ([_vp, _vp, _i, _i, _vp, _vp, _d, _d, _d, _d, _f, _f, _f, _vp, _vp, _vp, _vp], _i),
     "kalman_update": ([_vp, _vp, _vp, _vp, _i, _i, _vp, _vp, _vp], _i),
     "egosgm_refine_workspace_bytes": ([_i, _i], _sz),
     "refine_prediction": ([_vp, _vp, _i, _i, _f, _f, _vp, _vp, _vp, _sz, _vp], _i),
@@ -333,6 +334,27 @@ def warp_disparity(d_prev: torch.Tensor, p_prev: torch.Tensor, R, t, f, cx, cy, 
                               t.ctypes.data_as(_vp), f, cx, cy, baseline, q, _ptr(out[0]),
                               _ptr(out[1]), _ptr(zbuf), _stream())
     _check(rc, "warp_disparity")
+    return out
+
+
+def predict_disparity(d_prev: torch.Tensor, p_prev: torch.Tensor, R, t, f, cx, cy, baseline, q,
+                      edge_tol=2.0, fill_tol=1.0, out=None, zbuf: torch.Tensor | None = None):
+    """warp_disparity + refine_prediction in one call (bit-identical)."""
+    _need(d_prev, torch.float32, name="d_prev")
+    h, w = d_prev.shape
+    _need(p_prev, torch.float32, h * w, "p_prev")
+    dev = d_prev.device
+    if out is None:
+        out = (torch.empty((h, w), dtype=torch.float32, device=dev),
+               torch.empty((h, w), dtype=torch.float32, device=dev))
+    if zbuf is None:
+        zbuf = torch.empty(h * w, dtype=torch.int64, device=dev)
+    R = np.ascontiguousarray(R, dtype=np.float64).ravel()
+    t = np.ascontiguousarray(t, dtype=np.float64).ravel()
+    rc = lib().predict_disparity(_ptr(d_prev), _ptr(p_prev), w, h, R.ctypes.data_as(_vp),
+                                 t.ctypes.data_as(_vp), f, cx, cy, baseline, q, edge_tol, fill_tol,
+                                 _ptr(out[0]), _ptr(out[1]), _ptr(zbuf), _stream())
+    _check(rc, "predict_disparity")
     return out
 
 

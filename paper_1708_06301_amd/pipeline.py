@@ -67,8 +67,6 @@ class StreamState:
         f32 = dict(dtype=torch.float32, device=dev)
         self.d = torch.full((h, w), -1.0, **f32)     # D^{k}
         self.p = torch.zeros((h, w), **f32)          # P^{k}
-        self.d_warp = torch.empty((h, w), **f32)
-        self.p_warp = torch.empty((h, w), **f32)
         self.d_pred = torch.empty((h, w), **f32)
         self.p_pred = torch.empty((h, w), **f32)
         self.zbuf = torch.empty(n, dtype=torch.int64, device=dev)
@@ -109,10 +107,11 @@ class StreamState:
         if self.full_range_next():
             return None
         cfg, c = self.cfg, self.calib
-        eg.warp_disparity(self.d, self.p, R, t, c.f, c.cx, c.cy, c.baseline, cfg.q,
-                          out=(self.d_warp, self.p_warp), zbuf=self.zbuf)
-        eg.refine_prediction(self.d_warp, self.p_warp, cfg.edge_tol, cfg.fill_tol,
-                             out=(self.d_pred, self.p_pred), workspace=self.ws)
+        # warp (Sec. 2.2) and refinement (Sec. 2.2.2), fused: the refinement
+        # decodes the warp's z-buffer itself
+        eg.predict_disparity(self.d, self.p, R, t, c.f, c.cx, c.cy, c.baseline, cfg.q,
+                             cfg.edge_tol, cfg.fill_tol, out=(self.d_pred, self.p_pred),
+                             zbuf=self.zbuf)
         if cfg.lr_predict:
             # Fig. 4 (d): the right map is predicted the same way, with the
             # right camera's motion, and the left prediction checked against it
@@ -161,7 +160,7 @@ class StreamState:
     def resident_bytes(self) -> int:
         """Device bytes this stream holds (maps, prediction buffers, windows,
         outputs and workspaces)."""
-        ts = [self.d, self.p, self.d_warp, self.p_warp, self.d_pred, self.p_pred, self.zbuf,
+        ts = [self.d, self.p, self.d_pred, self.p_pred, self.zbuf,
               self.lo, self.hi, self.off, self.invalid, self.zeros, *self.out.values(),
               *[getattr(self, k, None) for k in ("d_r", "d_rwarp", "p_rwarp", "d_rpred", "p_rpred")],
               self.ws.sgm, self.ws.win, getattr(self.ws, "ref", None)]

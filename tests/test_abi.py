@@ -173,3 +173,20 @@ def test_prediction_lr_check_validation(orc):
         Rr, tr = eg.right_motion(R, t, base)
         assert np.array_equal(Rr, R)
         assert np.allclose(tr, orc.right_motion(R, t, base), rtol=0, atol=1e-15)
+
+
+def test_predict_disparity_validation():
+    lib = eg.lib()
+    f = FAKE
+    R = (C.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1)
+    t = (C.c_double * 3)(0, 0, -1)
+    args = lambda **kw: dict(dict(dp=f, pp=f, w=10, h=10, q=0.5, et=2.0, ft=1.0, do=C.c_void_p(0x2000),
+                                  po=C.c_void_p(0x3000), z=f), **kw)
+    def call(a):
+        return lib.predict_disparity(a["dp"], a["pp"], a["w"], a["h"], R, t, 700.0, 5.0, 5.0, 0.5, a["q"],
+                                     a["et"], a["ft"], a["do"], a["po"], a["z"], None)
+    assert call(args(dp=None)) == -1
+    assert call(args(w=0)) == -1
+    assert call(args(q=0.0)) == -1
+    assert call(args(et=float("nan"))) == -1
+    assert call(args(do=f)) == -1          # output aliases an input

@@ -214,6 +214,22 @@ def test_windows_edge_values():
     assert np.array_equal(_np(off).view(np.uint32), wo[2])
 
 
+@pytest.mark.parametrize("w,h", [(256, 3), (257, 2), (513, 5), (700, 4), (1, 9)])
+def test_windows_across_row_chunks(w, h):
+    """Offsets are built per 256-pixel chunk of a row and then shifted by
+    the earlier chunks' totals: widths on and around chunk boundaries."""
+    _say("windows chunks", w, h)
+    D = 96
+    r = np.random.default_rng(w * 7 + h)
+    d = r.uniform(-5, 100, (h, w)).astype(np.float32)
+    p = r.uniform(0, 30, (h, w)).astype(np.float32)
+    for r_fixed in (-1, 3):
+        lo, hi, off = eg.windows_from_prediction(_gpu(d), _gpu(p), D, r_fixed=r_fixed, r_min=0, r_max=40)
+        wo = orc.windows(d.ravel(), p.ravel(), D, r_fixed=r_fixed, r_min=0, r_max=40)
+        assert np.array_equal(_np(lo).ravel(), wo[0]) and np.array_equal(_np(hi).ravel(), wo[1])
+        assert np.array_equal(_np(off).view(np.uint32), wo[2])
+
+
 def _rot(a, b, c):
     ca, sa, cb, sb, cc, sc = np.cos(a), np.sin(a), np.cos(b), np.sin(b), np.cos(c), np.sin(c)
     return (np.array([[ca, 0, sa], [0, 1, 0], [-sa, 0, ca]]) @
@@ -298,6 +314,27 @@ def test_refine_degenerate_shapes(h, w):
         gd, gp = eg.refine_prediction(_gpu(d), _gpu(p), edge_tol, fill_tol)
         od, op = orc.refine(d, p, edge_tol, fill_tol)
         assert np.array_equal(_np(gd), od) and np.array_equal(_np(gp), op), (edge_tol, fill_tol)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_predict_disparity_equals_warp_then_refine(seed):
+    """The fused prediction decodes the z-buffer inside the refinement; its
+    maps must be bit-identical to warp_disparity followed by refine_prediction."""
+    r = np.random.default_rng(70 + seed)
+    w, h = (1242, 375) if seed == 0 else (int(r.integers(3, 300)), int(r.integers(2, 120)))
+    _say("predict fused", w, h, seed)
+    base = np.cumsum(r.normal(0, 0.3, size=(h, w)), axis=1).astype(np.float32) + 30
+    d = np.where(r.random((h, w)) < 0.1, -1.0, base).astype(np.float32)
+    p = r.uniform(0.01, 5, size=(h, w)).astype(np.float32)
+    R = _rot(*r.normal(0, 0.01, 3))
+    t = np.array([r.normal(0, 0.05), r.normal(0, 0.02), -abs(r.normal(1.0, 0.2))])
+    f = 718.0 * w / 1242.0
+    cam = (f, (w - 1) / 2, (h - 1) / 2, 0.54)
+    for edge_tol, fill_tol in ((2.0, 1.0), (-1.0, 0.0), (0.5, 3.0)):
+        gd, gp = eg.warp_disparity(_gpu(d), _gpu(p), R, t, *cam, 0.5)
+        rd, rp = eg.refine_prediction(gd, gp, edge_tol, fill_tol)
+        fd, fp = eg.predict_disparity(_gpu(d), _gpu(p), R, t, *cam, 0.5, edge_tol, fill_tol)
+        assert np.array_equal(_np(fd), _np(rd)) and np.array_equal(_np(fp), _np(rp)), (edge_tol, fill_tol)
 
 
 def test_kalman():
