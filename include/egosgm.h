@@ -6,6 +6,8 @@
  * The method (Sec. 2) runs, per stereo frame k:
  *   disparity prediction  D^{k|k-1}, P^{k|k-1} from D^{k-1}, P^{k-1} and the
  *                         ego-motion (Sec. 2.1-2.2)          -> warp_disparity
+ *   refinement            edge rejection, zoom hole filling (Sec. 2.2.2)
+ *                         -> refine_prediction (or both in predict_disparity)
  *   search windows        [d^{k|k-1} +- 3 sqrt(p^{k|k-1})] (Sec. 2.3)
  *                                                 -> sgm_windows_from_prediction
  *   stereo matching       census + 8-path SGM over those windows, matching
@@ -57,7 +59,7 @@ typedef enum egosgm_status {
     EGOSGM_EUNSUPPORTED = -4 /* valid request this build does not implement    */
 } egosgm_status;
 
-/* Matcher parameters.  The paper fixes none of them (it names a [3x3]
+/* Matcher parameters.  The paper fixes none of them (it names a 3x3
  * matching window and S_max = 10 for it, Sec. 2.3.1); the values used for
  * the street sequences are D = 128, P1 = 10, P2 = 120, S_max = 80, lr_tol = 1. */
 typedef struct egosgm_sgm_params {
