@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define EGOSGM_ABI_VERSION 1
+#define EGOSGM_ABI_VERSION 2
 
 /* Largest disparity range and the census window (9 wide, 7 tall: 62 bits). */
 #define EGOSGM_MAX_DISP 256
@@ -70,6 +70,10 @@ typedef struct egosgm_sgm_params {
     int32_t lr_tol;   /* left-right tolerance in pixels; < 0 disables the check */
     int32_t n_paths;  /* aggregated directions: 8 (0 means 8), or 4 for the cheaper
                          variant along and against the rows and the columns       */
+    int32_t census_ready; /* 0: the call computes the census codes; 1: sgm_census
+                         already wrote them (and reset the right-map keys) into
+                         this workspace, e.g. on another stream, ordered before
+                         this call.  Plans require 0.                             */
 } egosgm_sgm_params;
 
 /* Optional intermediate outputs for inspection (each member nullable; the
@@ -127,6 +131,17 @@ int sgm_full(const uint8_t* left, const uint8_t* right, int w, int h, int pitch,
              const egosgm_sgm_params* params, int16_t* disp_wta, float* disp_sub,
              float* var_meas, int16_t* disp_right, const egosgm_debug* debug,
              void* workspace, size_t workspace_bytes, void* stream);
+
+/* The census pass of sgm_full / sgm_reduced on its own (the 9x7 census of
+ * both images, Sec. 2.3.1's matching cost, and the reset of the right-map
+ * keys), into `workspace` as those calls lay it out for (w, h, max_disp).
+ * A following sgm_full / sgm_reduced on the same workspace with
+ * census_ready = 1 skips its own census pass, so the census can run on
+ * another stream while the prediction of the frame runs; the caller orders
+ * the two (an event) and must not start it before the previous matcher call
+ * on this workspace has finished.  EINVAL / EWORKSPACE as sgm_full. */
+int sgm_census(const uint8_t* left, const uint8_t* right, int w, int h, int pitch, int max_disp,
+               void* workspace, size_t workspace_bytes, void* stream);
 
 /* Workspace bytes for sgm_windows_from_prediction on a w x h map. */
 size_t egosgm_windows_workspace_bytes(int w, int h);

@@ -101,6 +101,7 @@ int check_params(const egosgm_sgm_params* prm) {
     if (prm->p1 < 0 || prm->p2 < prm->p1 || prm->p2 > 255 - kCensusBits) return EGOSGM_EINVAL;
     if (prm->s_max < 0) return EGOSGM_EINVAL;
     if (prm->n_paths != 0 && prm->n_paths != 4 && prm->n_paths != 8) return EGOSGM_EINVAL;
+    if (prm->census_ready != 0 && prm->census_ready != 1) return EGOSGM_EINVAL;
     return EGOSGM_OK;
 }
 
@@ -152,7 +153,7 @@ int run_sgm(const uint8_t* left, const uint8_t* right, int w, int h, int pitch, 
     a.wta_raw = dbg ? dbg->wta_raw : nullptr;
 
     const size_t n = (size_t)w * h;
-    if (timed(EGOSGM_STAGE_CENSUS, s, [&] {
+    if (!prm->census_ready && timed(EGOSGM_STAGE_CENSUS, s, [&] {
             return launch_census_pair(left, right, w, h, pitch, const_cast<uint64_t*>(a.census_l),
                                       const_cast<uint64_t*>(a.census_r), a.key_r, s);
         }) != hipSuccess)
@@ -249,7 +250,7 @@ int sgm_plan_create(const egosgm_pair* pairs, int n, const egosgm_sgm_params* pa
                     void* workspace, size_t workspace_bytes, egosgm_plan** out) {
     if (!pairs || n <= 0 || !out) return EGOSGM_EINVAL;
     *out = nullptr;
-    if (!params) return EGOSGM_EINVAL;
+    if (!params || params->census_ready) return EGOSGM_EINVAL;   // a plan computes its census itself
     egosgm_sgm_params prm = *params;
     int max_disp = 1;
     for (int i = 0; i < n; ++i) {
@@ -512,6 +513,27 @@ int sgm_reduced(const uint8_t* left, const uint8_t* right, int w, int h, int pit
     return run_sgm(left, right, w, h, pitch, win, params, disp_wta, disp_sub, var_meas,
                    disp_right, debug, workspace, workspace_bytes,
                    static_cast<hipStream_t>(stream));
+}
+
+int sgm_census(const uint8_t* left, const uint8_t* right, int w, int h, int pitch, int max_disp,
+               void* workspace, size_t workspace_bytes, void* stream) {
+    if (!left || !right) return EGOSGM_EINVAL;
+    const int rc = check_shape(w, h, max_disp);
+    if (rc) return rc;
+    if (pitch < w) return EGOSGM_EINVAL;
+    WsLayout L;
+    ws_layout(w, h, max_disp, L);
+    if (!workspace || workspace_bytes < L.total) return EGOSGM_EWORKSPACE;
+    uint8_t* base = static_cast<uint8_t*>(workspace);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return timed(EGOSGM_STAGE_CENSUS, s, [&] {
+               return launch_census_pair(left, right, w, h, pitch,
+                                         reinterpret_cast<uint64_t*>(base + L.census_l),
+                                         reinterpret_cast<uint64_t*>(base + L.census_r),
+                                         reinterpret_cast<uint32_t*>(base + L.key_r), s);
+           }) == hipSuccess
+               ? EGOSGM_OK
+               : EGOSGM_EDEVICE;
 }
 
 size_t egosgm_windows_workspace_bytes(int w, int h) {

@@ -34,6 +34,7 @@ _SIGS = {
                      _sz, _vp], _i),
     "egosgm_warp_matrix": ([_vp, _vp, _d, _d, _d, _d, _vp], _i),
     "warp_disparity": ([_vp, _vp, _i, _i, _vp, _vp, _d, _d, _d, _d, _f, _vp, _vp, _vp, _vp], _i),
+    "sgm_census": ([_vp, _vp, _i, _i, _i, _i, _vp, _sz, _vp], _i),
     "predict_disparity": ([_vp, _vp, _i, _i, _vp, _vp, _d, _d, _d, _d, _f, _f, _f, _vp, _vp, _vp, _vp], _i),
     "kalman_update": ([_vp, _vp, _vp, _vp, _i, _i, _vp, _vp, _vp], _i),
     "egosgm_refine_workspace_bytes": ([_i, _i], _sz),
@@ -86,7 +87,8 @@ def _check(rc: int, what: str):
 
 class SgmParams(C.Structure):
     _fields_ = [("max_disp", C.c_int32), ("p1", C.c_int32), ("p2", C.c_int32),
-                ("s_max", C.c_int32), ("lr_tol", C.c_int32), ("n_paths", C.c_int32)]
+                ("s_max", C.c_int32), ("lr_tol", C.c_int32), ("n_paths", C.c_int32),
+                ("census_ready", C.c_int32)]
 
 
 class SgmDebug(C.Structure):
@@ -126,9 +128,11 @@ class MatchParams:
     s_max: int = 80
     lr_tol: int = 1
     n_paths: int = 8       # or 4: along and against the rows and the columns only
+    census_ready: int = 0  # 1: sgm_census already filled the workspace's census codes
 
     def c(self) -> SgmParams:
-        return SgmParams(self.max_disp, self.p1, self.p2, self.s_max, self.lr_tol, self.n_paths)
+        return SgmParams(self.max_disp, self.p1, self.p2, self.s_max, self.lr_tol, self.n_paths,
+                         self.census_ready)
 
 
 def _stream():
@@ -251,6 +255,20 @@ def sgm_full(left: torch.Tensor, right: torch.Tensor, params: MatchParams | None
         o = dict(o)
         o.update(dbg)
     return o
+
+
+def sgm_census(left: torch.Tensor, right: torch.Tensor, max_disp: int,
+               workspace: Workspace | None = None):
+    """The matcher's census pass alone, into the workspace; a following
+    sgm_full / sgm_reduced with census_ready=1 on that workspace skips it."""
+    _need(left, torch.uint8, name="left")
+    _need(right, torch.uint8, name="right")
+    h, w = left.shape
+    if right.shape != left.shape:
+        raise EgoSgmError("left/right shapes differ")
+    ws, nbytes = (workspace or _ws(left.device)).sgm_bytes(w, h, max_disp)
+    _check(lib().sgm_census(_ptr(left), _ptr(right), w, h, w, max_disp, _ptr(ws), nbytes, _stream()),
+           "sgm_census")
 
 
 def windows_from_prediction(d_pred: torch.Tensor, p_pred: torch.Tensor | None, max_disp: int,

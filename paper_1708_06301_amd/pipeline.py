@@ -48,6 +48,7 @@ class FrameConfig:
     sad_max: int = 600
     lr_predict: bool = False  # left-right check of the prediction against the warped right map
     lr_predict_tol: float = 1.0
+    overlap_census: bool = False  # step(): census on a second stream (measured 2% slower here)
 
     def match(self) -> eg.MatchParams:
         return eg.MatchParams(self.max_disp, self.p1, self.p2, self.s_max, self.lr_tol,
@@ -85,6 +86,12 @@ class StreamState:
         self.ws.refine_bytes(w, h)
         self.invalid = torch.full((h, w), -1.0, **f32)
         self.zeros = torch.zeros((h, w), **f32)
+        # step() runs the matcher's census on a second stream (default
+        # priority) while the prediction of the frame runs on the caller's
+        self.side = torch.cuda.Stream(device=dev) if own_matcher and cfg.overlap_census else None
+        self.ev_census = torch.cuda.Event() if self.side is not None else None
+        self.ev_matched = torch.cuda.Event() if self.side is not None else None
+        self.census_pending = False
         if cfg.lr_predict:   # right map of the previous frame and its prediction
             self.d_r = torch.full((h, w), -1.0, **f32)
             self.d_rwarp = torch.empty((h, w), **f32)
@@ -126,13 +133,31 @@ class StreamState:
                                    out=(self.lo, self.hi, self.off), workspace=self.ws)
         return self.lo, self.hi, self.off
 
+    def census_ahead(self, left: torch.Tensor, right: torch.Tensor):
+        """Starts the matcher's census pass of this frame on the second
+        stream, after the previous frame's matcher is done with the
+        workspace; match() then waits for it and skips its own."""
+        self.side.wait_event(self.ev_matched)
+        with torch.cuda.stream(self.side):
+            eg.sgm_census(left, right, self.cfg.max_disp, workspace=self.ws)
+            self.ev_census.record(self.side)
+        left.record_stream(self.side)    # the allocator must not hand them out before
+        right.record_stream(self.side)   # the side stream is done with them
+        self.census_pending = True
+
     def match(self, left: torch.Tensor, right: torch.Tensor, windows):
         """Stereo matching of this frame into self.out (Sec. 2.3)."""
         prm = self.cfg.match()
+        if self.census_pending:
+            torch.cuda.current_stream(self.device).wait_event(self.ev_census)
+            prm.census_ready = 1
+            self.census_pending = False
         if windows is None:
             eg.sgm_full(left, right, prm, out=self.out, workspace=self.ws)
         else:
             eg.sgm_reduced(left, right, *windows, prm, out=self.out, workspace=self.ws)
+        if self.side is not None:
+            self.ev_matched.record(torch.cuda.current_stream(self.device))
         self.filter(left, right, self.out)
 
     def filter(self, left, right, out):
@@ -169,6 +194,8 @@ class StreamState:
     def step(self, left: torch.Tensor, right: torch.Tensor, R=None, t=None):
         """Processes one stereo frame; R, t map the previous camera frame to
         this one (M_k = R M_{k-1} + t).  Returns the updated (d, p) maps."""
+        if self.side is not None:
+            self.census_ahead(left, right)
         win = self.predict(R, t)
         self.match(left, right, win)
         return self.update()

@@ -26,7 +26,7 @@ def test_every_declared_symbol_is_exported():
     lib = eg.lib()
     for n in names:
         assert hasattr(lib, n), n
-    assert eg.abi_version() == 1
+    assert eg.abi_version() == 2
 
 
 def test_workspace_sizes():
@@ -42,7 +42,7 @@ FAKE = C.c_void_p(0x1000)   # never dereferenced: validation fails first
 
 
 def _prm(**kw):
-    base = dict(max_disp=64, p1=10, p2=120, s_max=80, lr_tol=1, n_paths=8)
+    base = dict(max_disp=64, p1=10, p2=120, s_max=80, lr_tol=1, n_paths=8, census_ready=0)
     base.update(kw)
     return eg.SgmParams(*base.values())
 
@@ -50,7 +50,8 @@ def _prm(**kw):
 @pytest.mark.parametrize("kw,code", [(dict(max_disp=0), -1), (dict(max_disp=257), -1),
                                      (dict(p1=-1), -1), (dict(p1=50, p2=40), -1),
                                      (dict(p2=194), -1), (dict(s_max=-1), -1),
-                                     (dict(n_paths=5), -1), (dict(n_paths=16), -1)])
+                                     (dict(n_paths=5), -1), (dict(n_paths=16), -1),
+                                     (dict(census_ready=2), -1), (dict(census_ready=-1), -1)])
 def test_sgm_rejects_bad_params(kw, code):
     lib = eg.lib()
     prm = _prm(**kw)
@@ -190,3 +191,22 @@ def test_predict_disparity_validation():
     assert call(args(q=0.0)) == -1
     assert call(args(et=float("nan"))) == -1
     assert call(args(do=f)) == -1          # output aliases an input
+
+
+def test_sgm_census_validation():
+    lib = eg.lib()
+    f = FAKE
+    n = lib.egosgm_sgm_workspace_bytes(64, 32, 64)
+    assert lib.sgm_census(None, f, 64, 32, 64, 64, f, n, None) == -1
+    assert lib.sgm_census(f, f, 64, 32, 63, 64, f, n, None) == -1          # pitch < w
+    assert lib.sgm_census(f, f, 64, 32, 64, 0, f, n, None) == -1           # max_disp
+    assert lib.sgm_census(f, f, 64, 32, 64, 64, f, n - 1, None) == -2      # workspace too small
+    assert lib.sgm_census(f, f, 64, 32, 64, 64, None, n, None) == -2
+
+
+def test_plans_reject_a_precomputed_census():
+    lib = eg.lib()
+    prm = _prm(census_ready=1)
+    P = (eg.PairDesc * 1)()
+    out = C.c_void_p()
+    assert lib.sgm_plan_create(P, 1, C.byref(prm), FAKE, 1 << 40, C.byref(out)) == -1

@@ -178,6 +178,32 @@ def test_selection_walk_every_pixel(s_max, rmax, D):
     assert np.abs(_np(g["disp_sub"]).astype(np.float64) - o["disp_sub"]).max() <= TOL
 
 
+def test_census_on_another_stream_then_reduced():
+    """sgm_census on a second stream, then sgm_reduced with census_ready=1
+    on the first (ordered by an event), equals sgm_reduced alone."""
+    _say("census ahead, 300x70 D=96")
+    w, h, D = 300, 70, 96
+    left, right = _random_pair(w, h, seed=77, max_shift=40)
+    d, p = _random_windows(w, h, D, seed=78)
+    lo, hi, off = eg.windows_from_prediction(_gpu(d), _gpu(p), D, r_min=1, r_max=6)
+    L, R = _gpu(left), _gpu(right)
+    ref = eg.sgm_reduced(L, R, lo, hi, off, eg.MatchParams(D))
+    ws = eg.Workspace(DEV)
+    side = torch.cuda.Stream(device=DEV)
+    ev = torch.cuda.Event()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        eg.sgm_census(L, R, D, workspace=ws)
+        ev.record(side)
+    torch.cuda.current_stream().wait_event(ev)
+    prm = eg.MatchParams(D)
+    prm.census_ready = 1
+    got = eg.sgm_reduced(L, R, lo, hi, off, prm, workspace=ws)
+    torch.cuda.synchronize()
+    for k in ("disp_wta", "disp_sub", "var_meas", "disp_right"):
+        assert torch.equal(got[k], ref[k]), k
+
+
 @pytest.mark.parametrize("D", [48, 128])
 def test_sgm_reduced_full_windows_equal_full(D):
     _say("reduced == full, 120x40", D)

@@ -118,7 +118,8 @@ def test_served_stream_is_the_same_alone_in_a_mix_and_in_the_pipeline(slots):
     mix = _serve([B, A, C], [(0, 0), (1, 0), (2, 0), (2, 1), (1, 1), (0, 1), (1, 2), (0, 2),
                              (2, 2), (2, 3), (0, 3), (1, 3)], slots)
     # the plain per-frame pipeline with its own matcher
-    st = pipeline.StreamState(128, 48, pipeline.camera_of(A[0]), cfg_a, DEV)
+    st = pipeline.StreamState(128, 48, pipeline.camera_of(A[0]),
+                              pipeline.FrameConfig(**{**cfg_a.__dict__, "overlap_census": True}), DEV)
     ref = []
     for k, (L, R) in enumerate(A[1]):
         Rm, t = A[2][k] if k > 0 else (None, None)
