@@ -638,12 +638,21 @@ __device__ inline typename CostWord<NP>::T pack_costs(const uint32_t (&L)[NP]) {
 // m + P2 (<= 255 + 193), so they never win a minimum: they act as +infinity
 // for the next step, and stay below 0x3fff + 193, so nothing overflows.
 template <int G, int NP>
+// shp / shn: the last lane shifts, carried from step to step.  At 64 lanes
+// the shifted-in value of lane 0 (63) is never written, so it keeps the +inf
+// the caller starts them with, and no per-step copy of +inf is needed.
 __device__ inline void packed_update(uint32_t (&L)[NP], const uint32_t (&c)[NP], int& m,
-                                     uint32_t p1pk, int p2) {
+                                     uint32_t p1pk, int p2, uint32_t& shp, uint32_t& shn) {
     const uint32_t mpk = (uint32_t)m * 0x10001u;
     const uint32_t m2pk = (uint32_t)(m + p2) * 0x10001u;
-    const uint32_t prv = from_prev_lane<G>(L[NP - 1]);
-    const uint32_t nxt = from_next_lane<G>(L[0]);
+    uint32_t prv, nxt;
+    if (G == 64) {
+        prv = shp = __builtin_amdgcn_update_dpp(shp, L[NP - 1], 0x138, 0xF, 0xF, false);   // wave_shr:1
+        nxt = shn = __builtin_amdgcn_update_dpp(shn, L[0], 0x130, 0xF, 0xF, false);        // wave_shl:1
+    } else {
+        prv = from_prev_lane<G>(L[NP - 1]);
+        nxt = from_next_lane<G>(L[0]);
+    }
     uint32_t Ln[NP];
 #pragma unroll
     for (int r = 0; r < NP; ++r) {
@@ -689,11 +698,12 @@ __device__ inline void packed_scanline_full(const SgmLaunch& a, const Scan& sc, 
 #pragma unroll
     for (int r = 0; r < NP; ++r) L[r] = 0u;
     int m = 0;
+    uint32_t shp = kInfPk, shn = kInfPk;   // lane-shift state (packed_update)
     int p = p0;
     auto step = [&](const Word& w) {
         uint32_t c[NP];
         unpack_costs<NP>(w, c);
-        packed_update<G, NP>(L, c, m, p1pk, p2);
+        packed_update<G, NP>(L, c, m, p1pk, p2, shp, shn);
         *reinterpret_cast<gmem<Word>*>(vol + at(p)) = pack_costs<NP>(L);
     };
     int i = 0;
@@ -888,6 +898,7 @@ __device__ inline void win_scanline(const SgmLaunch& a, const Scan& sc, int lane
 #pragma unroll
     for (int r = 0; r < NP; ++r) L[r] = 0u;   // zero predecessor: the first step gives L = C
     int m = 0;
+    uint32_t shp = kInfPk, shn = kInfPk;   // lane-shift state (packed_update)
     int p = p0;
     auto step = [&](int tc) {
         const uint32_t lo = s_lw[tc] & 0xffffu, w = s_lw[tc] >> 16;
@@ -904,7 +915,7 @@ __device__ inline void win_scanline(const SgmLaunch& a, const Scan& sc, int lane
         for (int r = 0; r < NP; ++r)
             c[r] = (in[2 * r] ? (uint32_t)cb[tc][2 * r] : (uint32_t)kInf) |
                    ((in[2 * r + 1] ? (uint32_t)cb[tc][2 * r + 1] : (uint32_t)kInf) << 16);
-        packed_update<64, NP>(L, c, m, p1pk, p2);
+        packed_update<64, NP>(L, c, m, p1pk, p2, shp, shn);
 #pragma unroll
         for (int t = 0; t < S; ++t) {
             const uint32_t v = (t & 1) ? (L[t >> 1] >> 16) : L[t >> 1];
