@@ -912,14 +912,16 @@ __device__ inline void win_scanline(const SgmLaunch& a, const Scan& sc, int lane
         }
         uint32_t c[NP];
 #pragma unroll
-        for (int r = 0; r < NP; ++r)
-            c[r] = (in[2 * r] ? (uint32_t)cb[tc][2 * r] : (uint32_t)kInf) |
-                   ((in[2 * r + 1] ? (uint32_t)cb[tc][2 * r + 1] : (uint32_t)kInf) << 16);
+        for (int r = 0; r < NP; ++r)   // two 16-bit halves packed by one byte permute
+            c[r] = __builtin_amdgcn_perm(in[2 * r + 1] ? (uint32_t)cb[tc][2 * r + 1] : (uint32_t)kInf,
+                                         in[2 * r] ? (uint32_t)cb[tc][2 * r] : (uint32_t)kInf, 0x05040100u);
         packed_update<64, NP>(L, c, m, p1pk, p2, shp, shn);
+        // the window offset goes into the scalar offset; the per-lane offset
+        // of a slot outside the window is pushed out of range
 #pragma unroll
         for (int t = 0; t < S; ++t) {
             const uint32_t v = (t & 1) ? (L[t >> 1] >> 16) : L[t >> 1];
-            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)v, vol, in[t] ? off + sl[t] : kDropOffset, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)v, vol, in[t] ? sl[t] : kDropOffset, off, 0);
         }
     };
 
