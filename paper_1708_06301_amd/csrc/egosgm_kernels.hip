@@ -1012,10 +1012,10 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_ragged_kernel(SgmLaunch a, i
 
 // ------------------------------------------------------------------ selection
 template <int NPATH>
-__device__ inline int sum_paths(const gmem<uint8_t>* __restrict__ vol, size_t stride, uint32_t j) {
+__device__ inline int sum_paths(const gmem<uint8_t>* const (&vols)[NPATH], uint32_t j) {
     int s = 0;
 #pragma unroll
-    for (int r = 0; r < NPATH; ++r) s += vol[(size_t)r * stride + j];
+    for (int r = 0; r < NPATH; ++r) s += vols[r][j];
     return s;
 }
 
@@ -1042,6 +1042,11 @@ __device__ inline void select_segment(const SgmLaunch& a, int seg, int y) {
     __syncthreads();
     const gmem<uint8_t>* __restrict__ vol = gptr(a.vol);
     const size_t stride = a.vol_stride;
+    // one base per direction (uniform), so each load is a scalar base plus
+    // the slot index, without a 64-bit address per load
+    const gmem<uint8_t>* vols[NPATH];
+#pragma unroll
+    for (int r = 0; r < NPATH; ++r) vols[r] = vol + (size_t)r * stride;
     // Pixels are taken NB at a time: their windows, then the path costs of
     // their first PK chunks, are all requested before any is used, so a group
     // waits for two memory latencies per NB pixels instead of per pixel.
@@ -1064,7 +1069,7 @@ __device__ inline void select_segment(const SgmLaunch& a, int seg, int y) {
             for (int k = 0; k < PK; ++k) {
                 const uint32_t j = o + (uint32_t)min(lane + G * k, max(wb - 1, 0));
 #pragma unroll
-                for (int r = 0; r < NPATH; ++r) c[b][k][r] = vol[(size_t)r * stride + j];
+                for (int r = 0; r < NPATH; ++r) c[b][k][r] = vols[r][j];
             }
         }
 #pragma unroll
@@ -1087,7 +1092,7 @@ __device__ inline void select_segment(const SgmLaunch& a, int seg, int y) {
 #pragma unroll
                         for (int r = 0; r < NPATH; ++r) S += c[b][k < PK ? k : 0][r];
                     } else {
-                        S = sum_paths<NPATH>(vol, stride, off + (uint32_t)s);
+                        S = sum_paths<NPATH>(vols, off + (uint32_t)s);
                     }
                     const int d = lo + s;
                     const int key = (S << 9) | d;
