@@ -256,18 +256,21 @@ __device__ inline int row_min16(int v) {
 }
 
 // Minimum over a lane group of G (16, 32 or 64) lanes; every lane of the
-// group must be active.  Rows are chained with row_bcast 15 (rows 1 and 3
-// take row 0's and row 2's minimum) and row_bcast 31 (rows 2 and 3 take row
-// 1's), then the group's last lane is read into a scalar register.
+// group must be active.  32 lanes: the two rows of a half are combined by a
+// row swap.  64 lanes: rows are chained with row_bcast 15 (rows 1 and 3 take
+// row 0's and row 2's minimum) and row_bcast 31 (rows 2 and 3 take row 1's),
+// then the last lane is read into a scalar register.
 template <int G>
 __device__ inline int group_min(int v) {
     v = row_min16(v);
     if (G == 16) return v;
-    v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x142, 0xA, 0xF, false));
     if (G == 32) {
-        const int a = __builtin_amdgcn_readlane(v, 31), b = __builtin_amdgcn_readlane(v, 63);
-        return (threadIdx.x & 32) ? b : a;
+        // v_permlane16_swap on (v, v) leaves rows (0,0,2,2) in one result and
+        // (1,1,3,3) in the other: their minimum is each 32-lane half's
+        const auto sw = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+        return min((int)sw[0], (int)sw[1]);
     }
+    v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x142, 0xA, 0xF, false));
     v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x143, 0xC, 0xF, false));
     return __builtin_amdgcn_readlane(v, 63);
 }
