@@ -1089,6 +1089,7 @@ __device__ inline void select_segment(const SgmLaunch& a, int seg, int y) {
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const int s = lane + G * k;
+                if (k > 0 && __builtin_amdgcn_ballot_w64(s < w) == 0) break;   // no group needs chunk k
                 if (s < w) {
                     int S = 0;
                     if (k < PK) {
