@@ -319,25 +319,41 @@ __device__ inline void cost_segment(const SgmLaunch& a, int seg, int y) {
     for (int i = threadIdx.x; i < kSeg; i += kBlock) cls[i] = (x0 + i < W) ? rowl[x0 + i] : 0ull;
     __syncthreads();
     const int grp = threadIdx.x / G, lane = threadIdx.x % G;
-    for (int i = grp; i < kSeg; i += GPB) {
-        const int x = x0 + i;
-        if (x >= W) break;
-        int lo, wd;
-        uint32_t off;
-        if (WM == kWinFull) {
-            lo = 0;
-            wd = D;
-            off = (uint32_t)(y * W + x) * (uint32_t)D;
-        } else {
-            lo = s_lo[i];
-            wd = s_w[i];
-            off = s_off[i];
+    if constexpr (WM == kWinFull) {
+        for (int i = grp; i < kSeg; i += GPB) {
+            const int x = x0 + i;
+            if (x >= W) break;
+            const uint32_t off = (uint32_t)(y * W + x) * (uint32_t)D;
+            const uint64_t cl = cls[i];
+            for (int sl = lane; sl < D; sl += G) {
+                const int c = (x - sl >= 0) ? __popcll(cl ^ crs[i + (D - 1) - sl]) : kCensusBits;
+                cost[off + (uint32_t)sl] = (uint8_t)c;
+            }
         }
-        const uint64_t cl = cls[i];
-        for (int sl = lane; sl < wd; sl += G) {
-            const int d = lo + sl;
-            const int c = (x - d >= 0) ? __popcll(cl ^ crs[i + (D - 1) - d]) : kCensusBits;
-            cost[off + (uint32_t)sl] = (uint8_t)c;
+    } else {
+        // the group's pixels' windows and left codes are read from LDS
+        // together (one wait), then each pixel's slots are written
+        constexpr int NPX = kSeg / GPB;
+        int lo[NPX], wd[NPX];
+        uint32_t off[NPX];
+        uint64_t cl[NPX];
+#pragma unroll
+        for (int j = 0; j < NPX; ++j) {
+            const int i = grp + j * GPB;
+            lo[j] = s_lo[i];
+            wd[j] = x0 + i < W ? s_w[i] : 0;   // past the row: no slots
+            off[j] = s_off[i];
+            cl[j] = cls[i];
+        }
+#pragma unroll
+        for (int j = 0; j < NPX; ++j) {
+            const int i = grp + j * GPB;
+            const int x = x0 + i;
+            for (int sl = lane; sl < wd[j]; sl += G) {
+                const int d = lo[j] + sl;
+                const int c = (x - d >= 0) ? __popcll(cl[j] ^ crs[i + (D - 1) - d]) : kCensusBits;
+                cost[off[j] + (uint32_t)sl] = (uint8_t)c;
+            }
         }
     }
 }
