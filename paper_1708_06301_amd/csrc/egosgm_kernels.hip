@@ -64,11 +64,23 @@ __device__ __attribute__((always_inline)) inline void census_tile(const uint8_t*
     uint8_t* tb = reinterpret_cast<uint8_t*>(&tile[0][0]);
     const gmem<const uint8_t>* __restrict__ gimg = gptr(img);
     const int x0 = tx * kCtW, y0 = ty * kCtH;
-    for (int i = threadIdx.x; i < TW * TH; i += kBlock) {
+    // every load of the staging is issued before the first LDS write, so the
+    // block waits on one memory latency, not one per pass (the index of the
+    // last, partial pass is clamped and its surplus loads are not stored)
+    constexpr int NF = (TW * TH + kBlock - 1) / kBlock;
+    uint32_t v[NF];
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+        const int i = min((int)threadIdx.x + j * kBlock, TW * TH - 1);
         const int r = i / TW, c = i - r * TW;
         const int gx = min(max(x0 + c - kHaloX, 0), w - 1);
         const int gy = min(max(y0 + r - kHaloY, 0), h - 1);
-        tb[i] = gimg[(size_t)gy * pitch + gx];
+        v[j] = gimg[(size_t)gy * pitch + gx];
+    }
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+        const int i = (int)threadIdx.x + j * kBlock;
+        if (i < TW * TH) tb[i] = (uint8_t)v[j];
     }
     __syncthreads();
     const int lx = threadIdx.x % 64, ly = threadIdx.x / 64;
@@ -205,8 +217,18 @@ __global__ __launch_bounds__(kBlock) void windows_base_kernel(int w, int h, uint
     __shared__ uint32_t ws[kBlock / 64];
     const int y = blockIdx.y, c = blockIdx.x, nc = gridDim.x;
     const int q = y * nc + c;   // this chunk's raster index
+    // the totals are read eight passes at a time, all loads issued before
+    // the first add (indexes clamped, the surplus dropped), so a block waits
+    // on one memory latency per 8 * kBlock chunks
+    constexpr int U = 8;
     uint32_t part = 0;
-    for (int i = threadIdx.x; i < q; i += kBlock) part += gptr(chunk_tot)[i];
+    for (int i0 = 0; i0 < q; i0 += U * kBlock) {
+        uint32_t v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) v[j] = gptr(chunk_tot)[min(i0 + j * kBlock + (int)threadIdx.x, q - 1)];
+#pragma unroll
+        for (int j = 0; j < U; ++j) part += i0 + j * kBlock + (int)threadIdx.x < q ? v[j] : 0u;
+    }
     uint32_t excl;
     const uint32_t base = block_exclusive_scan(part, excl, ws);
     const int x = c * kBlock + (int)threadIdx.x;

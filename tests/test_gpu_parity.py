@@ -240,10 +240,12 @@ def test_windows_edge_values():
     assert np.array_equal(_np(off).view(np.uint32), wo[2])
 
 
-@pytest.mark.parametrize("w,h", [(256, 3), (257, 2), (513, 5), (700, 4), (1, 9)])
+@pytest.mark.parametrize("w,h", [(256, 3), (257, 2), (513, 5), (700, 4), (1, 9), (300, 1100),
+                                 (4000, 600)])
 def test_windows_across_row_chunks(w, h):
     """Offsets are built per 256-pixel chunk of a row and then shifted by
-    the earlier chunks' totals: widths on and around chunk boundaries."""
+    the earlier chunks' totals: widths on and around chunk boundaries, and
+    more chunks than one pass of the totals' sum covers (2048)."""
     _say("windows chunks", w, h)
     D = 96
     r = np.random.default_rng(w * 7 + h)
