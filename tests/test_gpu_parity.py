@@ -365,10 +365,11 @@ def test_predict_disparity_equals_warp_then_refine(seed):
         assert np.array_equal(_np(fd), _np(rd)) and np.array_equal(_np(fp), _np(rp)), (edge_tol, fill_tol)
 
 
-def test_kalman():
-    _say("kalman")
+@pytest.mark.parametrize("n", [100003, 1, 255, 1025, 4 * 256 + 3])
+def test_kalman(n):
+    """Sizes around one block's kEw * 256 pixels and a ragged tail."""
+    _say("kalman", n)
     r = np.random.default_rng(4)
-    n = 100003
     dp = r.uniform(0, 255, n).astype(np.float32)
     pp = r.uniform(0.001, 100, n).astype(np.float32)
     z = (dp + r.normal(0, 3, n)).astype(np.float32)
