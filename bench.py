@@ -51,6 +51,23 @@ def measured_traffic(kernel_name):
     return None if k is None else k["fetch_bytes"] + k["write_bytes"]
 
 
+def measured_valu_active(kernel_name):
+    """SQ_ACTIVE_INST_VALU per dispatch of kernel_name (quad-cycles in which a
+    SIMD's vector ALU issues, summed over all SIMDs) from the committed
+    rocprofv3 counter summary, or None when the kernel source has changed
+    since those counters were taken."""
+    import hashlib
+    try:
+        prof = json.load(open(os.path.join(ROOT, "profiles", "sq_counters_street_1242x375_D128.json")))
+        src = open(os.path.join(ROOT, "paper_1708_06301_amd", "csrc", "egosgm_kernels.hip"), "rb").read()
+    except (OSError, ValueError):
+        return None
+    if hashlib.sha256(src).hexdigest() != prof.get("kernel_source_sha256"):
+        return None
+    k = prof.get("kernels", {}).get(kernel_name)
+    return None if k is None else k.get("SQ_ACTIVE_INST_VALU")
+
+
 def build_sequence(n_frames, w, h, device):
     import torch
     from paper_1708_06301_amd import pipeline, synth
@@ -548,6 +565,11 @@ def main():
                     traffic=measured_traffic(kname) if (w, h, cfg.max_disp) == (1242, 375, 128) else None,
                     avg_launch_ms=round(avg_ms, 4), launches=dom_n,
                     alg_bytes_per_launch=int(alg_bytes))
+        # what does bound the kernel: the fraction of SIMD cycles in which the
+        # vector ALU issues, from the counter summary and this run's launch
+        # time (256 CUs at the 2.4 GHz peak clock)
+        act = measured_valu_active(kname) if (w, h, cfg.max_disp) == (1242, 375, 128) else None
+        roof["valu_busy"] = None if act is None else round(act / (256 * avg_ms * 1e-3 * 2.4e9), 3)
 
     out = {
         "metric": METRIC,
