@@ -486,9 +486,15 @@ constexpr int lds_row(int G, int K) { return 2 * G * K + 2; }
 // only for pixels where some lane group of the wave has a window wider than
 // G (a wave-uniform test on the prefetched window words), into a ring of
 // their own.  Narrow windows then cost one load per step instead of K.
-template <int G, int K, int WM, int PF, bool ODW = false>
+// Q32 (ragged windows, w*h < 2^27, so every byte offset below, including
+// the overshoot past either end of a scanline, fits an int): the window word RM steps ahead is read
+// through a buffer at a running byte offset clamped into the scanline (past
+// its end the last pixel's word again), so the prefetch address costs an
+// add, a max and a min, without 64-bit address arithmetic.
+template <int G, int K, int WM, int PF, bool ODW = false, bool Q32 = false>
 __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane,
                                     uint16_t* b0, uint16_t* b1) {
+    static_assert(!Q32 || WM == kWinRagged, "byte-offset window words need ragged windows");
     constexpr int RM = 2 * PF;
     constexpr int KP = ODW ? 1 : K;   // prefetched chunks
     constexpr int ROW = lds_row(G, K);
@@ -505,6 +511,13 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
     auto load_meta = [&](int j, int pix) { mm[j] = scan_meta<WM>(a, pix); };
 #pragma unroll
     for (int j = 0; j < RM; ++j) load_meta(j, j < len ? p0 + j * dp : p_last);
+    const __amdgpu_buffer_rsrc_t mbuf = byte_buffer(a.meta, Q32 ? (uint32_t)a.w * (uint32_t)a.h * 8u : 0u);
+    const int q_lo = 8 * min(p0, p_last), q_hi = 8 * max(p0, p_last), dq = 8 * dp;
+    int q_next = 8 * (p0 + RM * dp);
+    auto next_meta = [&](int j) {
+        mm[j] = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(mbuf, min(max(q_next, q_lo), q_hi), 0, 0));
+        q_next += dq;
+    };
     int cst[PF][KP];
     int wst[PF][K > KP ? K - KP : 1];   // chunks KP.. of wide pixels (ODW)
     auto load_costs = [&](int slot, uint64_t m) {
@@ -563,7 +576,7 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
                 const int Lm = in ? L : kInf;
                 cur[lo_c + s + 1] = (uint16_t)Lm;
                 if (in) vol[off_c + (uint32_t)s] = (uint8_t)L;
-                mn = min(mn, Lm);
+                mn = k == 0 ? Lm : min(mn, Lm);   // in-window L < kInf, so chunk 0 needs no min
             }
         }
         lds_order();
@@ -581,8 +594,12 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
         for (int u = 0; u < RM; ++u) {
             step(u, u % PF, u & 1);
             load_costs(u % PF, mm[(u + PF) % RM]);
-            load_meta(u, (i + u + RM < len) ? p + RM * dp : p_last);
-            p += dp;
+            if constexpr (Q32) {
+                next_meta(u);
+            } else {
+                load_meta(u, (i + u + RM < len) ? p + RM * dp : p_last);
+                p += dp;
+            }
         }
     }
 #pragma unroll
@@ -1046,8 +1063,12 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_ragged_kernel(SgmLaunch a, i
         const int task = n_win_tasks + (blockIdx.x - n_win_blocks) * GPB + grp;
         if (task >= n_tasks) return;
         // wide chunks on demand at 32 lanes (measured faster there; slower at 16 and 64)
-        lds_scanline<GL, K, kWinRagged, PF, GL == 32>(a, scan_of(task, a.w, a.h), lane, lds[grp][0],
-                                                      lds[grp][1]);
+        if ((uint64_t)a.w * (uint64_t)a.h < (1ull << 27))
+            lds_scanline<GL, K, kWinRagged, PF, GL == 32, true>(a, scan_of(task, a.w, a.h), lane, lds[grp][0],
+                                                                lds[grp][1]);
+        else
+            lds_scanline<GL, K, kWinRagged, PF, GL == 32>(a, scan_of(task, a.w, a.h), lane, lds[grp][0],
+                                                          lds[grp][1]);
     }
 }
 
