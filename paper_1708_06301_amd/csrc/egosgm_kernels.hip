@@ -520,9 +520,12 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
     };
     int cst[PF][KP];
     int wst[PF][K > KP ? K - KP : 1];   // chunks KP.. of wide pixels (ODW)
+    bool wide_pf[PF];                    // ODW: the wave-uniform wide test, kept for the step
     auto load_costs = [&](int slot, uint64_t m) {
         load_costs_buf<G, KP>(cbuf, meta_off(m), meta_w(m), lane, cst[slot]);
-        if (K > KP && __builtin_amdgcn_ballot_w64(meta_w(m) > G) != 0) {
+        const bool wd = K > KP && __builtin_amdgcn_ballot_w64(meta_w(m) > G) != 0;
+        wide_pf[slot] = wd;
+        if (wd) {
 #pragma unroll
             for (int k = KP; k < K; ++k)
                 wst[slot][k - KP] = __builtin_amdgcn_raw_buffer_load_b8(
@@ -539,7 +542,10 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
     lds_order();
     for (int e = lane; e < meta_w(mm[0]); e += G) b1[meta_lo(mm[0]) + 1 + e] = 0;   // zero predecessor
     lds_order();
-    int lo_q = meta_lo(mm[0]), m_q = 0;
+    int m_q = 0;
+    // the previous step's row at its window start (chunk 0 of this lane):
+    // the address it was written at is the one erased one step later
+    uint16_t* erase = b1 + meta_lo(mm[0]) + lane + 1;
     // Chunks k (slots lane + G*k) written by the previous step: wave-uniform
     // bits, since a chunk runs when any lane group of the wave needs it.
     uint32_t done_q = 0;
@@ -562,7 +568,9 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
         const int m2 = m_q + p2;
         int mn = kInf;
         uint32_t done_c = 0;
-        const bool wide = K > 1 && __builtin_amdgcn_ballot_w64(w_c > G) != 0;   // wave-uniform
+        // wave-uniform; with ODW the same test on the same window word was
+        // taken when this step's costs were requested
+        const bool wide = K > 1 && (K > KP ? wide_pf[tc] : __builtin_amdgcn_ballot_w64(w_c > G) != 0);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int s = lane + G * k;
@@ -582,10 +590,10 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
         lds_order();
 #pragma unroll
         for (int k = 0; k < K; ++k)
-            if (done_q & (1u << k)) prv[lo_q + lane + G * k + 1] = kInf;
+            if (done_q & (1u << k)) erase[G * k] = kInf;
         done_q = done_c;
         m_q = group_min<G>(mn);
-        lo_q = lo_c;
+        erase = cur + lo_c + lane + 1;
     };
 
     int i = 0;
