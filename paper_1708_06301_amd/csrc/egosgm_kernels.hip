@@ -434,15 +434,17 @@ __device__ inline void dir_step(int dir, int& dx, int& dy) {
     dy = (dir == 2 || dir == 4 || dir == 5) ? 1 : ((dir == 3 || dir == 6 || dir == 7) ? -1 : 0);
 }
 
-// Costs of this lane's slots s = lane + G*k of one pixel's window (clamped
-// into the window), through a raw buffer.  The window offset differs
-// between the lane groups of a wave, so it goes into the per-lane offset.
+// Costs of this lane's slots s = lane + G*k of one pixel's window, through a
+// raw buffer.  The window offset differs between the lane groups of a wave,
+// so it goes into the per-lane offset.  Lanes past the window read other
+// pixels' bytes (or zero past the buffer's end, where the hardware drops the
+// read); the LDS scanline step replaces every such slot by +infinity, so the
+// offset needs no clamp.
 template <int G, int K>
-__device__ inline void load_costs_buf(__amdgpu_buffer_rsrc_t cbuf, uint32_t off, int w, int lane,
-                                      int (&c)[K]) {
+__device__ inline void load_costs_buf(__amdgpu_buffer_rsrc_t cbuf, uint32_t off, int lane, int (&c)[K]) {
 #pragma unroll
     for (int k = 0; k < K; ++k)
-        c[k] = __builtin_amdgcn_raw_buffer_load_b8(cbuf, off + (uint32_t)min(lane + G * k, w - 1), 0, 0);
+        c[k] = __builtin_amdgcn_raw_buffer_load_b8(cbuf, off + (uint32_t)(lane + G * k), 0, 0);
 }
 
 // A scanline task: direction, first pixel, pixel step and length.
@@ -522,14 +524,14 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
     int wst[PF][K > KP ? K - KP : 1];   // chunks KP.. of wide pixels (ODW)
     bool wide_pf[PF];                    // ODW: the wave-uniform wide test, kept for the step
     auto load_costs = [&](int slot, uint64_t m) {
-        load_costs_buf<G, KP>(cbuf, meta_off(m), meta_w(m), lane, cst[slot]);
+        load_costs_buf<G, KP>(cbuf, meta_off(m), lane, cst[slot]);
         const bool wd = K > KP && __builtin_amdgcn_ballot_w64(meta_w(m) > G) != 0;
         wide_pf[slot] = wd;
         if (wd) {
 #pragma unroll
             for (int k = KP; k < K; ++k)
                 wst[slot][k - KP] = __builtin_amdgcn_raw_buffer_load_b8(
-                    cbuf, meta_off(m) + (uint32_t)min(lane + G * k, meta_w(m) - 1), 0, 0);
+                    cbuf, meta_off(m) + (uint32_t)(lane + G * k), 0, 0);
         }
     };
 #pragma unroll
