@@ -489,10 +489,13 @@ constexpr int lds_row(int G, int K) { return 2 * G * K + 2; }
 // G (a wave-uniform test on the prefetched window words), into a ring of
 // their own.  Narrow windows then cost one load per step instead of K.
 // Q32 (ragged windows, w*h < 2^27, so every byte offset below, including
-// the overshoot past either end of a scanline, fits an int): the window word RM steps ahead is read
+// the overshoot past either end of a scanline, fits an int; and the eight
+// path volumes within 2^32 bytes): the window word RM steps ahead is read
 // through a buffer at a running byte offset clamped into the scanline (past
 // its end the last pixel's word again), so the prefetch address costs an
-// add, a max and a min, without 64-bit address arithmetic.
+// add, a max and a min, without 64-bit address arithmetic; and path costs are
+// stored at a 32-bit offset from the common base of the eight volumes, the
+// same for every lane group of the wave, so a store needs no 64-bit address.
 template <int G, int K, int WM, int PF, bool ODW = false, bool Q32 = false>
 __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane,
                                     uint16_t* b0, uint16_t* b1) {
@@ -516,6 +519,8 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
     const __amdgpu_buffer_rsrc_t mbuf = byte_buffer(a.meta, Q32 ? (uint32_t)a.w * (uint32_t)a.h * 8u : 0u);
     const int q_lo = 8 * min(p0, p_last), q_hi = 8 * max(p0, p_last), dq = 8 * dp;
     int q_next = 8 * (p0 + RM * dp);
+    gmem<uint8_t>* __restrict__ vol_all = gptr(a.vol);
+    const uint32_t vrow = (uint32_t)sc.dir * (uint32_t)a.vol_stride + (uint32_t)lane;
     auto next_meta = [&](int j) {
         mm[j] = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(mbuf, min(max(q_next, q_lo), q_hi), 0, 0));
         q_next += dq;
@@ -585,7 +590,12 @@ __device__ inline void lds_scanline(const SgmLaunch& a, const Scan& sc, int lane
                 const bool in = s < w_c;
                 const int Lm = in ? L : kInf;
                 cur[lo_c + s + 1] = (uint16_t)Lm;
-                if (in) vol[off_c + (uint32_t)s] = (uint8_t)L;
+                if (in) {
+                    if constexpr (Q32)
+                        vol_all[vrow + off_c + (uint32_t)(G * k)] = (uint8_t)L;
+                    else
+                        vol[off_c + (uint32_t)s] = (uint8_t)L;
+                }
                 mn = k == 0 ? Lm : min(mn, Lm);   // in-window L < kInf, so chunk 0 needs no min
             }
         }
@@ -1073,7 +1083,7 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_ragged_kernel(SgmLaunch a, i
         const int task = n_win_tasks + (blockIdx.x - n_win_blocks) * GPB + grp;
         if (task >= n_tasks) return;
         // wide chunks on demand at 32 lanes (measured faster there; slower at 16 and 64)
-        if ((uint64_t)a.w * (uint64_t)a.h < (1ull << 27))
+        if ((uint64_t)a.w * (uint64_t)a.h < (1ull << 27) && (uint64_t)kNumPaths * a.vol_stride < (1ull << 32))
             lds_scanline<GL, K, kWinRagged, PF, GL == 32, true>(a, scan_of(task, a.w, a.h), lane, lds[grp][0],
                                                                 lds[grp][1]);
         else
