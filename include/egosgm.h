@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define EGOSGM_ABI_VERSION 2
+#define EGOSGM_ABI_VERSION 3
 
 /* Largest disparity range and the census window (9 wide, 7 tall: 62 bits). */
 #define EGOSGM_MAX_DISP 256
@@ -363,7 +363,7 @@ int sgm_plan_destroy(egosgm_plan* plan);
 /* ------------------------------------------------------------------ tuning
  * Launch shapes and schedules of the path kernels, process-wide (the second
  * piece of state the library keeps; set it before enqueueing work, e.g. from
- * an autotuner).  Results never depend on it.  Defaults: {64, 32, 1, 16}. */
+ * an autotuner).  Results never depend on it.  Defaults: {64, 32, 1, 16, 0}. */
 typedef struct egosgm_tuning {
     int32_t full_group;      /* lanes per scanline, full-range kernel: 16, 32, 64             */
     int32_t ragged_group;    /* lanes per scanline, ragged windows through LDS: 16, 32, 64    */
@@ -376,6 +376,10 @@ typedef struct egosgm_tuning {
                                    per scanline (window-start moves by lane permutes)        */
     int32_t batch_group;     /* lanes per scanline in batched plans (fixed when a plan is
                                 created): 16, 32, 64                                           */
+    int32_t wide_offsets;    /* LDS scanlines of ragged windows: 0 addresses window words and
+                                path costs by 32-bit offsets wherever the image allows it
+                                (w*h < 2^27 and the eight path volumes within 4 GiB); 1 uses
+                                64-bit addresses everywhere, the form larger images take        */
 } egosgm_tuning;
 
 int egosgm_set_tuning(const egosgm_tuning* tuning);

@@ -60,7 +60,7 @@ hipError_t timed(int stage, hipStream_t s, F&& fn) {
 }
 
 // Launch-shape choices (set by egosgm_set_tuning; read at every launch).
-egosgm_tuning g_tuning = {64, 32, 1, 16};
+egosgm_tuning g_tuning = {64, 32, 1, 16, 0};
 std::mutex g_tuning_mu;
 
 constexpr size_t kAlign = 256;
@@ -139,6 +139,7 @@ int run_sgm(const uint8_t* left, const uint8_t* right, int w, int h, int pitch, 
         a.full_group = g_tuning.full_group;
         a.ragged_group = g_tuning.ragged_group;
         a.ragged_schedule = g_tuning.ragged_schedule;
+        a.wide_offsets = g_tuning.wide_offsets;
     }
     a.cost = base + L.cost;
     a.key_r = reinterpret_cast<uint32_t*>(base + L.key_r);
@@ -699,7 +700,7 @@ int egosgm_set_tuning(const egosgm_tuning* t) {
     if (!t) return EGOSGM_EINVAL;
     auto ok = [](int g) { return g == 16 || g == 32 || g == 64; };
     if (!ok(t->full_group) || !ok(t->ragged_group) || !ok(t->batch_group) || t->ragged_schedule < 0 ||
-        t->ragged_schedule > 3)
+        t->ragged_schedule > 3 || (t->wide_offsets != 0 && t->wide_offsets != 1))
         return EGOSGM_EINVAL;
     std::lock_guard<std::mutex> g(g_tuning_mu);
     g_tuning = *t;

@@ -44,6 +44,7 @@ struct SgmLaunch {
     int full_group;          // lanes per scanline, full-range path kernel (16, 32, 64)
     int ragged_group;        // lanes per scanline, ragged path kernel (16, 32, 64)
     int ragged_schedule;     // 0: all scanlines via LDS, 1: rows on packed registers, 2: all packed
+    int wide_offsets;        // 1: LDS scanlines keep 64-bit addresses even where 32-bit offsets fit
     uint8_t* cost;           // matching cost per search slot
     uint32_t* key_r;         // w*h right-map keys (S << 9 | d), cleared by the census pass
     uint64_t* meta;          // w*h packed windows (offset | lo << 32 | width << 48), written by

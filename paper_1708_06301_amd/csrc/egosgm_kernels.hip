@@ -1083,7 +1083,8 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_ragged_kernel(SgmLaunch a, i
         const int task = n_win_tasks + (blockIdx.x - n_win_blocks) * GPB + grp;
         if (task >= n_tasks) return;
         // wide chunks on demand at 32 lanes (measured faster there; slower at 16 and 64)
-        if ((uint64_t)a.w * (uint64_t)a.h < (1ull << 27) && (uint64_t)kNumPaths * a.vol_stride < (1ull << 32))
+        if (!a.wide_offsets && (uint64_t)a.w * (uint64_t)a.h < (1ull << 27) &&
+            (uint64_t)kNumPaths * a.vol_stride < (1ull << 32))
             lds_scanline<GL, K, kWinRagged, PF, GL == 32, true>(a, scan_of(task, a.w, a.h), lane, lds[grp][0],
                                                                 lds[grp][1]);
         else

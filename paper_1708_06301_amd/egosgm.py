@@ -59,6 +59,9 @@ STAGES = ("census", "windows", "cost", "paths", "select", "warp", "kalman", "ref
           "batch_census", "batch_cost", "batch_paths", "batch_select")
 
 
+ABI_VERSION = 3   # EGOSGM_ABI_VERSION of include/egosgm.h
+
+
 def lib():
     """Loads libegosgm.so (raises if it has not been built)."""
     global _lib
@@ -71,6 +74,9 @@ def lib():
             fn = getattr(h, name)
             fn.argtypes = args
             fn.restype = res
+        if h.egosgm_abi_version() != ABI_VERSION:   # the structs below follow this version
+            raise RuntimeError(f"{LIB_PATH} has ABI version {h.egosgm_abi_version()}, "
+                               f"this binding expects {ABI_VERSION}: rebuild it")
         _lib = h
     return _lib
 
@@ -98,18 +104,19 @@ class SgmDebug(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("full_group", C.c_int32), ("ragged_group", C.c_int32),
-                ("ragged_schedule", C.c_int32), ("batch_group", C.c_int32)]
+                ("ragged_schedule", C.c_int32), ("batch_group", C.c_int32),
+                ("wide_offsets", C.c_int32)]
 
 
-DEFAULT_TUNING = dict(full_group=64, ragged_group=32, ragged_schedule=1, batch_group=16)
+DEFAULT_TUNING = dict(full_group=64, ragged_group=32, ragged_schedule=1, batch_group=16, wide_offsets=0)
 
 
 def set_tuning(full_group: int = 64, ragged_group: int = 64, ragged_schedule: int = 0,
-               batch_group: int | None = None):
+               batch_group: int | None = None, wide_offsets: int = 0):
     """Sets the launch shapes; batch_group None keeps the current one."""
     if batch_group is None:
         batch_group = get_tuning()["batch_group"] if _lib is not None else 16
-    t = Tuning(full_group, ragged_group, ragged_schedule, batch_group)
+    t = Tuning(full_group, ragged_group, ragged_schedule, batch_group, wide_offsets)
     _check(lib().egosgm_set_tuning(C.byref(t)), "egosgm_set_tuning")
 
 
@@ -117,7 +124,8 @@ def get_tuning() -> dict:
     t = Tuning()
     _check(lib().egosgm_get_tuning(C.byref(t)), "egosgm_get_tuning")
     return dict(full_group=t.full_group, ragged_group=t.ragged_group,
-                ragged_schedule=t.ragged_schedule, batch_group=t.batch_group)
+                ragged_schedule=t.ragged_schedule, batch_group=t.batch_group,
+                wide_offsets=t.wide_offsets)
 
 
 @dataclass

@@ -26,7 +26,7 @@ def test_every_declared_symbol_is_exported():
     lib = eg.lib()
     for n in names:
         assert hasattr(lib, n), n
-    assert eg.abi_version() == 2
+    assert eg.abi_version() == 3
 
 
 def test_workspace_sizes():
@@ -121,8 +121,11 @@ def test_tuning_validation():
     assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, 4, 16))) == -1
     assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, 3, 16))) == 0
     assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, 0, 8))) == -1
+    assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, 1, 16, 2))) == -1
+    assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, 1, 16, 1))) == 0
     eg.set_tuning(16, 64, 0, 32)
-    assert eg.get_tuning() == dict(full_group=16, ragged_group=64, ragged_schedule=0, batch_group=32)
+    assert eg.get_tuning() == dict(full_group=16, ragged_group=64, ragged_schedule=0, batch_group=32,
+                                   wide_offsets=0)
     eg.set_tuning(**before)
 
 

@@ -400,14 +400,15 @@ def test_tuning_never_changes_results(D):
                    _gpu(wo[2].view(np.int32)))
     prm = eg.MatchParams(max_disp=D)
     try:
-        for fg, rg, pr in itertools.product((16, 32, 64), (16, 32, 64), (0, 1, 2, 3)):
-            eg.set_tuning(fg, rg, pr)
+        # wide_offsets = 1 runs the 64-bit addressing that images of 2^27 pixels take
+        for fg, rg, pr, wo_ in itertools.product((16, 32, 64), (16, 32, 64), (0, 1, 2, 3), (0, 1)):
+            eg.set_tuning(fg, rg, pr, wide_offsets=wo_)
             a = eg.sgm_full(L, R, prm)
             b = eg.sgm_reduced(L, R, lo, hi, off, prm)
-            assert np.array_equal(_np(a["disp_wta"]), o_full["disp_wta"]), (fg, rg, pr)
+            assert np.array_equal(_np(a["disp_wta"]), o_full["disp_wta"]), (fg, rg, pr, wo_)
             assert np.array_equal(_np(a["var_meas"]).astype(np.float64), o_full["var_meas"])
-            assert np.array_equal(_np(b["disp_wta"]), o_red["disp_wta"]), (fg, rg, pr)
-            assert np.array_equal(_np(b["disp_right"]), o_red["disp_right"]), (fg, rg, pr)
+            assert np.array_equal(_np(b["disp_wta"]), o_red["disp_wta"]), (fg, rg, pr, wo_)
+            assert np.array_equal(_np(b["disp_right"]), o_red["disp_right"]), (fg, rg, pr, wo_)
     finally:
         eg.set_tuning(**eg.DEFAULT_TUNING)
 
