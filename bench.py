@@ -1,25 +1,31 @@
 """Benchmark: ego-motion reduced census + SGM on one MI355X.
 
-One step = one pass of the whole path over a 20-frame synthetic street
-sequence at 1242x375 (ground plane + 12 boxes + backdrop, f = 718 px,
-b = 0.54 m, 1 m/frame forward with yaw ~ N(0, 0.5 deg)): frame 0 is matched
-over the full range (D = 128); frames 1..19 warp the previous map by the
-ego-motion, derive windows of radius 4 around the prediction, match only
-inside them and update the map with the Kalman filter.  Census 9x7, 8 paths,
-P1 = 10, P2 = 120.  All stereo pairs are resident in HBM before timing.
+Headline workload: a 30-frame synthetic street sequence at 2048x1024 (ground
+plane + 12 boxes + backdrop, f = 718*2048/1242 px, b = 0.54 m, 1 m/frame
+forward with yaw ~ N(0, 0.5 deg)).  One step = one pass of the whole path
+over the sequence: frame 0 is matched over the full range (D = 256); frames
+1..29 warp the previous map by the ego-motion, refine the prediction, derive
+windows of radius 6 around it, match only inside them and update the map
+with the Kalman filter.  Census 9x7, 8 paths, P1 = 10, P2 = 120.  All stereo
+pairs are resident in HBM before timing.
 
-value = pixel*disparity*path updates per second (GCUPS) over the timed steps.
-Also reported: frames/s, per-frame latency p50/p99, the same sequence with
-plain full-range SGM on every frame, the roofline of the dominant kernel
-(HIP events around each stage on the library's stream, over the timed
-region) and the CPU oracle timed on a bounded sample of the same workload.
+value = pixel*disparity*path updates per second (GCUPS) over the timed
+steps.  Also reported: frames/s, per-frame latency p50/p99, the same
+sequence with plain full-range SGM on every frame, the roofline of the
+dominant kernel (HIP events around each stage on the library's stream,
+over the timed region) and the CPU oracle timed on a bounded sample of the
+same workload.  Further sections: the 20-frame 1242x375 sequence (D = 128,
+r = 4) with its quality and variants, a batch of 32 mixed pairs in one
+graph launch, and 16 served camera streams.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import subprocess
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -30,48 +36,68 @@ sys.path.insert(0, ROOT)
 METRIC = "SGM GCUPS (pixel·disp·path/s) + frames/s, reduced vs full range; p99 latency"
 HBM_PEAK_GBS = 8000.0
 
+# The two sequence workloads: (name, w, h, frames, D, r, seed config index)
+HIGHRES = ("highres", 2048, 1024, 30, 256, 6, 3)
+STREET = ("street", 1242, 375, 20, 128, 4, 1)
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(kernel_name):
-    """HBM bytes per dispatch of kernel_name from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel source has
-    changed since those counters were taken."""
+def profile_name(kind, w, h, D):
+    tag = "highres" if (w, h) == (2048, 1024) else "street"
+    return os.path.join(ROOT, "profiles", f"{kind}_{tag}_{w}x{h}_D{D}.json")
+
+
+def _profile_entry(kind, w, h, D, kernel_name):
+    """Per-dispatch counters of kernel_name from a committed rocprofv3
+    summary, or None when there is none for this workload or the kernel
+    source has changed since the counters were taken."""
     import hashlib
     try:
-        prof = json.load(open(os.path.join(ROOT, "profiles", "hbm_traffic_street_1242x375_D128.json")))
+        prof = json.load(open(profile_name(kind, w, h, D)))
         src = open(os.path.join(ROOT, "paper_1708_06301_amd", "csrc", "egosgm_kernels.hip"), "rb").read()
     except (OSError, ValueError):
         return None
     if hashlib.sha256(src).hexdigest() != prof.get("kernel_source_sha256"):
         return None
-    k = prof.get("kernels", {}).get(kernel_name)
+    return prof.get("kernels", {}).get(kernel_name)
+
+
+def measured_traffic(w, h, D, kernel_name):
+    """HBM bytes per dispatch (FETCH_SIZE + WRITE_SIZE, calibrated)."""
+    k = _profile_entry("hbm_traffic", w, h, D, kernel_name)
     return None if k is None else k["fetch_bytes"] + k["write_bytes"]
 
 
-def measured_valu_active(kernel_name):
-    """SQ_ACTIVE_INST_VALU per dispatch of kernel_name (quad-cycles in which a
-    SIMD's vector ALU issues, summed over all SIMDs) from the committed
-    rocprofv3 counter summary, or None when the kernel source has changed
-    since those counters were taken."""
-    import hashlib
-    try:
-        prof = json.load(open(os.path.join(ROOT, "profiles", "sq_counters_street_1242x375_D128.json")))
-        src = open(os.path.join(ROOT, "paper_1708_06301_amd", "csrc", "egosgm_kernels.hip"), "rb").read()
-    except (OSError, ValueError):
-        return None
-    if hashlib.sha256(src).hexdigest() != prof.get("kernel_source_sha256"):
-        return None
-    k = prof.get("kernels", {}).get(kernel_name)
+def measured_valu_active(w, h, D, kernel_name):
+    """SQ_ACTIVE_INST_VALU per dispatch (quad-cycles in which a SIMD's vector
+    ALU issues, summed over all SIMDs)."""
+    k = _profile_entry("sq_counters", w, h, D, kernel_name)
     return None if k is None else k.get("SQ_ACTIVE_INST_VALU")
 
 
-def build_sequence(n_frames, w, h, device):
+def kernel_symbol(stage, tuning, D):
+    """rocprofv3 name of the kernel a reduced frame launches for `stage`."""
+    if stage == "paths":
+        if tuning["ragged_schedule"] == 3:
+            return f"sgm_paths_reg_kernel<{1 if D <= 64 else (2 if D <= 128 else 4)}, 4>"
+        g = tuning["ragged_group"]
+        dr = 64 if D <= 64 else (128 if D <= 128 else 256)
+        return (f"sgm_paths_ragged_kernel<{tuning['ragged_schedule']}, {1 if D <= 128 else 2}, {g}, "
+                f"{dr // g}, 4>")
+    if stage == "select":
+        k = 1 if D <= 16 else (4 if D <= 64 else (8 if D <= 128 else 16))
+        return f"sgm_select_kernel<16, {k}, 0, 8>"
+    return None
+
+
+# ---------------------------------------------------------------- sequences
+def build_sequence(n_frames, w, h, seed_cfg, device):
     import torch
     from paper_1708_06301_amd import pipeline, synth
-    seq = synth.street_sequence(w, h, n_frames, seed=synth.seed_for(1))
+    seq = synth.street_sequence(w, h, n_frames, seed=synth.seed_for(seed_cfg))
     frames, gts = [], []
     t0 = time.time()
     for k in range(n_frames):
@@ -135,31 +161,152 @@ def timed_steps(state, frames, motions, steps, with_events=True, stage_timing=Fa
     return dt, lat
 
 
-def cpu_baseline(seq, frames_np, motions, cfg, budget_s=20.0):
-    """The oracle's own frame loop on the first frames of the same sequence:
-    frame 0 full range, then warp + windows + reduced SGM + Kalman, until
-    about budget_s seconds of single-threaded CPU work have been spent."""
+def frame_config(D, r):
+    from paper_1708_06301_amd import pipeline
+    return pipeline.FrameConfig(max_disp=D, p1=10, p2=120, s_max=80, lr_tol=1, q=0.5,
+                                r_fixed=r, r_min=0, r_max=256, edge_tol=2.0, fill_tol=1.0)
+
+
+def roofline(stages, per_frame, n, tuning, w, h, D):
+    """Roofline of the dominant stage of the reduced frames.  Algorithmic
+    bytes are what the method must move per launch:
+      paths:  4 B per searched slot (the forward and backward sweeps of the
+              aggregation exchange one uint16 partial sum, written and read)
+              plus 50 B per pixel (census codes for both sweeps, window,
+              outputs), i.e. (4|W| + 50) / (8|W|) B per path update;
+      select: the aggregated sum read once (2 B per slot) plus 12 B per
+              pixel (window, outputs, right-map key).
+    achieved = those bytes / the stage's average launch time (library
+    events on the kernel's stream over the timed region)."""
+    dom = max(stages, key=lambda s: stages[s][0])
+    dom_ms, dom_n = stages[dom]
+    avg_ms = dom_ms / max(dom_n, 1)
+    S_red = float(np.mean(per_frame[1:]))
+    if dom == "paths":
+        alg = 4 * S_red + 50 * n
+    elif dom == "select":
+        alg = 2 * S_red + 12 * n
+    else:
+        return None
+    kname = kernel_symbol(dom, tuning, D)
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(w, h, D, kname) if kname else None
+    act = measured_valu_active(w, h, D, kname) if kname else None
+    return dict(kernel=dom, symbol=kname, bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                traffic_over_alg=None if traffic is None else round(traffic / alg, 3),
+                avg_launch_ms=round(avg_ms, 4), launches=dom_n, alg_bytes_per_launch=int(alg),
+                # what does bound the kernel: the fraction of SIMD cycles in
+                # which the vector ALU issues (256 CUs at the 2.4 GHz peak clock)
+                valu_busy=None if act is None else round(act / (256 * avg_ms * 1e-3 * 2.4e9), 3))
+
+
+def measure_sequence(spec, args, dev, tune=True):
+    """Times one sequence workload: the reduced pipeline, the same frames
+    with full-range SGM on every frame, frame latencies, per-stage times
+    and the dominant kernel's roofline."""
+    import torch
+    from paper_1708_06301_amd import autotune, pipeline
+    from paper_1708_06301_amd import egosgm as eg
+    name, w, h, nf, D, r, seed_cfg = spec
+    seq, frames, motions, gts = build_sequence(nf, w, h, seed_cfg, dev)
+    calib = pipeline.camera_of(seq)
+    cfg = frame_config(D, r)
+    red = pipeline.StreamState(w, h, calib, cfg, dev)
+    cfg_full = pipeline.FrameConfig(**{**cfg.__dict__, "full_range_only": True})
+    full = pipeline.StreamState(w, h, calib, cfg_full, dev)
+    if tune:
+        tuning, _ = autotune.tune(lambda: run_sequence(red, frames, motions), w, h, D, tag=name,
+                                  use_cache=not args.retune, log=log)
+    else:
+        tuning = eg.get_tuning()
+    tuning = {k: tuning[k] for k in ("full_group", "ragged_group", "ragged_schedule")}
+    eg.set_tuning(**tuning)
+    upd_red, per_frame = searched_updates(red, frames, motions)
+    upd_full, _ = searched_updates(full, frames, motions)
+    n = w * h
+    search_frac = [s / (n * D) for s in per_frame]
+
+    # a cached tuning skips the tuner's passes: keep the GPU busy for about a
+    # second first, so that the timed steps never start from idle clocks
+    t_settle = time.perf_counter()
+    while time.perf_counter() - t_settle < 1.0:
+        run_sequence(red, frames, motions)
+        torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        run_sequence(red, frames, motions)
+        run_sequence(full, frames, motions)
+    torch.cuda.synchronize()
+
+    # the timed region: exactly `steps` steps of the reduced pipeline with no
+    # instrumentation (the throughput figures), then the same for the full
+    # range; frame latencies come from a second pass with one event pair per
+    # frame, and the per-stage figures from a third pass with the library's
+    # stage events on (both add launch overhead of their own)
+    dt, _ = timed_steps(red, frames, motions, args.steps, with_events=False)
+    dt_full, _ = timed_steps(full, frames, motions, args.steps, with_events=False)
+    _, lat = timed_steps(red, frames, motions, args.steps)
+    _, lat_full = timed_steps(full, frames, motions, args.steps)
+    eg.timing_read()
+    timed_steps(red, frames, motions, args.steps, with_events=False, stage_timing=True)
+    stages = eg.timing_read()
+    stages = {k: v for k, v in stages.items() if v[1]}
+
+    red_lat = lat[:, 1:].ravel()
+    fps, fps_full = nf * args.steps / dt, nf * args.steps / dt_full
+    out = {
+        "gcups": round(upd_red * args.steps / dt / 1e9, 2),
+        "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "workload": f"street sequence {w}x{h}, {nf} frames: frame 0 full SGM D={D}, frames 1-{nf - 1} "
+                    f"warp + refine + Kalman (f32) + reduced SGM r=+-{r}; census 9x7, 8 paths, "
+                    "P1=10, P2=120",
+        "w": w, "h": h, "frames": nf, "max_disp": D, "r": r,
+        "fps": round(fps, 1),
+        "frame_latency_ms": {"p50": round(float(np.percentile(red_lat, 50)), 4),
+                             "p99": round(float(np.percentile(red_lat, 99)), 4),
+                             "frame0": round(float(np.median(lat[:, 0])), 4)},
+        "full_range": {"gcups": round(upd_full * args.steps / dt_full / 1e9, 2), "fps": round(fps_full, 1),
+                       "ms_per_step": round(dt_full / args.steps * 1e3, 3),
+                       "frame_latency_ms_p50": round(float(np.percentile(lat_full.ravel(), 50)), 4)},
+        "speedup_vs_full": round(fps / fps_full, 3),
+        "search_fraction": {"mean_reduced": round(float(np.mean(search_frac[1:])), 4),
+                            "per_frame": [round(x, 4) for x in search_frac]},
+        "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
+        "roofline": roofline(stages, per_frame, n, tuning, w, h, D),
+        "tuning": tuning,
+    }
+    ctx = dict(seq=seq, frames=frames, motions=motions, gts=gts, cfg=cfg, red=red, full=full,
+               calib=calib)
+    return out, ctx
+
+
+# ---------------------------------------------------------------- CPU oracle
+def _oracle_band_loop(left, right, motions, cam, cfg, y0, y1, n_frames, budget_s):
+    """The oracle's own frame loop on rows y0..y1-1 of the sequence (a band
+    matched as an image of its own; the principal point moves with it):
+    frame 0 over the full range, then warp + refine + windows + reduced SGM
+    + Kalman, until n_frames frames or budget_s seconds.  Returns (path
+    updates, seconds, frames done)."""
     from oracle import oracle as orc
-    cam = seq.cam
+    f, cx, cy, b = cam
+    cy = cy - y0
     t0 = time.perf_counter()
-    upd = 0
-    d = p = None
-    k = 0
-    while k < len(frames_np):
-        L, R = frames_np[k]
+    upd, d, p, k = 0, None, None, 0
+    while k < n_frames:
+        L = np.ascontiguousarray(left[k, y0:y1])
+        R = np.ascontiguousarray(right[k, y0:y1])
         if k == 0:
-            o = orc.sgm(L, R, cfg.max_disp, cfg.p1, cfg.p2, cfg.s_max, cfg.lr_tol)
-            upd += 8 * L.size * cfg.max_disp
+            o = orc.sgm(L, R, cfg["D"], cfg["p1"], cfg["p2"], cfg["s_max"], cfg["lr_tol"])
+            upd += 8 * L.size * cfg["D"]
             dk, pk = orc.kalman(np.full(L.shape, -1, np.float32), np.zeros(L.shape, np.float32),
                                 o["disp_sub"].astype(np.float32), o["var_meas"].astype(np.float32))
         else:
-            Rm, t = motions[k]
-            wp = orc.warp(d, p, Rm, t, cam.f, cam.cx, cam.cy, cam.baseline, cfg.q)
+            Rm, t = motions[k, :9].reshape(3, 3), motions[k, 9:]
+            wp = orc.warp(d, p, Rm, t, f, cx, cy, b, cfg["q"])
             dp, pp = orc.refine(wp["d_pred"].astype(np.float32), wp["p_pred"].astype(np.float32),
-                                cfg.edge_tol, cfg.fill_tol)
-            win = orc.windows(dp, pp, cfg.max_disp, r_fixed=cfg.r_fixed, r_min=cfg.r_min,
-                              r_max=cfg.r_max)
-            o = orc.sgm(L, R, cfg.max_disp, cfg.p1, cfg.p2, cfg.s_max, cfg.lr_tol, windows=win)
+                                cfg["edge_tol"], cfg["fill_tol"])
+            win = orc.windows(dp, pp, cfg["D"], r_fixed=cfg["r"], r_min=0, r_max=256)
+            o = orc.sgm(L, R, cfg["D"], cfg["p1"], cfg["p2"], cfg["s_max"], cfg["lr_tol"], windows=win)
             upd += 8 * int(win[2][-1])
             dk, pk = orc.kalman(dp, pp, o["disp_sub"].astype(np.float32),
                                 o["var_meas"].astype(np.float32))
@@ -167,13 +314,126 @@ def cpu_baseline(seq, frames_np, motions, cfg, budget_s=20.0):
         k += 1
         if time.perf_counter() - t0 > budget_s:
             break
-    dt = time.perf_counter() - t0
-    return dict(value=round(upd / dt / 1e9, 4), unit="GCUPS", cores=1, kind="oracle",
-                sample=f"frames 0..{k - 1} of the same sequence (frame 0 full range D="
-                       f"{cfg.max_disp}, then warp + refine + windows r={cfg.r_fixed} + reduced SGM + "
-                       f"Kalman), single-threaded plain C oracle, {dt:.1f} s")
+    return upd, time.perf_counter() - t0, k
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_worker():
+    """One oracle instance of the parallel CPU figure, in a child process
+    started before the parent touched the GPU: it waits for one job line
+    (JSON: dir, y0, y1, frames, budget, out) on stdin, runs it and exits;
+    an empty line or end of input means no job."""
+    line = sys.stdin.readline().strip()
+    if not line:
+        return 0
+    job = json.loads(line)
+    d = job["dir"]
+    left = np.load(os.path.join(d, "left.npy"), mmap_mode="r")
+    right = np.load(os.path.join(d, "right.npy"), mmap_mode="r")
+    motions = np.load(os.path.join(d, "motions.npy"))
+    meta = json.load(open(os.path.join(d, "meta.json")))
+    upd, sec, k = _oracle_band_loop(left, right, motions, meta["cam"], meta["cfg"], job["y0"], job["y1"],
+                                    job["frames"], job["budget"])
+    json.dump(dict(upd=upd, sec=sec, frames=k), open(job["out"], "w"))
+    return 0
+
+
+class CpuPool:
+    """Child processes for the parallel CPU figure, one per core (at most
+    16, the CPU share of one GPU on the box).  They are started before this
+    process initialises the GPU, so no child inherits a GPU context, and
+    they idle on stdin until run() hands each its job."""
+
+    def __init__(self):
+        self.n = max(1, min(16, len(os.sched_getaffinity(0))))
+        self.procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker"],
+                                       stdin=subprocess.PIPE, text=True) for _ in range(self.n)]
+
+    def run(self, jobs):
+        for p, j in zip(self.procs, jobs):
+            p.stdin.write(json.dumps(j) + "\n")
+            p.stdin.flush()
+        return self.close()
+
+    def close(self):
+        ok = True
+        for p in self.procs:
+            try:
+                p.stdin.close()
+            except OSError:
+                pass
+            ok = p.wait() == 0 and ok
+        self.procs = []
+        return ok
+
+
+def cpu_baseline(seq, frames, motions, cfg, pool=None, budget_s=20.0, band=128, par_frames=6):
+    """The plain single-threaded C oracle on bounded samples of the headline
+    workload.  (i) One instance on one core: the oracle's frame loop over a
+    band of `band` rows through the middle of the same frames (frame 0 full
+    range, then reduced frames) until about budget_s seconds.  (ii) With a
+    CpuPool, one instance per pool process and core, each on its own band of
+    rows so the bands tile the whole image, over the first par_frames
+    frames, all at once; its figure is the total updates over the wall
+    time."""
+    from oracle import oracle as orc
+    orc.build(force=False)
+    nf = len(frames)
+    w, h = seq.cam.w, seq.cam.h
+    left = np.stack([np.asarray(L) for L, _ in frames])
+    right = np.stack([np.asarray(R) for _, R in frames])
+    mot = np.zeros((nf, 12))
+    for k in range(1, nf):
+        Rm, t = motions[k]
+        mot[k, :9] = np.asarray(Rm).ravel()
+        mot[k, 9:] = np.asarray(t).ravel()
+    cam = [seq.cam.f, seq.cam.cx, seq.cam.cy, seq.cam.baseline]
+    c = dict(D=cfg.max_disp, p1=cfg.p1, p2=cfg.p2, s_max=cfg.s_max, lr_tol=cfg.lr_tol, q=cfg.q,
+             edge_tol=cfg.edge_tol, fill_tol=cfg.fill_tol, r=cfg.r_fixed)
+    y0 = max(0, h // 2 - band // 2)
+    y1 = min(h, y0 + band)
+    upd1, sec1, k1 = _oracle_band_loop(left, right, mot, cam, c, y0, y1, nf, budget_s)
+    par = None
+    if pool is not None:
+        n_work = pool.n
+        with tempfile.TemporaryDirectory(prefix="egosgm_cpu_") as tmp:
+            np.save(os.path.join(tmp, "left.npy"), left[:par_frames])
+            np.save(os.path.join(tmp, "right.npy"), right[:par_frames])
+            np.save(os.path.join(tmp, "motions.npy"), mot[:par_frames])
+            json.dump(dict(cam=cam, cfg=c), open(os.path.join(tmp, "meta.json"), "w"))
+            cuts = [round(i * h / n_work) for i in range(n_work + 1)]
+            jobs = [dict(dir=tmp, y0=cuts[i], y1=cuts[i + 1], frames=par_frames, budget=4 * budget_s,
+                         out=os.path.join(tmp, f"out{i}.json")) for i in range(n_work)]
+            t0 = time.perf_counter()
+            ok = pool.run(jobs)
+            wall = time.perf_counter() - t0
+            if ok:
+                res = [json.load(open(j["out"])) for j in jobs]
+                par = dict(value=round(sum(r["upd"] for r in res) / wall / 1e9, 4), unit="GCUPS",
+                           cores=n_work, wall_s=round(wall, 1),
+                           sample=f"frames 0..{min(r['frames'] for r in res) - 1} of the same sequence, "
+                                  f"the image cut into {n_work} row bands of about {h // n_work} rows "
+                                  "(each matched on its own), one single-threaded oracle instance per "
+                                  "band and core, all at once")
+    return dict(value=round(upd1 / sec1 / 1e9, 4), unit="GCUPS", cores=1, kind="oracle",
+                cpu_model=_cpu_model(),
+                sample=f"rows {y0}..{y1 - 1} (a {w}x{y1 - y0} band matched on its own) of frames "
+                       f"0..{k1 - 1} of the same sequence: frame 0 full range D={cfg.max_disp}, then "
+                       f"warp + refine + windows r={cfg.r_fixed} + reduced SGM + Kalman; "
+                       f"single-threaded plain C oracle, {sec1:.1f} s",
+                all_cores=par)
+
+
+# ---------------------------------------------------------------- sections
 def batch_section(dev, n_pairs, steps, log):
     """32 mixed stereo pairs (640x192 D=64, 960x288 D=96, 1242x375 D=128) with
     per-pixel windows r = clamp(ceil(3 sqrt(p)), 2, 16) taken from each pair's
@@ -224,7 +484,7 @@ def batch_section(dev, n_pairs, steps, log):
     def best_plan(cs):
         best, times = None, {}
         for g in (16, 32, 64):
-            eg.set_tuning(**{**base, "batch_group": g})
+            eg.set_tuning(batch_group=g)
             p = eg.Plan(cs, prm)
             times[g] = timed(p.run, reps)
             if best is None or times[g] < times[best[0]]:
@@ -258,7 +518,7 @@ def batch_section(dev, n_pairs, steps, log):
     torch.cuda.synchronize()
     paths_ms, paths_n = st_ms["batch_paths"]
     avg = paths_ms / max(paths_n, 1)
-    alg = 16 * slots + 64 * pixels           # as for the single-frame ragged path kernel
+    alg = 4 * slots + 50 * pixels            # the aggregation's bytes (4|W| + 50 per pixel)
     achieved = alg / (avg * 1e-3) / 1e9
     out = {
         "workload": f"{n_pairs} pairs (640x192 D=64, 960x288 D=96, 1242x375 D=128), windows "
@@ -300,7 +560,7 @@ def quality_section(red, full, frames, motions, gts, max_disp):
     for k, (L, R) in enumerate(frames):
         Rm, t = motions[k] if k > 0 else (None, None)
         d_red, _ = red.step(L, R, Rm, t)
-        d_full, _ = full.step(L, R, Rm, t)
+        full.step(L, R, Rm, t)
         torch.cuda.synchronize()
         if k == 0:
             continue
@@ -315,8 +575,9 @@ def variants_section(w, h, calib, cfg, frames, motions, gts, dev, reps=3):
     """Variants on the same sequence: 4 paths (rows and columns only), the
     SAD check (radius 2, at most 600, i.e. a mean absolute difference of 24
     per pixel) after the left-right check, and the left-right check of the
-    prediction (the warped right map, tolerance 1 px) before the windows.  Time per 20-frame step (median of reps, HIP events)
-    and the filtered map's bad-pixel rates."""
+    prediction (the warped right map, tolerance 1 px) before the windows.
+    Time per step (median of reps, HIP events) and the filtered map's
+    bad-pixel rates."""
     import torch
     from paper_1708_06301_amd import pipeline
     from paper_1708_06301_amd.quality import bad_pixels, summarise
@@ -355,7 +616,6 @@ def serve_section(dev, n_frames, log, budget_gib=32.0):
     frame latency (arrival to completion), fps, frames later than one frame
     period.  Then the same frames all queued at once (capacity), reduced and
     full range, for the served speedup over full-range SGM."""
-    import numpy as np
     import torch
     from paper_1708_06301_amd import pipeline, synth
     from paper_1708_06301_amd.serve import GpuExecutor, Server, StreamSpec
@@ -437,22 +697,27 @@ def serve_section(dev, n_frames, log, budget_gib=32.0):
 
 
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--cpu-worker":
+        return cpu_worker()
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--frames", type=int, default=20)
-    ap.add_argument("--width", type=int, default=1242)
-    ap.add_argument("--height", type=int, default=375)
+    ap.add_argument("--workload", choices=("highres", "street"), default="highres",
+                    help="headline sequence (the other one is reported as a section)")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="time the headline sequence only (no other section)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default tuning")
+    ap.add_argument("--no-street", action="store_true", help="skip the 1242x375 section")
     ap.add_argument("--no-batch", action="store_true", help="skip the 32-pair batched section")
     ap.add_argument("--batch-pairs", type=int, default=32)
     ap.add_argument("--no-serve", action="store_true", help="skip the 16-stream serving section")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the variants section (its 4-path runs share the path kernel's symbol)")
+    ap.add_argument("--no-quality", action="store_true")
     ap.add_argument("--serve-frames", type=int, default=300)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (counter calibration)")
@@ -463,9 +728,18 @@ def main():
               file=sys.stderr)
         return 2
 
+    # the CPU baseline's worker processes start before anything touches the GPU
+    pool = CpuPool() if not args.no_cpu_baseline and not args.copy_calibration else None
+    try:
+        return run(args, pool)
+    finally:
+        if pool is not None:
+            pool.close()
+
+
+def run(args, pool):
     import torch
     from paper_1708_06301_amd import egosgm as eg
-    from paper_1708_06301_amd import pipeline
 
     dev = torch.device("cuda:0")
     if args.copy_calibration:
@@ -477,141 +751,55 @@ def main():
         print(json.dumps({"copy_calibration_bytes_per_dispatch": 256 << 20, "dispatches": 5}))
         return 0
     eg.lib()
-    w, h, nf = args.width, args.height, args.frames
-    seq, frames, motions, gts = build_sequence(nf, w, h, dev)
-    calib = pipeline.camera_of(seq)
-    cfg = pipeline.FrameConfig(max_disp=128, p1=10, p2=120, s_max=80, lr_tol=1, q=0.5,
-                               r_fixed=4, r_min=0, r_max=256, edge_tol=2.0, fill_tol=1.0)
-    red = pipeline.StreamState(w, h, calib, cfg, dev)
-    cfg_full = pipeline.FrameConfig(**{**cfg.__dict__, "full_range_only": True})
-    full = pipeline.StreamState(w, h, calib, cfg_full, dev)
-
-    from paper_1708_06301_amd import autotune
-    if args.no_tune:
-        tuning = eg.get_tuning()
-    else:
-        tuning, _ = autotune.tune(lambda: run_sequence(red, frames, motions), w, h,
-                                  cfg.max_disp, tag="street", use_cache=not args.retune, log=log)
-    upd_red, per_frame = searched_updates(red, frames, motions)
-    upd_full, _ = searched_updates(full, frames, motions)
-    n = w * h
-    search_frac = [s / (n * cfg.max_disp) for s in per_frame]
-
-    # a cached tuning skips the tuner's passes: keep the GPU busy for about a
-    # second first, so that the timed steps never start from idle clocks
-    t_settle = time.perf_counter()
-    while time.perf_counter() - t_settle < 1.0:
-        run_sequence(red, frames, motions)
-        torch.cuda.synchronize()
-    for _ in range(args.warmup):
-        run_sequence(red, frames, motions)
-        run_sequence(full, frames, motions)
-    torch.cuda.synchronize()
-
-    # main timed region: exactly `steps` steps of the reduced pipeline with
-    # no instrumentation (the throughput figures), then the same for the
-    # full range; frame latencies come from a second pass with one event pair
-    # per frame, and the per-stage figures from a third pass with the
-    # library's stage events on (both add launch overhead of their own).
-    dt, _ = timed_steps(red, frames, motions, args.steps, with_events=False)
-    dt_full, _ = timed_steps(full, frames, motions, args.steps, with_events=False)
-    _, lat = timed_steps(red, frames, motions, args.steps)
-    _, lat_full = timed_steps(full, frames, motions, args.steps)
-    eg.timing_read()
-    timed_steps(red, frames, motions, args.steps, with_events=False, stage_timing=True)
-    stages = eg.timing_read()
-
-    ms_step = dt / args.steps * 1e3
-    gcups = upd_red * args.steps / dt / 1e9
-    gcups_full = upd_full * args.steps / dt_full / 1e9
-    fps = nf * args.steps / dt
-    fps_full = nf * args.steps / dt_full
-    red_lat = lat[:, 1:].ravel()
-
-    # dominant kernel of the reduced frames (stage events cover frames 1..)
-    dom = max(stages, key=lambda s: stages[s][0])
-    dom_ms, dom_n = stages[dom]
-    avg_ms = dom_ms / max(dom_n, 1)
-    # algorithmic bytes per launch of that kernel on a reduced frame, with
-    # S = mean searched slots of frames 1.. and n = pixels:
-    #   paths:  reads C and writes L once per slot and direction (16 B per
-    #           slot) plus lo/hi/offset (8 B) per pixel and direction;
-    #   select: reads the 8 path costs per slot (8 B), the window (8 B/px)
-    #           and writes disparity, subpixel and variance (10 B/px).
-    S_red = float(np.mean(per_frame[1:]))
-    if dom == "paths":
-        alg_bytes = 16 * S_red + 64 * n
-    elif dom == "select":
-        alg_bytes = 8 * S_red + 18 * n
-    else:
-        alg_bytes = None
-    roof = None
-    kname = None
-    if dom == "paths":
-        g = tuning["ragged_group"]
-        D = cfg.max_disp
-        if tuning["ragged_schedule"] == 3:
-            kname = f"sgm_paths_reg_kernel<{1 if D <= 64 else (2 if D <= 128 else 4)}, 4>"
-        else:
-            dr = 64 if D <= 64 else (128 if D <= 128 else 256)
-            kname = (f"sgm_paths_ragged_kernel<{tuning['ragged_schedule']}, {1 if D <= 128 else 2}, {g}, "
-                     f"{dr // g}, 4>")
-    elif dom == "select":
-        kname = f"sgm_select_kernel<16, {max(1, cfg.max_disp // 16)}, false>"
-    if alg_bytes is not None:
-        achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
-        roof = dict(kernel=dom, bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=measured_traffic(kname) if (w, h, cfg.max_disp) == (1242, 375, 128) else None,
-                    avg_launch_ms=round(avg_ms, 4), launches=dom_n,
-                    alg_bytes_per_launch=int(alg_bytes))
-        # what does bound the kernel: the fraction of SIMD cycles in which the
-        # vector ALU issues, from the counter summary and this run's launch
-        # time (256 CUs at the 2.4 GHz peak clock)
-        act = measured_valu_active(kname) if (w, h, cfg.max_disp) == (1242, 375, 128) else None
-        roof["valu_busy"] = None if act is None else round(act / (256 * avg_ms * 1e-3 * 2.4e9), 3)
+    head_spec, other_spec = (HIGHRES, STREET) if args.workload == "highres" else (STREET, HIGHRES)
+    head, hctx = measure_sequence(head_spec, args, dev, tune=not args.no_tune)
+    log(f"headline {head_spec[0]}: {head['gcups']} GCUPS, {head['ms_per_step']} ms per step")
 
     out = {
         "metric": METRIC,
-        "value": round(gcups, 2),
+        "value": head["gcups"],
         "unit": "GCUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 3),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": f"street sequence {w}x{h}, {nf} frames: frame 0 full SGM "
-                               f"D={cfg.max_disp}, frames 1-{nf - 1} warp + refine + Kalman (f32) + "
-                               f"reduced SGM r=+-{cfg.r_fixed}; census 9x7, 8 paths, P1=10, P2=120",
-                   "w": w, "h": h, "frames": nf, "max_disp": cfg.max_disp, "r": cfg.r_fixed},
-        "fps": round(fps, 1),
-        "frame_latency_ms": {"p50": round(float(np.percentile(red_lat, 50)), 4),
-                             "p99": round(float(np.percentile(red_lat, 99)), 4),
-                             "frame0": round(float(np.median(lat[:, 0])), 4)},
-        "full_range": {"gcups": round(gcups_full, 2), "fps": round(fps_full, 1),
-                       "ms_per_step": round(dt_full / args.steps * 1e3, 3),
-                       "frame_latency_ms_p50": round(float(np.percentile(lat_full.ravel(), 50)), 4)},
-        "speedup_vs_full": round(fps / fps_full, 3),
-        "search_fraction": {"mean_reduced": round(float(np.mean(search_frac[1:])), 4),
-                            "per_frame": [round(x, 4) for x in search_frac]},
-        "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
-        "roofline": roof,
-        "tuning": tuning,
+        "config": {"workload": head["workload"], "w": head["w"], "h": head["h"],
+                   "frames": head["frames"], "max_disp": head["max_disp"], "r": head["r"]},
+        **{k: head[k] for k in ("fps", "frame_latency_ms", "full_range", "speedup_vs_full",
+                                "search_fraction", "stages_ms_per_step", "roofline", "tuning")},
     }
-    out["quality"] = quality_section(red, full, frames, motions, gts, cfg.max_disp)
-    if not args.no_variants:
-        out["variants"] = variants_section(w, h, calib, cfg, frames, motions, gts, dev)
-    if not args.no_batch:
-        out["batched"] = batch_section(dev, args.batch_pairs, args.steps, log)
-    if not args.no_serve:
-        out["serving"] = serve_section(dev, args.serve_frames, log)
+    if not args.only_headline and not args.no_quality:
+        out["quality"] = quality_section(hctx["red"], hctx["full"], hctx["frames"], hctx["motions"],
+                                         hctx["gts"], head["max_disp"])
+    cpu = None
     if not args.no_cpu_baseline:
-        frames_np = [(L.cpu().numpy(), R.cpu().numpy()) for L, R in frames]
-        out["cpu_baseline"] = cpu_baseline(seq, frames_np, motions, cfg, args.cpu_budget)
+        # the oracle gets host copies of the frames; the GPU state is released first
+        seq, frames, motions, cfg = hctx["seq"], hctx["frames"], hctx["motions"], hctx["cfg"]
+        cpu = (seq, [(L.cpu().numpy(), R.cpu().numpy()) for L, R in frames], motions, cfg)
+    del hctx
+    torch.cuda.empty_cache()
+    if not args.only_headline and not args.no_street:
+        sec, sctx = measure_sequence(other_spec, args, dev, tune=not args.no_tune)
+        if not args.no_quality:
+            sec["quality"] = quality_section(sctx["red"], sctx["full"], sctx["frames"], sctx["motions"],
+                                             sctx["gts"], sec["max_disp"])
+        if not args.no_variants:
+            sec["variants"] = variants_section(sec["w"], sec["h"], sctx["calib"], sctx["cfg"],
+                                               sctx["frames"], sctx["motions"], sctx["gts"], dev)
+        out[f"{other_spec[0]}_{other_spec[1]}x{other_spec[2]}"] = sec
+        del sctx
+        torch.cuda.empty_cache()
+    if not args.only_headline and not args.no_batch:
+        out["batched"] = batch_section(dev, args.batch_pairs, args.steps, log)
+    if not args.only_headline and not args.no_serve:
+        out["serving"] = serve_section(dev, args.serve_frames, log)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu_baseline(*cpu, pool=pool, budget_s=args.cpu_budget)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -20,7 +20,9 @@
  *  - Buffer arguments are DEVICE pointers (HIP device memory, e.g. the data
  *    of torch tensors on the GPU) unless the argument says "host".  The
  *    caller owns every buffer; the library never allocates, frees or keeps
- *    caller-visible memory and keeps no state between calls.
+ *    caller-visible memory.  Its only process-wide state is the launch
+ *    tuning (egosgm_set_tuning) and the opt-in stage timing
+ *    (egosgm_timing_enable); results never depend on either.
  *  - Images and maps are row-major, pixel p = y*w + x.  Images are uint8
  *    with a row pitch in bytes (pitch >= w); every map is dense (pitch = w).
  *  - Every call is asynchronous on `stream` (a hipStream_t; NULL is the
@@ -225,9 +227,10 @@ int warp_disparity(const float* d_prev, const float* p_prev, int w, int h,
  *  3. the same with the vertical neighbours, reading the result of step 2.
  * fill_tol <= 0 disables steps 2 and 3.  Means are correctly rounded floats.
  * d_in, p_in: w*h float (a predicted map, e.g. from warp_disparity);
- * d_out, p_out: w*h float, must not alias the inputs; workspace: device
- * memory of egosgm_refine_workspace_bytes(w, h) (reserved: the current
- * kernel keeps its intermediate maps on chip). */
+ * d_out, p_out: w*h float, must not alias the inputs.  workspace,
+ * workspace_bytes: unused (kept for the ABI; may be NULL, 0):
+ * egosgm_refine_workspace_bytes returns 0, since the kernel keeps its
+ * intermediate maps on chip. */
 size_t egosgm_refine_workspace_bytes(int w, int h);
 int refine_prediction(const float* d_in, const float* p_in, int w, int h, float edge_tol,
                       float fill_tol, float* d_out, float* p_out, void* workspace,

@@ -24,9 +24,22 @@ CANDIDATES = [dict(full_group=f, ragged_group=r, ragged_schedule=s)
               for f, r, s in itertools.product((16, 32, 64), (16, 32, 64), (0, 1, 2, 3))]
 
 
+def _kernel_version():
+    """ABI version and a hash of the kernel source: a tuning measured on
+    other kernels is never reused."""
+    import hashlib
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "egosgm_kernels.hip")
+    try:
+        with open(src, "rb") as fh:
+            digest = hashlib.sha256(fh.read()).hexdigest()[:16]
+    except OSError:
+        digest = "nosrc"
+    return f"abi{eg.abi_version()}-{digest}"
+
+
 def _key(w, h, max_disp, tag=""):
     name = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
-    return f"{name}|{w}x{h}|D{max_disp}|{tag}"
+    return f"{name}|{_kernel_version()}|{w}x{h}|D{max_disp}|{tag}"
 
 
 def _load():

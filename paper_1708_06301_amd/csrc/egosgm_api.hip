@@ -633,11 +633,18 @@ int warp_disparity(const float* d_prev, const float* p_prev, int w, int h, const
                : EGOSGM_EDEVICE;
 }
 
-int predict_disparity(const float* d_prev, const float* p_prev, int w, int h, const double* R,
-                      const double* t, double f, double cx, double cy, double baseline, float q,
-                      float edge_tol, float fill_tol, float* d_pred, float* p_pred, uint64_t* zbuf,
-                      void* stream) {
-    if (!d_prev || !p_prev || !d_pred || !p_pred || !zbuf) return EGOSGM_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// The prediction of predict_disparity and predict_disparity_static: the
+// warp's scatter into the z-buffer z, then the refinement decoding it.
+// with_timing: bracket the stages with the timing events when they are on.
+int run_predict(const float* d_prev, const float* p_prev, int w, int h, const double* R,
+                const double* t, double f, double cx, double cy, double baseline, float q,
+                float edge_tol, float fill_tol, float* d_pred, float* p_pred,
+                unsigned long long* z, bool with_timing, hipStream_t s) {
+    if (!d_prev || !p_prev || !d_pred || !p_pred || !z) return EGOSGM_EINVAL;
     if (w <= 0 || h <= 0 || (long long)w * h >= (1ll << 31)) return EGOSGM_EINVAL;
     if (!(q > 0.0f) || !std::isfinite(q)) return EGOSGM_EINVAL;
     if (std::isnan(edge_tol) || std::isnan(fill_tol)) return EGOSGM_EINVAL;
@@ -647,21 +654,33 @@ int predict_disparity(const float* d_prev, const float* p_prev, int w, int h, co
     const int rc = warp_matrix_d(R, t, f, cx, cy, baseline, Hd);
     if (rc) return rc;
     for (int i = 0; i < 16; ++i) H[i] = (float)Hd[i];
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    unsigned long long* z = reinterpret_cast<unsigned long long*>(zbuf);
-    if (timed(EGOSGM_STAGE_WARP, s, [&] { return launch_warp_scatter(d_prev, w, h, H, z, s); }) != hipSuccess)
-        return EGOSGM_EDEVICE;
-    return timed(EGOSGM_STAGE_REFINE, s, [&] {
-               return launch_refine_from_zbuf(z, d_prev, p_prev, w, h, Hd, (double)q, edge_tol,
-                                              fill_tol, d_pred, p_pred, s);
-           }) == hipSuccess
-               ? EGOSGM_OK
-               : EGOSGM_EDEVICE;
+    auto scatter = [&] { return launch_warp_scatter(d_prev, w, h, H, z, s); };
+    auto refine = [&] {
+        return launch_refine_from_zbuf(z, d_prev, p_prev, w, h, Hd, (double)q, edge_tol, fill_tol,
+                                       d_pred, p_pred, s);
+    };
+    if ((with_timing ? timed(EGOSGM_STAGE_WARP, s, scatter) : scatter()) != hipSuccess) return EGOSGM_EDEVICE;
+    return (with_timing ? timed(EGOSGM_STAGE_REFINE, s, refine) : refine()) == hipSuccess ? EGOSGM_OK
+                                                                                           : EGOSGM_EDEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+int predict_disparity(const float* d_prev, const float* p_prev, int w, int h, const double* R,
+                      const double* t, double f, double cx, double cy, double baseline, float q,
+                      float edge_tol, float fill_tol, float* d_pred, float* p_pred, uint64_t* zbuf,
+                      void* stream) {
+    return run_predict(d_prev, p_prev, w, h, R, t, f, cx, cy, baseline, q, edge_tol, fill_tol, d_pred,
+                       p_pred, reinterpret_cast<unsigned long long*>(zbuf), true,
+                       static_cast<hipStream_t>(stream));
 }
 
 size_t egosgm_refine_workspace_bytes(int w, int h) {
-    if (w <= 0 || h <= 0) return 0;
-    return align_up((size_t)w * h * 2 * sizeof(float));
+    (void)w;
+    (void)h;
+    return 0;   // the refinement keeps its intermediate maps on chip
 }
 
 int refine_prediction(const float* d_in, const float* p_in, int w, int h, float edge_tol,
@@ -671,11 +690,11 @@ int refine_prediction(const float* d_in, const float* p_in, int w, int h, float 
     if (w <= 0 || h <= 0 || (long long)w * h >= (1ll << 31)) return EGOSGM_EINVAL;
     if (std::isnan(edge_tol) || std::isnan(fill_tol)) return EGOSGM_EINVAL;
     if (d_out == d_in || p_out == p_in || d_out == p_in || p_out == d_in) return EGOSGM_EINVAL;
-    if (!workspace || workspace_bytes < egosgm_refine_workspace_bytes(w, h)) return EGOSGM_EWORKSPACE;
+    (void)workspace;   // none needed (egosgm_refine_workspace_bytes is 0)
+    (void)workspace_bytes;
     hipStream_t s = static_cast<hipStream_t>(stream);
     return timed(EGOSGM_STAGE_REFINE, s, [&] {
-               return launch_refine(d_in, p_in, w, h, edge_tol, fill_tol, d_out, p_out,
-                                    static_cast<float*>(workspace), s);
+               return launch_refine(d_in, p_in, w, h, edge_tol, fill_tol, d_out, p_out, s);
            }) == hipSuccess
                ? EGOSGM_OK
                : EGOSGM_EDEVICE;

@@ -120,7 +120,7 @@ hipError_t launch_refine_from_zbuf(const unsigned long long* zbuf, const float* 
                                    float edge_tol, float fill_tol, float* d_out, float* p_out,
                                    hipStream_t s);
 hipError_t launch_refine(const float* d_in, const float* p_in, int w, int h, float edge_tol,
-                         float fill_tol, float* d_out, float* p_out, float* tmp, hipStream_t s);
+                         float fill_tol, float* d_out, float* p_out, hipStream_t s);
 hipError_t launch_sad_check(const uint8_t* left, const uint8_t* right, int w, int h, int pitch,
                             int radius, int sad_max, int16_t* disp_wta, float* disp_sub,
                             float* var_meas, hipStream_t s);

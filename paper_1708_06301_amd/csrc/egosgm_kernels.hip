@@ -1929,8 +1929,7 @@ hipError_t launch_refine_from_zbuf(const unsigned long long* zbuf, const float* 
 }
 
 hipError_t launch_refine(const float* d_in, const float* p_in, int w, int h, float edge_tol,
-                         float fill_tol, float* d_out, float* p_out, float* tmp, hipStream_t s) {
-    (void)tmp;   // the fused kernel keeps its intermediate maps in LDS
+                         float fill_tol, float* d_out, float* p_out, hipStream_t s) {
     dim3 grid((w + kRfW - 1) / kRfW, (h + kRfH - 1) / kRfH);
     RefineSrc src{};
     src.d_in = d_in;

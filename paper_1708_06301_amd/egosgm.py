@@ -111,12 +111,15 @@ class Tuning(C.Structure):
 DEFAULT_TUNING = dict(full_group=64, ragged_group=32, ragged_schedule=1, batch_group=16, wide_offsets=0)
 
 
-def set_tuning(full_group: int = 64, ragged_group: int = 64, ragged_schedule: int = 0,
-               batch_group: int | None = None, wide_offsets: int = 0):
-    """Sets the launch shapes; batch_group None keeps the current one."""
-    if batch_group is None:
-        batch_group = get_tuning()["batch_group"] if _lib is not None else 16
-    t = Tuning(full_group, ragged_group, ragged_schedule, batch_group, wide_offsets)
+def set_tuning(full_group: int | None = None, ragged_group: int | None = None,
+               ragged_schedule: int | None = None, batch_group: int | None = None,
+               wide_offsets: int | None = None):
+    """Sets the launch shapes; every argument left None keeps its current
+    value (the library's own default until something else was set)."""
+    cur = get_tuning()
+    new = dict(full_group=full_group, ragged_group=ragged_group, ragged_schedule=ragged_schedule,
+               batch_group=batch_group, wide_offsets=wide_offsets)
+    t = Tuning(**{k: cur[k] if v is None else int(v) for k, v in new.items()})
     _check(lib().egosgm_set_tuning(C.byref(t)), "egosgm_set_tuning")
 
 

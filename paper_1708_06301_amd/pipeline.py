@@ -90,7 +90,6 @@ class StreamState:
         # priority) while the prediction of the frame runs on the caller's
         self.side = torch.cuda.Stream(device=dev) if own_matcher and cfg.overlap_census else None
         self.ev_census = torch.cuda.Event() if self.side is not None else None
-        self.ev_matched = torch.cuda.Event() if self.side is not None else None
         self.census_pending = False
         if cfg.lr_predict:   # right map of the previous frame and its prediction
             self.d_r = torch.full((h, w), -1.0, **f32)
@@ -137,7 +136,10 @@ class StreamState:
         """Starts the matcher's census pass of this frame on the second
         stream, after the previous frame's matcher is done with the
         workspace; match() then waits for it and skips its own."""
-        self.side.wait_event(self.ev_matched)
+        # after everything enqueued on the caller's stream so far: the
+        # previous frame's matcher (done with the workspace) and whatever
+        # produced the images (an asynchronous copy, a renderer)
+        self.side.wait_stream(torch.cuda.current_stream(self.device))
         with torch.cuda.stream(self.side):
             eg.sgm_census(left, right, self.cfg.max_disp, workspace=self.ws)
             self.ev_census.record(self.side)
@@ -156,8 +158,6 @@ class StreamState:
             eg.sgm_full(left, right, prm, out=self.out, workspace=self.ws)
         else:
             eg.sgm_reduced(left, right, *windows, prm, out=self.out, workspace=self.ws)
-        if self.side is not None:
-            self.ev_matched.record(torch.cuda.current_stream(self.device))
         self.filter(left, right, self.out)
 
     def filter(self, left, right, out):

@@ -361,6 +361,14 @@ class GpuExecutor:
             self._rebuild(slot)
         plan = slot["plan"]
         full = []
+        # the frames may still be in flight on the caller's stream (an
+        # asynchronous copy or rendering): the slot's work starts after it,
+        # and the allocator keeps their memory until the slot is done
+        slot["stream"].wait_stream(torch.cuda.current_stream(self.device))
+        for r in group:
+            for t in (r.left, r.right):
+                if isinstance(t, torch.Tensor) and t.is_cuda:
+                    t.record_stream(slot["stream"])
         with torch.cuda.stream(slot["stream"]):
             changes = []
             for r in group:

@@ -111,7 +111,7 @@ def _to_u8(v):
 # Single pairs with a known disparity field
 # --------------------------------------------------------------------------
 def texture(w: int, h: int, seed: int, noise_sigma: float = 6.0, scale: float = 16.0):
-    """uint8 texture: 128 + 90 fBm(x/scale, y/scale) + N(0, sigma^2)."""
+    """uint8 texture: 128 + 180 fBm(x/scale, y/scale) + N(0, sigma^2)."""
     r = rng(seed)
     pn = Perlin(int(r.integers(0, 2**62)))
     yy, xx = np.mgrid[0:h, 0:w].astype(np.float64)
@@ -226,8 +226,7 @@ def make_scene(seed: int, n_frames: int, step: float = 1.0, yaw_sigma_deg: float
         poses.append((Rwc.copy(), c.copy()))
     travel = step * max(n_frames - 1, 0)
     boxes = []
-    n_total = n_boxes + int(np.ceil(n_boxes * travel / 62.0))
-    for _ in range(n_total):
+    for _ in range(n_boxes):
         s = r.uniform(8.0, 70.0 + travel)          # distance along the route
         k = min(int(s / max(step, 1e-9)), n_frames - 1) if travel > 0 else 0
         Rk, ck = poses[k]

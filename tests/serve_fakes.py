@@ -6,7 +6,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from oracle import oracle as orc
+import oracle_frames
 from paper_1708_06301_amd.serve import StreamFailed
 
 
@@ -44,20 +44,9 @@ class OracleExecutor:
             c = spec.calib
             L, R = np.asarray(r.left), np.asarray(r.right)
             full = r.reset or e["d"] is None
-            if full:
-                o = orc.sgm(L, R, cfg.max_disp, cfg.p1, cfg.p2, cfg.s_max, cfg.lr_tol)
-                dk, pk = orc.kalman(np.full(L.shape, -1, np.float32), np.zeros(L.shape, np.float32),
-                                    o["disp_sub"].astype(np.float32),
-                                    o["var_meas"].astype(np.float32))
-            else:
-                wp = orc.warp(e["d"], e["p"], r.R, r.t, c.f, c.cx, c.cy, c.baseline, cfg.q)
-                dp, pp = orc.refine(wp["d_pred"].astype(np.float32),
-                                    wp["p_pred"].astype(np.float32), cfg.edge_tol, cfg.fill_tol)
-                win = orc.windows(dp, pp, cfg.max_disp, r_fixed=cfg.r_fixed, r_min=cfg.r_min,
-                                  r_max=cfg.r_max, k_sigma=cfg.k_sigma)
-                o = orc.sgm(L, R, cfg.max_disp, cfg.p1, cfg.p2, cfg.s_max, cfg.lr_tol, windows=win)
-                dk, pk = orc.kalman(dp, pp, o["disp_sub"].astype(np.float32),
-                                    o["var_meas"].astype(np.float32), cfg.keep_unmeasured)
+            f = oracle_frames.frame(L, R, None if full else e["d"], None if full else e["p"],
+                                    None if full else (r.R, r.t), c, cfg)
+            dk, pk = f["d"], f["p"]
             e["d"], e["p"] = dk.astype(np.float32), pk.astype(np.float32)
             outs.append(dict(full_range=full, d=e["d"].copy(), p=e["p"].copy()))
             rec.append((r.sid, r.seq, full))

@@ -123,7 +123,11 @@ def test_tuning_validation():
     assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, 0, 8))) == -1
     assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, 1, 16, 2))) == -1
     assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, 1, 16, 1))) == 0
+    # arguments left out keep their current value (wide_offsets = 1 from above)
     eg.set_tuning(16, 64, 0, 32)
+    assert eg.get_tuning() == dict(full_group=16, ragged_group=64, ragged_schedule=0, batch_group=32,
+                                   wide_offsets=1)
+    eg.set_tuning(wide_offsets=0)
     assert eg.get_tuning() == dict(full_group=16, ragged_group=64, ragged_schedule=0, batch_group=32,
                                    wide_offsets=0)
     eg.set_tuning(**before)

@@ -459,13 +459,21 @@ def test_plan_matches_single_pairs(group, n_paths):
         ref = _single(c, prm)
         torch.cuda.synchronize()
         assert _same(plan.outputs[i], ref) is None, (i, _same(plan.outputs[i], ref))
-    # one pair also against the oracle
-    c = cases[2]
-    h, w = c["left"].shape
-    wo = tuple(t.cpu().numpy().ravel() for t in c["windows"][:2]) + (c["windows"][2].cpu().numpy().view(np.uint32),)
-    o = orc.sgm(c["left"].cpu().numpy(), c["right"].cpu().numpy(), 128, 9, 110, 70, 1, windows=wo,
-                n_paths=n_paths)
-    assert np.array_equal(_np(plan.outputs[2]["disp_wta"]), o["disp_wta"])
+    # every pair also against the oracle, every output
+    for i, c in enumerate(cases):
+        wo = None
+        if c["windows"] is not None:
+            wo = (c["windows"][0].cpu().numpy().ravel(), c["windows"][1].cpu().numpy().ravel(),
+                  c["windows"][2].cpu().numpy().view(np.uint32))
+        o = orc.sgm(c["left"].cpu().numpy(), c["right"].cpu().numpy(), c["max_disp"], prm.p1, prm.p2,
+                    prm.s_max, prm.lr_tol, windows=wo, n_paths=n_paths)
+        g = plan.outputs[i]
+        assert np.array_equal(_np(g["disp_wta"]), o["disp_wta"]), i
+        assert np.array_equal(_np(g["disp_right"]), o["disp_right"]), i
+        assert np.array_equal(_np(g["var_meas"]).astype(np.float64), o["var_meas"]), i
+        sub = _np(g["disp_sub"]).astype(np.float64)
+        assert np.array_equal(sub < 0, o["disp_sub"] < 0), i
+        assert np.abs(sub - o["disp_sub"]).max() <= TOL, i
     plan.close()
 
 

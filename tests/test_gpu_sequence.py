@@ -1,0 +1,123 @@
+"""GPU parity over whole frame sequences (the per-frame loop of Sec. 2).
+
+Frame k of a sequence is predicted from D^{k-1}, P^{k-1} (warp and
+refinement, Sec. 2.2), matched inside the prediction's windows (Sec. 2.3)
+and updated by the Kalman filter (Sec. 2.4, Eq. 10-12), so every frame
+depends on all earlier ones.  At each frame the oracle is given the GPU's
+own D^{k-1}, P^{k-1} and checked step by step: the prediction (validity
+exact, values within 1e-4), the windows computed from the GPU's prediction
+(exact), the matcher inside those windows (integers exact, subpixel within
+1e-4) and the update of the GPU's prediction with the oracle's measurement
+(validity exact, within 1e-4).  The shapes and the launch configuration are
+those the benchmark times: the 20-frame 1242x375 street sequence (D = 128,
+r = 4) and the 2048x1024 sequence (D = 256, r = 6).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle_frames
+from paper_1708_06301_amd import egosgm as eg
+from paper_1708_06301_amd import pipeline, synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+DEV = "cuda:0"
+
+
+def _say(*a):
+    print("CASE", *a, flush=True)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _close_maps(g, o, what):
+    """Validity exact; valid values within TOL; invalid ones written as
+    (-1, 0)."""
+    g = np.asarray(g, np.float64)
+    o = np.asarray(o, np.float64)
+    assert np.array_equal(g >= 0, o >= 0), f"{what}: validity"
+    v = o >= 0
+    if v.any():
+        err = np.abs(g[v] - o[v]).max()
+        assert err <= TOL, f"{what}: max error {err}"
+
+
+def _check_matcher(st, o, what):
+    assert np.array_equal(_np(st.out["disp_wta"]), o["disp_wta"]), f"{what}: disp_wta"
+    assert np.array_equal(_np(st.out["disp_right"]), o["disp_right"]), f"{what}: disp_right"
+    assert np.array_equal(_np(st.out["var_meas"]).astype(np.float64), o["var_meas"]), f"{what}: var_meas"
+    sub = _np(st.out["disp_sub"]).astype(np.float64)
+    assert np.array_equal(sub < 0, o["disp_sub"] < 0), f"{what}: subpixel validity"
+    assert np.abs(sub - o["disp_sub"]).max() <= TOL, f"{what}: subpixel"
+
+
+def _run_chain(seq, cfg, n_frames, label):
+    """Steps the GPU pipeline over n_frames and checks every frame against
+    the oracle fed with the GPU's previous maps.  Returns the searched
+    fractions of the reduced frames."""
+    eg.set_tuning(**eg.DEFAULT_TUNING)
+    w, h = seq.cam.w, seq.cam.h
+    calib = pipeline.camera_of(seq)
+    st = pipeline.StreamState(w, h, calib, cfg, DEV)
+    motions = pipeline.motions(seq)
+    fractions = []
+    for k in range(n_frames):
+        _say(label, "frame", k)
+        L, R, _ = seq.frame(k)
+        Lg, Rg = torch.from_numpy(L).to(DEV), torch.from_numpy(R).to(DEV)
+        d_prev, p_prev = (None, None) if k == 0 else (_np(st.d), _np(st.p))
+        win = st.predict(*motions[k]) if k > 0 else st.predict()
+        st.match(Lg, Rg, win)
+        d, p = st.update()
+        torch.cuda.synchronize()
+        if k == 0:
+            o = oracle_frames.match(L, R, cfg)
+            _check_matcher(st, o, f"frame {k}")
+            od, op = oracle_frames.update(None, None, o, cfg)
+        else:
+            Rm, t = motions[k]
+            odp, opp, _ = oracle_frames.predict(d_prev, p_prev, Rm, t, calib, cfg)
+            gdp, gpp = _np(st.d_pred), _np(st.p_pred)
+            _close_maps(gdp, odp, f"frame {k} prediction d")
+            valid = odp >= 0
+            assert np.abs(gpp[valid].astype(np.float64) - opp[valid]).max() <= TOL, f"frame {k} prediction p"
+            wo = oracle_frames.windows(gdp, gpp, cfg)
+            assert np.array_equal(_np(win[0]).ravel(), wo[0]), f"frame {k}: lo"
+            assert np.array_equal(_np(win[1]).ravel(), wo[1]), f"frame {k}: hi"
+            assert np.array_equal(_np(win[2]).view(np.uint32), wo[2]), f"frame {k}: offsets"
+            fractions.append(int(wo[2][-1]) / (w * h * cfg.max_disp))
+            o = oracle_frames.match(L, R, cfg, wo)
+            _check_matcher(st, o, f"frame {k}")
+            od, op = oracle_frames.update(gdp, gpp, o, cfg)
+        _close_maps(_np(d), od, f"frame {k} update d")
+        gp, v = _np(p).astype(np.float64), od >= 0
+        assert np.abs(gp[v] - op[v]).max() <= TOL if v.any() else True, f"frame {k} update p"
+        assert (gp[~v] == 0).all(), f"frame {k}: variance of invalid pixels"
+    return fractions
+
+
+@pytest.mark.timeout(900)
+def test_street_sequence_20_frames_chained():
+    """The benchmark's 1242x375 sequence: frame 0 full range (D = 128),
+    frames 1-19 reduced (r = 4), all 20 chained."""
+    seq = synth.street_sequence(1242, 375, 20, seed=synth.seed_for(1))
+    cfg = pipeline.FrameConfig(max_disp=128, p1=10, p2=120, s_max=80, lr_tol=1, q=0.5,
+                               r_fixed=4, r_min=0, r_max=256, edge_tol=2.0, fill_tol=1.0)
+    frac = _run_chain(seq, cfg, 20, "street 1242x375")
+    assert 0.0 < max(frac) < 0.5
+
+
+@pytest.mark.timeout(900)
+def test_highres_sequence_first_frames_chained():
+    """The 2048x1024 sequence at full size: frame 0 over the full range with
+    D = 256 (8 w h D = 2^32 path updates, where the path kernels address by
+    64 bits), then two reduced frames with r = 6."""
+    seq = synth.street_sequence(2048, 1024, 3, seed=synth.seed_for(3))
+    cfg = pipeline.FrameConfig(max_disp=256, p1=10, p2=120, s_max=80, lr_tol=1, q=0.5,
+                               r_fixed=6, r_min=0, r_max=256, edge_tol=2.0, fill_tol=1.0)
+    frac = _run_chain(seq, cfg, 3, "highres 2048x1024")
+    assert 0.0 < max(frac) < 0.5

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle_frames
 from paper_1708_06301_amd import egosgm as eg
 from paper_1708_06301_amd import pipeline, synth
 from paper_1708_06301_amd.serve import GpuExecutor, Server, StreamSpec
@@ -131,3 +132,61 @@ def test_served_stream_is_the_same_alone_in_a_mix_and_in_the_pipeline(slots):
         for a, b, c in zip(alone[0][k], mix[1][k], ref[k]):
             assert torch.equal(a, b), k
             assert torch.equal(a, c), k
+
+
+def test_served_frames_follow_the_oracle():
+    """Every frame served in a mix of two streams (2 launch slots) equals
+    the oracle's frame step from the stream's served previous maps: warp,
+    refinement, windows, matching and Kalman update (Sec. 2): validity
+    exact, values within 1e-4."""
+    _say("served mix against the oracle")
+    cfg_a = pipeline.FrameConfig(max_disp=32, r_fixed=3)
+    cfg_b = pipeline.FrameConfig(max_disp=16, r_fixed=-1, r_min=1, r_max=8)
+    A = (*_sequence(128, 48, 4, 1), cfg_a)
+    B = (*_sequence(96, 40, 4, 2), cfg_b)
+    served = _serve([A, B], [(0, 0), (1, 0), (1, 1), (0, 1), (0, 2), (1, 2), (1, 3), (0, 3)], 2)
+    for i, (seq, frames, motions, cfg) in enumerate((A, B)):
+        calib = pipeline.camera_of(seq)
+        d_prev = p_prev = None
+        for k in range(4):
+            L, R = (t.cpu().numpy() for t in frames[k])
+            f = oracle_frames.frame(L, R, d_prev, p_prev, motions[k], calib, cfg)
+            d, p = (t.cpu().numpy() for t in served[i][k])
+            v = f["d"] >= 0
+            assert np.array_equal(d >= 0, v), (i, k)
+            assert np.abs(d[v] - f["d"][v]).max() <= 1e-4, (i, k)
+            assert np.abs(p[v] - f["p"][v]).max() <= 1e-4, (i, k)
+            assert (d[~v] == -1).all() and (p[~v] == 0).all(), (i, k)
+            d_prev, p_prev = d, p
+
+
+def test_frames_copied_without_a_sync_are_served_like_resident_ones():
+    """Frames handed to the server right after an asynchronous host-to-device
+    copy on the caller's stream (pinned memory, non_blocking, no
+    synchronisation) give the same results as frames already resident: the
+    executor orders its slot streams after the caller's stream."""
+    _say("serving frames from non-blocking copies")
+    cfg = pipeline.FrameConfig(max_disp=32, r_fixed=3)
+    seq, frames, motions = _sequence(128, 48, 4, 4)
+    host = [(L.cpu().pin_memory(), R.cpu().pin_memory()) for L, R in frames]
+    ref = _serve([(seq, frames, motions, cfg)], [(0, k) for k in range(4)], 2)
+    for slots in (1, 2):
+        ex = GpuExecutor(DEV, n_slots=slots, keep_outputs=True)
+        srv = Server(ex, hbm_budget=1 << 40)
+        sid = srv.open_stream(StreamSpec(128, 48, pipeline.camera_of(seq), cfg))
+        torch.cuda.synchronize()
+        for k in range(4):
+            L = torch.empty((48, 128), dtype=torch.uint8, device=DEV)
+            R = torch.empty((48, 128), dtype=torch.uint8, device=DEV)
+            torch.cuda._sleep(2_000_000)          # keep the caller's stream busy before the copies
+            L.copy_(host[k][0], non_blocking=True)
+            R.copy_(host[k][1], non_blocking=True)
+            Rm, t = motions[k] if k > 0 else (None, None)
+            srv.submit(sid, L, R, Rm, t)
+            srv.tick()
+        srv.drain(timeout=120)
+        torch.cuda.synchronize()
+        got = sorted(srv.results, key=lambda r: r.seq)
+        assert [r.status for r in got] == ["ok"] * 4
+        for k in range(4):
+            assert torch.equal(got[k].d, ref[0][k][0]) and torch.equal(got[k].p, ref[0][k][1]), (slots, k)
