@@ -376,7 +376,13 @@ typedef struct egosgm_tuning {
                                    the rest through LDS rows;
                                 2: every scanline as the rows of 1;
                                 3: every scanline on registers over its window, one wave
-                                   per scanline (window-start moves by lane permutes)        */
+                                   per scanline (window-start moves by lane permutes);
+                                4, 5: grouped scanlines: 8 (4) scanlines per wave, 8 (16)
+                                   lanes each; a window spanning up to 16 (32) slots is done
+                                   by its group, a wider one by the whole wave; the volumes
+                                   use an aligned internal layout, and the selection takes
+                                   narrow windows 4 lanes per pixel (images whose volumes
+                                   would pass 4 GiB at w*h*(D+9) bytes fall back to 1)      */
     int32_t batch_group;     /* lanes per scanline in batched plans (fixed when a plan is
                                 created): 16, 32, 64                                           */
     int32_t wide_offsets;    /* LDS scanlines of ragged windows: 0 addresses window words and

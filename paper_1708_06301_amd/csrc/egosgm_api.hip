@@ -69,22 +69,27 @@ constexpr int kMaxWidth = 4064;  // the epilogue keeps 16 bytes per column of a 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace: census codes of both images, right-map keys, the cost volume
-// and the eight path volumes (all sized for the full range).
+// and the eight path volumes (all sized for the full range).  A volume holds
+// either the ragged layout (w*h*D bytes at most, stride vol_stride) or the
+// quad layout of the grouped kernels (stride vol_stride_q; 0 when its
+// offsets would not fit 32 bits, and those kernels are then not used).
 struct WsLayout {
-    size_t census_l, census_r, key_r, meta, cost, vol, vol_stride, total;
+    size_t census_l, census_r, key_r, meta, cost, vol, vol_stride, vol_stride_q, total;
 };
 
 bool ws_layout(int w, int h, int D, WsLayout& L) {
     if (w <= 0 || h <= 0 || D < 1 || D > kMaxDisp) return false;
     const size_t n = (size_t)w * (size_t)h;
     L.vol_stride = n * (size_t)D;
+    L.vol_stride_q = quad_volume_bytes(w, h, D);
+    const size_t vbytes = std::max(L.vol_stride, L.vol_stride_q);
     L.census_l = 0;
     L.census_r = L.census_l + align_up(n * sizeof(uint64_t));
     L.key_r = L.census_r + align_up(n * sizeof(uint64_t));
     L.meta = L.key_r + align_up(n * sizeof(uint32_t));
     L.cost = L.meta + align_up(n * sizeof(uint64_t));
-    L.vol = L.cost + align_up(L.vol_stride);
-    L.total = L.vol + align_up((size_t)kNumPaths * L.vol_stride);
+    L.vol = L.cost + align_up(vbytes);
+    L.total = L.vol + align_up((size_t)kNumPaths * vbytes);
     return true;
 }
 
@@ -145,7 +150,14 @@ int run_sgm(const uint8_t* left, const uint8_t* right, int w, int h, int pitch, 
     a.key_r = reinterpret_cast<uint32_t*>(base + L.key_r);
     a.meta = reinterpret_cast<uint64_t*>(base + L.meta);
     a.vol = base + L.vol;
-    a.vol_stride = L.vol_stride;
+    // grouped scanlines (schedules 4, 5) need the quad layout; where its
+    // offsets would not fit 32 bits the rows-on-registers schedule runs instead
+    a.quad = 0;
+    if (win.lo != nullptr && a.ragged_schedule >= 4) {
+        if (L.vol_stride_q != 0) a.quad = 1;
+        else a.ragged_schedule = 1;
+    }
+    a.vol_stride = a.quad ? L.vol_stride_q : L.vol_stride;
     a.disp_wta = disp_wta;
     a.disp_sub = disp_sub;
     a.var_meas = var_meas;
@@ -172,11 +184,19 @@ int run_sgm(const uint8_t* left, const uint8_t* right, int w, int h, int pitch, 
         if (dbg->census_right &&
             hipMemcpyAsync(dbg->census_right, a.census_r, n * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
             return EGOSGM_EDEVICE;
-        if (dbg->paths &&
-            hipMemcpyAsync(dbg->paths, a.vol, kNumPaths * a.vol_stride, hipMemcpyDeviceToDevice, s) != hipSuccess)
-            return EGOSGM_EDEVICE;
-        if (dbg->cost && launch_copy_slots(a, a.cost, dbg->cost, s) != hipSuccess)
-            return EGOSGM_EDEVICE;
+        if (a.quad) {
+            if (dbg->paths && launch_copy_quad_slots(a, a.vol, a.vol_stride, dbg->paths, L.vol_stride,
+                                                     a.n_paths, s) != hipSuccess)
+                return EGOSGM_EDEVICE;
+            if (dbg->cost && launch_copy_quad_slots(a, a.cost, 0, dbg->cost, 0, 1, s) != hipSuccess)
+                return EGOSGM_EDEVICE;
+        } else {
+            if (dbg->paths && hipMemcpyAsync(dbg->paths, a.vol, kNumPaths * a.vol_stride,
+                                             hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return EGOSGM_EDEVICE;
+            if (dbg->cost && launch_copy_slots(a, a.cost, dbg->cost, s) != hipSuccess)
+                return EGOSGM_EDEVICE;
+        }
     }
     return EGOSGM_OK;
 }
@@ -719,7 +739,7 @@ int egosgm_set_tuning(const egosgm_tuning* t) {
     if (!t) return EGOSGM_EINVAL;
     auto ok = [](int g) { return g == 16 || g == 32 || g == 64; };
     if (!ok(t->full_group) || !ok(t->ragged_group) || !ok(t->batch_group) || t->ragged_schedule < 0 ||
-        t->ragged_schedule > 3 || (t->wide_offsets != 0 && t->wide_offsets != 1))
+        t->ragged_schedule > 5 || (t->wide_offsets != 0 && t->wide_offsets != 1))
         return EGOSGM_EINVAL;
     std::lock_guard<std::mutex> g(g_tuning_mu);
     g_tuning = *t;

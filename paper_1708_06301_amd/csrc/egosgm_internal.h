@@ -43,8 +43,10 @@ struct SgmLaunch {
     int n_paths;             // aggregated directions: 8, or 4 (directions 0-3)
     int full_group;          // lanes per scanline, full-range path kernel (16, 32, 64)
     int ragged_group;        // lanes per scanline, ragged path kernel (16, 32, 64)
-    int ragged_schedule;     // 0: all scanlines via LDS, 1: rows on packed registers, 2: all packed
+    int ragged_schedule;     // 0: all scanlines via LDS, 1: rows on packed registers, 2: all packed,
+                             // 3: relative registers, 4/5: grouped scanlines (8/16 lanes, quad layout)
     int wide_offsets;        // 1: LDS scanlines keep 64-bit addresses even where 32-bit offsets fit
+    int quad;                // ragged windows in the quad slot layout (grouped kernels, schedules 4-5)
     uint8_t* cost;           // matching cost per search slot
     uint32_t* key_r;         // w*h right-map keys (S << 9 | d), cleared by the census pass
     uint64_t* meta;          // w*h packed windows (offset | lo << 32 | width << 48), written by
@@ -106,6 +108,11 @@ hipError_t launch_sgm_cost(const SgmLaunch& a, hipStream_t s);
 hipError_t launch_sgm_paths(const SgmLaunch& a, hipStream_t s);
 hipError_t launch_sgm_select(const SgmLaunch& a, hipStream_t s);
 hipError_t launch_copy_slots(const SgmLaunch& a, const uint8_t* src, uint8_t* dst, hipStream_t s);
+// quad-layout volumes (stride src_stride) into the public ragged layout (stride dst_stride)
+hipError_t launch_copy_quad_slots(const SgmLaunch& a, const uint8_t* src, size_t src_stride, uint8_t* dst,
+                                  size_t dst_stride, int nvol, hipStream_t s);
+// bytes of one quad-layout volume for w*h pixels and range D (0 if it does not fit 32-bit offsets)
+size_t quad_volume_bytes(int w, int h, int D);
 hipError_t launch_windows(const float* d_pred, const float* p_pred, int w, int h,
                           float k_sigma, int r_fixed, int r_min, int r_max, int max_disp,
                           int16_t* lo, int16_t* hi, uint32_t* off, uint32_t* chunk_tot,

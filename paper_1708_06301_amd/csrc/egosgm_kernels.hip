@@ -1093,6 +1093,528 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_ragged_kernel(SgmLaunch a, i
     }
 }
 
+// ------------------------------------------------------------------ grouped scanlines
+// Quad slot layout (ragged windows on the grouped kernels).  Pixel p owns
+// the slots of disparities B(p) .. E(p)-1, B = lo & ~3, E = (lo + w + 3) & ~3,
+// from byte offset q(p) = (off(p) + 9p + 3) & ~3 of each volume (costs and
+// path costs).  q(p) is a multiple of 4 and q(p+1) >= q(p) + E - B (since
+// E - B <= w + 6), so a lane reads and writes whole aligned pairs or quads
+// of slots; the slots of [B, E) outside the window are padding, never read
+// as results.  A volume needs at most w*h*(D+9) + 8 bytes.
+__device__ inline uint32_t quad_off(uint32_t off, uint32_t p) { return (off + 9u * p + 3u) & ~3u; }
+
+// bytes b0 b1 of v -> (b0 | b1 << 16), bytes b2 b3 -> (b2 | b3 << 16)
+__device__ inline uint32_t bytes01(uint32_t v) { return __builtin_amdgcn_perm(0u, v, 0x0C010C00u); }
+__device__ inline uint32_t bytes23(uint32_t v) { return __builtin_amdgcn_perm(0u, v, 0x0C030C02u); }
+// low bytes of the two 16-bit halves of a and b -> a.lo, a.hi, b.lo, b.hi
+__device__ inline uint32_t pack4(uint32_t a, uint32_t b) { return __builtin_amdgcn_perm(b, a, 0x06040200u); }
+__device__ inline uint32_t pk_max(uint32_t a, uint32_t b) {
+    return as_u32(__builtin_elementwise_max(as_pk(a), as_pk(b)));
+}
+// +infinity in the halves of a pair whose slot lies outside [lo, lo+w)
+__device__ inline uint32_t pair_mask(int d, int lo, int w) {
+    return ((uint32_t)(d - lo) < (uint32_t)w ? 0u : (uint32_t)kInf) |
+           ((uint32_t)(d + 1 - lo) < (uint32_t)w ? 0u : (uint32_t)kInf << 16);
+}
+
+// Minimum over each 8-lane half of a 16-lane row, left in all its lanes.
+__device__ inline int min8(int v) {
+    v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0xB1, 0xF, 0xF, true));    // quad xor 1
+    v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x4E, 0xF, 0xF, true));    // quad xor 2
+    v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x141, 0xF, 0xF, true));   // row_half_mirror
+    return v;
+}
+template <int G>
+__device__ inline int small_group_min(int v) {
+    if constexpr (G == 8) return min8(v);
+    else return row_min16(v);
+}
+
+// Scanlines of the grouped kernel: the waves of each direction, in task
+// order (rows, columns, diagonals), each taking NG = 64/G scanlines of one
+// direction.  With `strided`, group g of wave j of a row or column direction
+// takes scanline g*waves + j, so each wave mixes scanlines from every part
+// of the image; diagonals take NG neighbouring scanlines (similar lengths).
+struct GroupTasks {
+    int n_dirs;
+    int strided;
+    int n_scan[kNumPaths];
+    int first_task[kNumPaths];
+    int wave_start[kNumPaths + 1];
+};
+
+// Grouped scanline kernel (ragged windows, quad layout).  A wave walks NG
+// scanlines of one direction at once, lane group g (G lanes) owning
+// scanline g.  Each scanline keeps its previous pixel's path costs in a
+// ping-pong pair of LDS rows indexed by absolute disparity (entry d + 2;
+// +infinity outside the written window, erased after use), as packed u16
+// pairs.  A step of a pixel whose window span fits 2G slots ("narrow") is
+// done by its own group, lane l owning slots B + 2l and B + 2l + 1: the d-1,
+// d, d+1 predecessors are three aligned dword reads and two alignbits.  A
+// pixel with a wider span ("wide": at the sizes used here, the pixels that
+// fall back to the full range) is done by the whole wave, lane L owning the
+// quad B + 4L .. B + 4L + 3, one wide pixel after another.  Window words
+// are prefetched 2*PF steps ahead, narrow costs PF steps ahead, and the
+// costs of the first NW wide pixels of a step PF steps ahead, all into ring
+// slots named at compile time.  A zero predecessor over the first pixel's
+// window makes the first step L = C.
+template <int G, int DMAX, int PF>
+__global__ __launch_bounds__(kBlock) void sgm_paths_group_kernel(SgmLaunch a, GroupTasks t) {
+    constexpr int NG = 64 / G;
+    constexpr int ROW = DMAX + 2 * G + 8;
+    constexpr int RM = 2 * PF;
+    constexpr int NW = 2;
+    static_assert(ROW % 4 == 0, "rows start 8-byte aligned");
+    __shared__ __attribute__((aligned(16))) uint16_t rows_all[kBlock / 64][NG][2][ROW];
+    const int lane = (int)(threadIdx.x & 63u);
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int gw = (int)blockIdx.x * (kBlock / 64) + wv;
+    if (gw >= t.wave_start[t.n_dirs]) return;
+    int dir = 0;
+    while (gw >= t.wave_start[dir + 1]) ++dir;
+    const int wl = gw - t.wave_start[dir];
+    const int nwav = t.wave_start[dir + 1] - t.wave_start[dir];
+    const int g = lane / G, l = lane % G;
+    const int j = (t.strided && dir < 4) ? g * nwav + wl : wl * NG + g;
+    const bool has = j < t.n_scan[dir];
+    Scan sc{dir, 0, 0, 0};
+    if (has) sc = scan_of(t.first_task[dir] + j, a.w, a.h);
+    const int len = has ? sc.len : 0;
+    int nmax = 0;
+#pragma unroll
+    for (int k = 0; k < NG; ++k) nmax = max(nmax, __builtin_amdgcn_readlane(len, k * G));
+    const int dp = sc.dp, p0 = sc.p0;
+    const int p_last = len > 0 ? p0 + (len - 1) * dp : p0;
+
+    const uint32_t cap = (uint32_t)a.vol_stride;
+    const __amdgpu_buffer_rsrc_t cbuf = byte_buffer(a.cost, cap);
+    const __amdgpu_buffer_rsrc_t vbuf = byte_buffer(a.vol + (size_t)dir * a.vol_stride, cap);
+    const __amdgpu_buffer_rsrc_t mbuf = byte_buffer(a.meta, (uint32_t)a.w * (uint32_t)a.h * 8u);
+    const uint32_t p1pk = (uint32_t)a.p1 * 0x10001u;
+    const int p2 = a.p2;
+
+    uint16_t (*rows)[2][ROW] = rows_all[wv];
+    uint32_t* myrow[2] = {reinterpret_cast<uint32_t*>(rows[g][0]), reinterpret_cast<uint32_t*>(rows[g][1])};
+
+    // window words of steps 0 .. RM-1, then one RM steps ahead per step
+    uint64_t mm[RM];
+    const int q_lo = 8 * min(p0, p_last), q_hi = 8 * max(p0, p_last), dq = 8 * dp;
+    int q_next = 8 * p0;
+    auto next_meta = [&](int k) {
+        mm[k] = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(mbuf, min(max(q_next, q_lo), q_hi), 0, 0));
+        q_next += dq;
+    };
+#pragma unroll
+    for (int k = 0; k < RM; ++k) next_meta(k);
+
+    uint32_t cst[PF];          // narrow: this lane's two cost bytes
+    uint32_t wc[PF][NW];       // wide: this lane's four cost bytes of the k-th prefetched wide pixel
+    int wg[PF][NW];            // wide: group of that pixel (wave-uniform), -1 none
+    // Costs of step `i` (window word mw) into ring slot `s`.  Every load is
+    // issued unconditionally (a step without wide pixels loads offset 0), so
+    // the number of memory operations between a load and its use is fixed
+    // and the waits before a use leave the later prefetches in flight.
+    auto load_costs = [&](int s, uint64_t mw, int i) {
+        cst[s] = __builtin_amdgcn_raw_buffer_load_b16(cbuf, meta_off(mw) + 2u * (uint32_t)l, 0, 0);
+        const int lo = meta_lo(mw), w = meta_w(mw);
+        const bool wide = i < len && ((lo + w + 3) & ~3) - (lo & ~3) > 2 * G;
+        uint64_t b = __builtin_amdgcn_ballot_w64(wide && l == 0);
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const int bit = b ? (int)__builtin_ctzll(b) : -1;
+            b &= b - 1;
+            const uint32_t og = bit >= 0 ? (uint32_t)__builtin_amdgcn_readlane((int)meta_off(mw), bit) : 0u;
+            wc[s][k] = __builtin_amdgcn_raw_buffer_load_b32(cbuf, og + 4u * (uint32_t)lane, 0, 0);
+            wg[s][k] = bit >= 0 ? bit / G : -1;
+        }
+    };
+#pragma unroll
+    for (int k = 0; k < PF; ++k) load_costs(k, mm[k], k);
+
+    // every entry +infinity, then a zero predecessor over the first window
+    {
+        uint32_t* all = reinterpret_cast<uint32_t*>(rows_all[wv]);
+        for (int e = lane; e < NG * ROW; e += 64) all[e] = kInfPk;
+    }
+    lds_order();
+    int pmode = 0;      // what the previous step wrote: 0 nothing, 1 the narrow frame, 2 span [pb, pe)
+    int pb = 0, pe = 0;
+    int perase = 0;     // pmode 1: dword of this lane's pair
+    if (has) {
+        const int lo = meta_lo(mm[0]), w = meta_w(mm[0]);
+        for (int s = l; s < w; s += G) rows[g][1][lo + s + 2] = 0;
+        pmode = 2;
+        pb = lo & ~3;
+        pe = (lo + w + 3) & ~3;
+    }
+    lds_order();
+    int m = 0;
+
+    // One wide pixel (group gg's window [lo_g, lo_g + w_g) at quad offset
+    // o_g, predecessor minimum m_g, this lane's cost dword cw) by the whole
+    // wave; returns the new minimum (wave-uniform).
+    auto wide_step = [&](int gg, int lo_g, int w_g, uint32_t o_g, int m_g, uint32_t cw, int par) {
+        const int Bw = lo_g & ~3, Ew = (lo_g + w_g + 3) & ~3;
+        const uint32_t* prg = reinterpret_cast<const uint32_t*>(rows[gg][par ^ 1]);
+        uint32_t* cug = reinterpret_cast<uint32_t*>(rows[gg][par]);
+        const int d = Bw + 4 * lane;
+        const bool in = d < Ew;
+        const int qd = in ? d >> 1 : 0;   // even: 8-byte aligned
+        const u32x2 A = *reinterpret_cast<const u32x2*>(prg + qd);
+        const u32x2 Bq = *reinterpret_cast<const u32x2*>(prg + qd + 2);
+        const uint32_t XM = align16(Bq.x, A.y);
+        const uint32_t m2 = (uint32_t)(m_g + p2) * 0x10001u, mg = (uint32_t)m_g * 0x10001u;
+        const uint32_t t0 = pk_min(pk_min(pk_add(pk_min(align16(A.y, A.x), XM), p1pk), A.y), m2);
+        const uint32_t t1 = pk_min(pk_min(pk_add(pk_min(XM, align16(Bq.y, Bq.x)), p1pk), Bq.x), m2);
+        const uint32_t L0 = pk_max(pk_sub(pk_add(bytes01(cw), t0), mg), pair_mask(d, lo_g, w_g));
+        const uint32_t L1 = pk_max(pk_sub(pk_add(bytes23(cw), t1), mg), pair_mask(d + 2, lo_g, w_g));
+        if (in) {
+            cug[qd + 1] = L0;
+            cug[qd + 2] = L1;
+        }
+        __builtin_amdgcn_raw_buffer_store_b32(pack4(L0, L1), vbuf, in ? o_g + 4u * (uint32_t)lane : kDropOffset,
+                                              0, 0);
+        const uint32_t mm2 = pk_min(L0, L1);
+        return group_min<64>(in ? (int)min(mm2 & 0xffffu, mm2 >> 16) : 0x7fffffff);
+    };
+
+    auto step = [&](int i, int ti, int tc, int par) {
+        const uint64_t mt = mm[ti];
+        const int lo = meta_lo(mt), w = meta_w(mt);
+        const uint32_t o = meta_off(mt);
+        const bool act = i < len;
+        const int B = lo & ~3;
+        const int span = ((lo + w + 3) & ~3) - B;
+        const bool nar = span <= 2 * G;
+        uint32_t* prv = myrow[par ^ 1];
+        uint32_t* cur = myrow[par];
+        int m_new = m;
+        const int mode = act ? (nar ? 1 : 2) : 0;
+        const int d0 = B + 2 * l;
+        const int qd = d0 >> 1;   // dword of entries d0-2, d0-1
+        uint32_t Lm = 0;
+        if (act && nar) {
+            const uint32_t W0 = prv[qd], W1 = prv[qd + 1], W2 = prv[qd + 2];
+            const uint32_t tt = pk_min(pk_min(pk_add(pk_min(align16(W1, W0), align16(W2, W1)), p1pk), W1),
+                                       (uint32_t)(m + p2) * 0x10001u);
+            const uint32_t L = pk_sub(pk_add(bytes01(cst[tc]), tt), (uint32_t)m * 0x10001u);
+            Lm = pk_max(L, pair_mask(d0, lo, w));
+            cur[qd + 1] = Lm;
+            m_new = small_group_min<G>((int)min(Lm & 0xffffu, Lm >> 16));
+        }
+        // unconditional store; lanes past the span or off the narrow path drop it
+        __builtin_amdgcn_raw_buffer_store_b16((uint16_t)__builtin_amdgcn_perm(0u, Lm, 0x0C0C0200u), vbuf,
+                                              (act && nar && 2 * l < span) ? o + 2u * (uint32_t)l : kDropOffset,
+                                              0, 0);
+        // wide pixels whose costs were prefetched, then any others
+        uint64_t wb = __builtin_amdgcn_ballot_w64(act && !nar && l == 0);
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const int gg = wg[tc][k];
+            if (gg >= 0) {
+                const int bit = gg * G;
+                const int mw = wide_step(gg, __builtin_amdgcn_readlane(lo, bit), __builtin_amdgcn_readlane(w, bit),
+                                         (uint32_t)__builtin_amdgcn_readlane((int)o, bit),
+                                         __builtin_amdgcn_readlane(m, bit), wc[tc][k], par);
+                if (g == gg) m_new = mw;
+                wb &= ~(1ull << bit);
+            }
+        }
+        while (wb) {
+            const int bit = (int)__builtin_ctzll(wb);
+            wb &= wb - 1;
+            const int gg = bit / G;
+            const uint32_t o_g = (uint32_t)__builtin_amdgcn_readlane((int)o, bit);
+            const uint32_t cw = __builtin_amdgcn_raw_buffer_load_b32(cbuf, o_g + 4u * (uint32_t)lane, 0, 0);
+            const int mw = wide_step(gg, __builtin_amdgcn_readlane(lo, bit), __builtin_amdgcn_readlane(w, bit), o_g,
+                                     __builtin_amdgcn_readlane(m, bit), cw, par);
+            if (g == gg) m_new = mw;
+        }
+        lds_order();
+        // erase what the previous step wrote into the row read now
+        if (pmode == 1) prv[perase] = kInfPk;
+        uint64_t eb = __builtin_amdgcn_ballot_w64(pmode == 2 && l == 0);
+        while (eb) {
+            const int bit = (int)__builtin_ctzll(eb);
+            eb &= eb - 1;
+            const int gg = bit / G;
+            const int b0 = __builtin_amdgcn_readlane(pb, bit), e0 = __builtin_amdgcn_readlane(pe, bit);
+            uint32_t* prg = reinterpret_cast<uint32_t*>(rows[gg][par ^ 1]);
+            const int d = b0 + 4 * lane;
+            if (d < e0) {
+                prg[(d >> 1) + 1] = kInfPk;
+                prg[(d >> 1) + 2] = kInfPk;
+            }
+        }
+        lds_order();
+        m = m_new;
+        pmode = mode;
+        pb = B;
+        pe = B + span;
+        perase = qd + 1;
+    };
+
+    int i = 0;
+    for (; i + RM <= nmax; i += RM) {
+#pragma unroll
+        for (int u = 0; u < RM; ++u) {
+            step(i + u, u, u % PF, u & 1);
+            load_costs(u % PF, mm[(u + PF) % RM], i + u + PF);
+            next_meta(u);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < RM; ++u) {
+        if (i + u < nmax) {
+            step(i + u, u, u % PF, u & 1);
+            if (u + PF < RM) load_costs(u % PF, mm[u + PF], i + u + PF);
+        }
+    }
+}
+
+// Costs in the quad layout.  One block per 64-pixel row segment: the
+// segment's windows (written as window words with the quad offset), then
+// all quads of its pixels spread over the block's threads, one dword of
+// four costs per quad (padding slots get a cost too: 62 past D or the image).
+__global__ __launch_bounds__(kBlock) void cost_quad_kernel(SgmLaunch a) {
+    __shared__ uint64_t crs[kSeg + kMaxDisp];
+    __shared__ uint64_t cls[kSeg];
+    __shared__ uint32_t s_pre[kSeg + 1];   // quads before each pixel of the segment
+    __shared__ int s_b[kSeg];
+    __shared__ uint32_t s_q[kSeg];
+    const int W = a.w, D = a.win.max_disp;
+    const int y = blockIdx.y, x0 = blockIdx.x * kSeg;
+    const int base = x0 - (D - 1);
+    const gmem<const uint64_t>* rowl = gptr(a.census_l + (size_t)y * W);
+    const gmem<const uint64_t>* rowr = gptr(a.census_r + (size_t)y * W);
+    if (threadIdx.x < 64) {
+        const int i = (int)threadIdx.x, x = x0 + i;
+        uint32_t nq = 0;
+        if (x < W) {
+            const int p = y * W + x;
+            const int lo = gptr(a.win.lo)[p], hi = gptr(a.win.hi)[p];
+            const uint32_t off = gptr(a.win.off)[p];
+            const int w = hi - lo + 1;
+            const uint32_t q = quad_off(off, (uint32_t)p);
+            gptr(a.meta)[p] = pack_meta(q, lo, w);
+            s_b[i] = lo & ~3;
+            s_q[i] = q;
+            nq = (uint32_t)((((lo + w + 3) & ~3) - (lo & ~3)) >> 2);
+        }
+        uint32_t inc = nq;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t v = __shfl_up(inc, o, 64);
+            if (i >= o) inc += v;
+        }
+        s_pre[i + 1] = inc;
+        if (i == 0) s_pre[0] = 0;
+    }
+    for (int i = threadIdx.x; i < kSeg + D - 1; i += kBlock) {
+        const int xr = base + i;
+        crs[i] = (xr >= 0 && xr < W) ? rowr[xr] : 0ull;
+    }
+    for (int i = threadIdx.x; i < kSeg; i += kBlock) cls[i] = (x0 + i < W) ? rowl[x0 + i] : 0ull;
+    __syncthreads();
+    const uint32_t total = s_pre[kSeg];
+    gmem<uint32_t>* cost = reinterpret_cast<gmem<uint32_t>*>(gptr(a.cost));
+    for (uint32_t k = threadIdx.x; k < total; k += kBlock) {
+        int i = 0;
+#pragma unroll
+        for (int st = 32; st > 0; st >>= 1)
+            if (s_pre[i + st] <= k) i += st;
+        const int x = x0 + i;
+        const uint32_t qk = k - s_pre[i];
+        const int d = s_b[i] + 4 * (int)qk;
+        const uint64_t cl = cls[i];
+        uint32_t word = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int dd = d + b;
+            const int c = (dd < D && x - dd >= 0) ? __popcll(cl ^ crs[i + (D - 1) - dd]) : kCensusBits;
+            word |= (uint32_t)c << (8 * b);
+        }
+        cost[(s_q[i] >> 2) + qk] = word;
+    }
+}
+
+// Selection in the quad layout (same results as select_segment).  One block
+// per 64-pixel row segment, wave v taking pixels 16v .. 16v+15: a pixel whose
+// window span fits 16 slots is done by a group of 4 lanes (lane j owning the
+// quad B + 4j), each wider one by the whole wave (lane L owning B + 4L), one
+// after another.  S is summed from the path volumes a dword (four slots) per
+// direction and lane; the winner key (S << 9 | d) is a minimum over the
+// group; the pixel's S row is staged in LDS for the parabola and the
+// uncertainty walk of Eq. 9 (lane 0 of the group); each slot offers its key
+// to right pixel x-d through the segment's LDS key array, flushed with one
+// global atomicMin per touched right pixel.
+template <int NPATH>
+__global__ __launch_bounds__(kBlock) void select_quad_kernel(SgmLaunch a) {
+    __shared__ uint32_t keyR[kSeg + kMaxDisp];
+    __shared__ __attribute__((aligned(16))) uint16_t sS[kSeg][16];
+    __shared__ __attribute__((aligned(16))) uint16_t sW[kBlock / 64][kMaxDisp + 4];
+    __shared__ float s_sub[kSeg], s_var[kSeg];
+    __shared__ int16_t s_wta[kSeg];
+    const int W = a.w, D = a.win.max_disp;
+    const int y = blockIdx.y, x0 = blockIdx.x * kSeg;
+    const int base = x0 - (D - 1);
+    const int lane = (int)(threadIdx.x & 63u);
+    const int wv = (int)(threadIdx.x >> 6);
+    for (int i = threadIdx.x; i < kSeg + D - 1; i += kBlock) keyR[i] = 0xffffffffu;
+    const uint32_t cap = (uint32_t)a.vol_stride;
+    __amdgpu_buffer_rsrc_t vb[NPATH];
+#pragma unroll
+    for (int r = 0; r < NPATH; ++r) vb[r] = byte_buffer(a.vol + (size_t)r * a.vol_stride, cap);
+    __syncthreads();
+
+    // S of the quad at byte offset `at`: pairs (d, d+1) and (d+2, d+3)
+    auto sum_quad = [&](uint32_t at, uint32_t& s01, uint32_t& s23) {
+        uint32_t v[NPATH];
+#pragma unroll
+        for (int r = 0; r < NPATH; ++r) v[r] = __builtin_amdgcn_raw_buffer_load_b32(vb[r], at, 0, 0);
+        s01 = 0;
+        s23 = 0;
+#pragma unroll
+        for (int r = 0; r < NPATH; ++r) {
+            s01 = pk_add(s01, bytes01(v[r]));
+            s23 = pk_add(s23, bytes23(v[r]));
+        }
+    };
+    // winner key of one slot (S << 9 | d), or all ones outside the window
+    // (keys are below 2^20; 0x7fffffff marks a slot outside the window)
+    auto key_of = [&](uint32_t S, int d, int lo, int w) {
+        return (uint32_t)(d - lo) < (uint32_t)w ? (int)((S << 9) | (uint32_t)d) : 0x7fffffff;
+    };
+    // parabola and walk on a staged S row (index 0 = disparity B)
+    auto epilogue = [&](const uint16_t* row, int B, int lo, int w, int ds, int sb, int i) {
+        const int hi = lo + w - 1;
+        const int j0 = ds - B;
+        float sub = (float)ds;
+        if (ds > lo && ds < hi) {
+            const int sa = row[j0 - 1], sc = row[j0 + 1];
+            const int den = sa - 2 * sb + sc;
+            if (den > 0) sub = (float)ds + (float)(sa - sc) / (float)(2 * den);
+        }
+        int acc = 0, n = 0;
+        for (int j = 1; ds - j >= lo; ++j) {
+            acc += (int)row[j0 - j] - sb;
+            if (acc >= a.s_max) break;
+            ++n;
+        }
+        acc = 0;
+        for (int j = 1; ds + j <= hi; ++j) {
+            acc += (int)row[j0 + j] - sb;
+            if (acc >= a.s_max) break;
+            ++n;
+        }
+        s_wta[i] = (int16_t)ds;
+        s_sub[i] = sub;
+        s_var[i] = (float)n;
+    };
+    // right-map offers of the four slots d .. d+3 of pixel i (column x)
+    auto offer = [&](uint32_t s01, uint32_t s23, int d, int lo, int w, int x, int i) {
+        const uint32_t S[4] = {s01 & 0xffffu, s01 >> 16, s23 & 0xffffu, s23 >> 16};
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int dd = d + b;
+            if ((uint32_t)(dd - lo) < (uint32_t)w && x - dd >= 0)
+                atomicMin(&keyR[i + (D - 1) - dd], (S[b] << 9) | (uint32_t)dd);
+        }
+    };
+    auto debug_agg = [&](uint32_t s01, uint32_t s23, int d, int lo, int w, int p) {
+        if (!a.agg) return;
+        const uint32_t off = gptr(a.win.off)[p];
+        const uint32_t S[4] = {s01 & 0xffffu, s01 >> 16, s23 & 0xffffu, s23 >> 16};
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if ((uint32_t)(d + b - lo) < (uint32_t)w) gptr(a.agg)[off + (uint32_t)(d + b - lo)] = (uint16_t)S[b];
+    };
+
+    // narrow pixels: group gq of 4 lanes, pixel i = 16 wv + gq
+    const int gq = lane >> 2, jq = lane & 3;
+    const int i = 16 * wv + gq, x = x0 + i;
+    const bool in_row = x < W;
+    const int p = y * W + min(x, W - 1);
+    const uint64_t mt = gptr(a.meta)[p];
+    const int lo = meta_lo(mt), w = meta_w(mt);
+    const uint32_t q = meta_off(mt);
+    const int B = lo & ~3;
+    const int span = ((lo + w + 3) & ~3) - B;
+    const bool nar = span <= 16;
+    if (in_row && nar) {
+        const int d = B + 4 * jq;
+        uint32_t s01 = 0xffffffffu, s23 = 0xffffffffu;
+        int kb = 0x7fffffff;
+        if (4 * jq < span) {
+            sum_quad(q + 4u * (uint32_t)jq, s01, s23);
+            kb = min(min(key_of(s01 & 0xffffu, d, lo, w), key_of(s01 >> 16, d + 1, lo, w)),
+                     min(key_of(s23 & 0xffffu, d + 2, lo, w), key_of(s23 >> 16, d + 3, lo, w)));
+            *reinterpret_cast<u32x2*>(&sS[i][4 * jq]) = u32x2{s01, s23};
+            offer(s01, s23, d, lo, w, x, i);
+            debug_agg(s01, s23, d, lo, w, p);
+        }
+        kb = min(kb, __builtin_amdgcn_update_dpp(0x7fffffff, kb, 0xB1, 0xF, 0xF, true));   // quad xor 1
+        kb = min(kb, __builtin_amdgcn_update_dpp(0x7fffffff, kb, 0x4E, 0xF, 0xF, true));   // quad xor 2
+        lds_order();
+        if (jq == 0) epilogue(sS[i], B, lo, w, kb & 511, kb >> 9, i);
+    }
+    // wide pixels of this wave, one after another
+    uint64_t wbits = __builtin_amdgcn_ballot_w64(in_row && !nar && jq == 0);
+    uint16_t* row = sW[wv];
+    while (wbits) {
+        const int bit = (int)__builtin_ctzll(wbits);
+        wbits &= wbits - 1;
+        const int lo_g = __builtin_amdgcn_readlane(lo, bit), w_g = __builtin_amdgcn_readlane(w, bit);
+        const uint32_t q_g = (uint32_t)__builtin_amdgcn_readlane((int)q, bit);
+        const int ig = 16 * wv + (bit >> 2), xg = x0 + ig;
+        const int Bg = lo_g & ~3, Eg = (lo_g + w_g + 3) & ~3;
+        const int d = Bg + 4 * lane;
+        int kb = 0x7fffffff;
+        if (d < Eg) {
+            uint32_t s01, s23;
+            sum_quad(q_g + 4u * (uint32_t)lane, s01, s23);
+            kb = min(min(key_of(s01 & 0xffffu, d, lo_g, w_g), key_of(s01 >> 16, d + 1, lo_g, w_g)),
+                     min(key_of(s23 & 0xffffu, d + 2, lo_g, w_g), key_of(s23 >> 16, d + 3, lo_g, w_g)));
+            *reinterpret_cast<u32x2*>(&row[4 * lane]) = u32x2{s01, s23};
+            offer(s01, s23, d, lo_g, w_g, xg, ig);
+            debug_agg(s01, s23, d, lo_g, w_g, y * W + xg);
+        }
+        const int kw = group_min<64>(kb);
+        lds_order();
+        if (lane == 0) epilogue(row, Bg, lo_g, w_g, kw & 511, kw >> 9, ig);
+        lds_order();   // the next wide pixel rewrites the row
+    }
+    __syncthreads();
+    if (threadIdx.x < kSeg && x0 + (int)threadIdx.x < W) {
+        const int ii = (int)threadIdx.x, pp = y * W + x0 + ii;
+        gptr(a.disp_wta)[pp] = s_wta[ii];
+        gptr(a.disp_sub)[pp] = s_sub[ii];
+        gptr(a.var_meas)[pp] = s_var[ii];
+        if (a.wta_raw) gptr(a.wta_raw)[pp] = s_wta[ii];
+    }
+    for (int ii = threadIdx.x; ii < kSeg + D - 1; ii += kBlock) {
+        const int xr = base + ii;
+        const uint32_t k = keyR[ii];
+        if (xr >= 0 && xr < W && k != 0xffffffffu)
+            __hip_atomic_fetch_min(gptr(a.key_r) + (size_t)y * W + xr, k, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Debug copy of nvol quad-layout volumes (stride src_stride) into the
+// public ragged layout (entry offsets[p] + d - lo[p], stride dst_stride).
+__global__ __launch_bounds__(kBlock) void copy_quad_slots_kernel(SgmLaunch a, const uint8_t* src, size_t src_stride,
+                                                                 uint8_t* dst, size_t dst_stride, int nvol) {
+    const int n = a.w * a.h;
+    for (int p = (int)(blockIdx.x * kBlock + threadIdx.x); p < n; p += (int)(gridDim.x * kBlock)) {
+        const int lo = a.win.lo[p], w = a.win.hi[p] - lo + 1;
+        const uint32_t off = a.win.off[p];
+        const uint32_t q = quad_off(off, (uint32_t)p) + (uint32_t)(lo & 3);
+        for (int v = 0; v < nvol; ++v)
+            for (int s = 0; s < w; ++s) dst[v * dst_stride + off + s] = src[v * src_stride + q + s];
+    }
+}
+
 // ------------------------------------------------------------------ selection
 template <int NPATH>
 __device__ inline int sum_paths(const gmem<uint8_t>* const (&vols)[NPATH], uint32_t j) {
@@ -1684,9 +2206,17 @@ hipError_t launch_census_pair(const uint8_t* left, const uint8_t* right, int w, 
     return hipGetLastError();
 }
 
+size_t quad_volume_bytes(int w, int h, int D) {
+    const unsigned long long n = (unsigned long long)w * (unsigned long long)h;
+    const unsigned long long b = n * (unsigned long long)(D + 9) + 8ull;
+    return b < (1ull << 32) ? (size_t)((b + 255ull) & ~255ull) : 0;
+}
+
 hipError_t launch_sgm_cost(const SgmLaunch& a, hipStream_t s) {
     dim3 grid((a.w + kSeg - 1) / kSeg, a.h);
-    if (a.win.lo == nullptr)
+    if (a.quad)
+        cost_quad_kernel<<<grid, kBlock, 0, s>>>(a);
+    else if (a.win.lo == nullptr)
         cost_kernel<64, kWinFull><<<grid, kBlock, 0, s>>>(a);
     else
         cost_kernel<16, kWinRagged><<<grid, kBlock, 0, s>>>(a);
@@ -1724,10 +2254,37 @@ hipError_t launch_sgm_paths(const SgmLaunch& a, hipStream_t s) {
     }
     // ragged: schedule 0 every scanline through LDS rows, 1 the rows on
     // windowed registers and the rest through LDS, 2 every scanline on
-    // windowed registers, 3 every scanline on relative registers.  The LDS
-    // part takes its lanes per scanline from the tuning.
+    // windowed registers, 3 every scanline on relative registers, 4 and 5
+    // grouped scanlines (8 or 16 lanes each, quad layout).  The LDS part of
+    // schedules 0-2 takes its lanes per scanline from the tuning.
     const int g = a.ragged_group;
     const int sched = a.ragged_schedule;
+    if (a.quad) {
+        const int G = sched == 5 ? 16 : 8, NG = 64 / G;
+        GroupTasks t{};
+        t.n_dirs = a.n_paths == 4 ? 4 : 8;
+        t.strided = 1;
+        const int W = a.w, H = a.h;
+        const int ns[kNumPaths] = {H, H, W, W, W + H - 1, W + H - 1, W + H - 1, W + H - 1};
+        int task = 0;
+        t.wave_start[0] = 0;
+        for (int r = 0; r < t.n_dirs; ++r) {
+            t.n_scan[r] = ns[r];
+            t.first_task[r] = task;
+            task += ns[r];
+            t.wave_start[r + 1] = t.wave_start[r] + (ns[r] + NG - 1) / NG;
+        }
+        const unsigned nb = (unsigned)((t.wave_start[t.n_dirs] + kBlock / 64 - 1) / (kBlock / 64));
+#define EGOSGM_GRP(GG)                                                                       \
+    do {                                                                                     \
+        if (D <= 64) sgm_paths_group_kernel<GG, 64, 4><<<nb, kBlock, 0, s>>>(a, t);           \
+        else if (D <= 128) sgm_paths_group_kernel<GG, 128, 4><<<nb, kBlock, 0, s>>>(a, t);    \
+        else sgm_paths_group_kernel<GG, 256, 4><<<nb, kBlock, 0, s>>>(a, t);                  \
+    } while (0)
+        if (G == 16) EGOSGM_GRP(16); else EGOSGM_GRP(8);
+#undef EGOSGM_GRP
+        return hipGetLastError();
+    }
     if (sched == 3) {
         const unsigned nb = blocks(n_tasks, 64);
         if (D <= 64) sgm_paths_reg_kernel<1, 4><<<nb, kBlock, 0, s>>>(a, n_tasks);
@@ -1767,7 +2324,10 @@ hipError_t launch_sgm_select(const SgmLaunch& a, hipStream_t s) {
         if (a.n_paths == 4) sgm_select_kernel<GG, KK, FF, 4><<<grid, kBlock, 0, s>>>(a); \
         else sgm_select_kernel<GG, KK, FF, 8><<<grid, kBlock, 0, s>>>(a);               \
     } while (0)
-    if (full) {
+    if (a.quad) {
+        if (a.n_paths == 4) select_quad_kernel<4><<<grid, kBlock, 0, s>>>(a);
+        else select_quad_kernel<8><<<grid, kBlock, 0, s>>>(a);
+    } else if (full) {
         if (D <= 64) EGOSGM_SEL(64, 1, kWinFull);
         else if (D <= 128) EGOSGM_SEL(64, 2, kWinFull);
         else EGOSGM_SEL(64, 4, kWinFull);
@@ -1789,6 +2349,12 @@ hipError_t launch_copy_slots(const SgmLaunch& a, const uint8_t* src, uint8_t* ds
         copy_slots_kernel<kWinFull><<<1024, kBlock, 0, s>>>(a, src, dst);
     else
         copy_slots_kernel<kWinRagged><<<1024, kBlock, 0, s>>>(a, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_quad_slots(const SgmLaunch& a, const uint8_t* src, size_t src_stride, uint8_t* dst,
+                                  size_t dst_stride, int nvol, hipStream_t s) {
+    copy_quad_slots_kernel<<<1024, kBlock, 0, s>>>(a, src, src_stride, dst, dst_stride, nvol);
     return hipGetLastError();
 }
 

@@ -104,7 +104,7 @@ def _random_windows(w, h, D, seed, rmax=6, frac_full=0.1, kind="random"):
     return d, p
 
 
-@pytest.mark.parametrize("sched", [0, 1, 2, 3])
+@pytest.mark.parametrize("sched", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("w,h,D,seed,kind,rmax", [
     (37, 19, 16, 1, "random", 6), (64, 20, 64, 2, "random", 6), (91, 27, 128, 3, "random", 6),
     (33, 5, 256, 4, "random", 6), (150, 23, 128, 5, "smooth", 6), (97, 17, 256, 6, "wide", 60),
@@ -129,11 +129,11 @@ def test_sgm_reduced_ragged(w, h, D, seed, kind, rmax, sched):
     _check_sgm(g, o, int(wo[2][-1]))
 
 
-@pytest.mark.parametrize("ragged", [False, True])
+@pytest.mark.parametrize("ragged,sched", [(False, 1), (True, 1), (True, 4), (True, 5)])
 @pytest.mark.parametrize("D", [64, 100, 128])
-def test_four_path_variant(ragged, D):
+def test_four_path_variant(ragged, sched, D):
     """n_paths = 4: directions 0-3 only (path volumes 0-3 and S bit-exact)."""
-    _say("4 paths, ragged" if ragged else "4 paths, full", D)
+    _say("4 paths, ragged" if ragged else "4 paths, full", D, "schedule", sched)
     w, h = 91, 27
     left, right = _random_pair(w, h, seed=D + 3, max_shift=min(D - 1, 30))
     prm = eg.MatchParams(max_disp=D, p1=10, p2=120, s_max=40, lr_tol=1, n_paths=4)
@@ -141,7 +141,11 @@ def test_four_path_variant(ragged, D):
         d, p = _random_windows(w, h, D, seed=D + 4, kind="smooth")
         wo = orc.windows(d, p, D, r_min=0, r_max=12)
         lo, hi, off = (_gpu(wo[0].reshape(h, w)), _gpu(wo[1].reshape(h, w)), _gpu(wo[2].view(np.int32)))
-        g = eg.sgm_reduced(_gpu(left), _gpu(right), lo, hi, off, prm, debug=True)
+        eg.set_tuning(ragged_schedule=sched)
+        try:
+            g = eg.sgm_reduced(_gpu(left), _gpu(right), lo, hi, off, prm, debug=True)
+        finally:
+            eg.set_tuning(**eg.DEFAULT_TUNING)
     else:
         wo = None
         g = eg.sgm_full(_gpu(left), _gpu(right), prm, debug=True)
@@ -158,20 +162,26 @@ def test_four_path_variant(ragged, D):
         assert np.array_equal(paths[k, :total].astype(np.int32), o["paths"][k]), f"path {k}"
 
 
+@pytest.mark.parametrize("sched", [1, 4])
 @pytest.mark.parametrize("s_max", [0, 7, 80, 600])
 @pytest.mark.parametrize("rmax,D", [(7, 64), (12, 128), (40, 128)])
-def test_selection_walk_every_pixel(s_max, rmax, D):
+def test_selection_walk_every_pixel(s_max, rmax, D, sched):
     """Left-right check off, so the uncertainty count and subpixel of every
     pixel are compared; windows up to 15 slots take the parallel walk, wider
-    ones the serial one."""
-    _say("selection walk, s_max", s_max, "rmax", rmax, "D", D)
+    ones the serial one (schedule 1); schedule 4's selection takes windows
+    whose quad span fits 16 slots in 4-lane groups, wider ones by the wave."""
+    _say("selection walk, s_max", s_max, "rmax", rmax, "D", D, "schedule", sched)
     w, h = 83, 21
     left, right = _random_pair(w, h, seed=s_max + rmax, max_shift=min(D - 1, 30))
     d, p = _random_windows(w, h, D, seed=rmax + 5, rmax=rmax, kind="smooth", frac_full=0.05)
     wo = orc.windows(d, p, D, r_min=0, r_max=rmax)
     lo, hi, off = (_gpu(wo[0].reshape(h, w)), _gpu(wo[1].reshape(h, w)), _gpu(wo[2].view(np.int32)))
     prm = eg.MatchParams(max_disp=D, p1=10, p2=120, s_max=s_max, lr_tol=-1)
-    g = eg.sgm_reduced(_gpu(left), _gpu(right), lo, hi, off, prm)
+    eg.set_tuning(ragged_schedule=sched)
+    try:
+        g = eg.sgm_reduced(_gpu(left), _gpu(right), lo, hi, off, prm)
+    finally:
+        eg.set_tuning(**eg.DEFAULT_TUNING)
     o = orc.sgm(left, right, D, p1=10, p2=120, s_max=s_max, lr_tol=-1, windows=wo)
     assert np.array_equal(_np(g["disp_wta"]), o["disp_wta"])
     assert np.array_equal(_np(g["var_meas"]).astype(np.float64), o["var_meas"])
@@ -401,7 +411,7 @@ def test_tuning_never_changes_results(D):
     prm = eg.MatchParams(max_disp=D)
     try:
         # wide_offsets = 1 runs the 64-bit addressing that images of 2^27 pixels take
-        for fg, rg, pr, wo_ in itertools.product((16, 32, 64), (16, 32, 64), (0, 1, 2, 3), (0, 1)):
+        for fg, rg, pr, wo_ in itertools.product((16, 32, 64), (16, 32, 64), (0, 1, 2, 3, 4, 5), (0, 1)):
             eg.set_tuning(fg, rg, pr, wide_offsets=wo_)
             a = eg.sgm_full(L, R, prm)
             b = eg.sgm_reduced(L, R, lo, hi, off, prm)
