@@ -166,6 +166,21 @@ int sgm_windows_from_prediction(const float* d_pred, const float* p_pred, int w,
                                 int max_disp, int16_t* lo, int16_t* hi, uint32_t* offsets,
                                 void* workspace, size_t workspace_bytes, void* stream);
 
+/* sgm_windows_from_prediction without a workspace, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, rules and results; the scan's per-chunk
+ * totals live in a fixed device array of the library instead, one per GPU
+ * (the current device at the call), held until the process ends.  Limit:
+ * h * ceil(w / 256) <= EGOSGM_NOALLOC_WINDOW_CHUNKS (e.g. 4096 x 4096), else
+ * EGOSGM_EUNSUPPORTED and nothing is enqueued.  The call allocates nothing.
+ * Calls that overlap on one GPU (other streams, other threads) share that
+ * array and race: order them, e.g. on one stream. */
+#define EGOSGM_NOALLOC_WINDOW_CHUNKS 65536
+int sgm_windows_from_prediction_noalloc(const float* d_pred, const float* p_pred, int w, int h,
+                                        float k_sigma, int r_fixed, int r_min, int r_max,
+                                        int max_disp, int16_t* lo, int16_t* hi,
+                                        uint32_t* offsets, void* stream);
+
 /* Reduced-range semi-global matching (Sec. 2.3): sgm_full restricted to the
  * per-pixel windows [lo[p], hi[p]]; predecessor entries outside the
  * predecessor's window count as +infinity and m is the minimum over that

@@ -59,6 +59,34 @@ hipError_t timed(int stage, hipStream_t s, F&& fn) {
     return e;
 }
 
+// Scratch of sgm_windows_from_prediction_noalloc: the per-chunk totals of
+// the offsets scan (one uint32 per kWindowChunk pixels of a row), in a
+// file-scope device array instead of a caller workspace.  Every GPU the
+// library runs on holds its own copy until the process ends.  In host code
+// `scratch` only names the symbol: its device address on each GPU comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) uint32_t scratch[EGOSGM_NOALLOC_WINDOW_CHUNKS];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t window_scratch(uint32_t** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<uint32_t*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
 // Launch-shape choices (set by egosgm_set_tuning; read at every launch).
 egosgm_tuning g_tuning = {64, 32, 1, 16, 0};
 std::mutex g_tuning_mu;
@@ -561,6 +589,27 @@ size_t egosgm_windows_workspace_bytes(int w, int h) {
     if (w <= 0 || h <= 0) return 0;
     const size_t chunks_per_row = ((size_t)w + kWindowChunk - 1) / kWindowChunk;
     return align_up((size_t)h * chunks_per_row * sizeof(uint32_t));
+}
+
+int sgm_windows_from_prediction_noalloc(const float* d_pred, const float* p_pred, int w, int h,
+                                        float k_sigma, int r_fixed, int r_min, int r_max, int max_disp,
+                                        int16_t* lo, int16_t* hi, uint32_t* offsets, void* stream) {
+    if (!d_pred || !lo || !hi || !offsets) return EGOSGM_EINVAL;
+    if (r_fixed < 0 && !p_pred) return EGOSGM_EINVAL;
+    if (r_min < 0 || r_max < r_min || !(k_sigma >= 0.0f)) return EGOSGM_EINVAL;
+    const int rc = check_shape(w, h, max_disp);
+    if (rc) return rc;
+    const size_t chunks = (size_t)h * (((size_t)w + kWindowChunk - 1) / kWindowChunk);
+    if (chunks > (size_t)EGOSGM_NOALLOC_WINDOW_CHUNKS) return EGOSGM_EUNSUPPORTED;
+    uint32_t* totals = nullptr;
+    if (window_scratch(&totals) != hipSuccess) return EGOSGM_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return timed(EGOSGM_STAGE_WINDOWS, s, [&] {
+               return launch_windows(d_pred, p_pred, w, h, k_sigma, r_fixed, r_min, r_max,
+                                     max_disp, lo, hi, offsets, totals, s);
+           }) == hipSuccess
+               ? EGOSGM_OK
+               : EGOSGM_EDEVICE;
 }
 
 int sgm_windows_from_prediction(const float* d_pred, const float* p_pred, int w, int h,

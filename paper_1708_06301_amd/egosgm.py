@@ -30,6 +30,8 @@ _SIGS = {
     "egosgm_windows_workspace_bytes": ([_i, _i], _sz),
     "sgm_windows_from_prediction": ([_vp, _vp, _i, _i, _f, _i, _i, _i, _i, _vp, _vp, _vp, _vp,
                                      _sz, _vp], _i),
+    "sgm_windows_from_prediction_noalloc": ([_vp, _vp, _i, _i, _f, _i, _i, _i, _i, _vp, _vp, _vp,
+                                             _vp], _i),
     "sgm_reduced": ([_vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                      _sz, _vp], _i),
     "egosgm_warp_matrix": ([_vp, _vp, _d, _d, _d, _d, _vp], _i),
@@ -301,6 +303,29 @@ def windows_from_prediction(d_pred: torch.Tensor, p_pred: torch.Tensor | None, m
                                            r_min, r_max, max_disp, _ptr(lo), _ptr(hi),
                                            _ptr(off), _ptr(ws), nbytes, _stream())
     _check(rc, "sgm_windows_from_prediction")
+    return lo, hi, off
+
+
+def windows_from_prediction_noalloc(d_pred: torch.Tensor, p_pred: torch.Tensor | None, max_disp: int,
+                                    r_fixed: int = -1, r_min: int = 0, r_max: int = 256,
+                                    k_sigma: float = 3.0, out=None):
+    """windows_from_prediction through the entry point that allocates
+    nothing (its scratch is a fixed device array of the library); `out`
+    (lo, hi, offsets) must be given where the caller cannot allocate."""
+    _need(d_pred, torch.float32, name="d_pred")
+    if p_pred is not None:
+        _need(p_pred, torch.float32, d_pred.numel(), name="p_pred")
+    h, w = d_pred.shape
+    if out is None:
+        dev = d_pred.device
+        out = (torch.empty((h, w), dtype=torch.int16, device=dev),
+               torch.empty((h, w), dtype=torch.int16, device=dev),
+               torch.empty(h * w + 1, dtype=torch.int32, device=dev))
+    lo, hi, off = out
+    rc = lib().sgm_windows_from_prediction_noalloc(_ptr(d_pred), _ptr(p_pred), w, h, k_sigma, r_fixed,
+                                                   r_min, r_max, max_disp, _ptr(lo), _ptr(hi),
+                                                   _ptr(off), _stream())
+    _check(rc, "sgm_windows_from_prediction_noalloc")
     return lo, hi, off
 
 

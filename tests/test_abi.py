@@ -83,6 +83,16 @@ def test_windows_warp_kalman_validation():
                                            FAKE, FAKE, 1 << 20, None) == -1
     assert lib.sgm_windows_from_prediction(FAKE, FAKE, 64, 32, 3.0, -1, 0, 8, 64, FAKE, FAKE,
                                            FAKE, FAKE, 4, None) == -2
+    # the allocation-free form: same checks, and sizes beyond its fixed scratch
+    assert lib.sgm_windows_from_prediction_noalloc(FAKE, None, 64, 32, 3.0, -1, 0, 8, 64, FAKE, FAKE,
+                                                   FAKE, None) == -1
+    assert lib.sgm_windows_from_prediction_noalloc(FAKE, FAKE, 64, 32, 3.0, -1, 9, 8, 64, FAKE, FAKE,
+                                                   FAKE, None) == -1
+    assert lib.sgm_windows_from_prediction_noalloc(FAKE, FAKE, 0, 32, 3.0, -1, 0, 8, 64, FAKE, FAKE,
+                                                   FAKE, None) == -1
+    # 257 x 32769: 2 chunks per row, 65538 chunks > 65536
+    assert lib.sgm_windows_from_prediction_noalloc(FAKE, FAKE, 257, 32769, 3.0, 4, 0, 8, 64, FAKE, FAKE,
+                                                   FAKE, None) == -4
     R = (C.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1)
     t = (C.c_double * 3)(0, 0, -1)
     assert lib.warp_disparity(FAKE, FAKE, 64, 32, R, t, 700.0, 32.0, 16.0, 0.54, 0.0, FAKE, FAKE,
