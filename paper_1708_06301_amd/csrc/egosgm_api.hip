@@ -182,7 +182,7 @@ int run_sgm(const uint8_t* left, const uint8_t* right, int w, int h, int pitch, 
     // offsets would not fit 32 bits the rows-on-registers schedule runs instead
     a.quad = 0;
     if (win.lo != nullptr && a.ragged_schedule >= 4) {
-        if (L.vol_stride_q != 0) a.quad = 1;
+        if (L.vol_stride_q != 0) a.quad = a.ragged_schedule == 5 ? 16 : 8;
         else a.ragged_schedule = 1;
     }
     a.vol_stride = a.quad ? L.vol_stride_q : L.vol_stride;

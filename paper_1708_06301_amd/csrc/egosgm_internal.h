@@ -46,7 +46,8 @@ struct SgmLaunch {
     int ragged_schedule;     // 0: all scanlines via LDS, 1: rows on packed registers, 2: all packed,
                              // 3: relative registers, 4/5: grouped scanlines (8/16 lanes, quad layout)
     int wide_offsets;        // 1: LDS scanlines keep 64-bit addresses even where 32-bit offsets fit
-    int quad;                // ragged windows in the quad slot layout (grouped kernels, schedules 4-5)
+    int quad;                // ragged windows in the frame slot layout of the grouped kernels
+                             // (schedules 4, 5): lanes per scanline G (frames of 2G slots), or 0
     uint8_t* cost;           // matching cost per search slot
     uint32_t* key_r;         // w*h right-map keys (S << 9 | d), cleared by the census pass
     uint64_t* meta;          // w*h packed windows (offset | lo << 32 | width << 48), written by

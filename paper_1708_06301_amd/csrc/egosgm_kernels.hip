@@ -1094,14 +1094,30 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_ragged_kernel(SgmLaunch a, i
 }
 
 // ------------------------------------------------------------------ grouped scanlines
-// Quad slot layout (ragged windows on the grouped kernels).  Pixel p owns
-// the slots of disparities B(p) .. E(p)-1, B = lo & ~3, E = (lo + w + 3) & ~3,
-// from byte offset q(p) = (off(p) + 9p + 3) & ~3 of each volume (costs and
-// path costs).  q(p) is a multiple of 4 and q(p+1) >= q(p) + E - B (since
-// E - B <= w + 6), so a lane reads and writes whole aligned pairs or quads
-// of slots; the slots of [B, E) outside the window are padding, never read
-// as results.  A volume needs at most w*h*(D+9) + 8 bytes.
-__device__ inline uint32_t quad_off(uint32_t off, uint32_t p) { return (off + 9u * p + 3u) & ~3u; }
+// Frame slot layout (ragged windows on the grouped kernels, frames of F
+// slots).  Pixel p owns the slots of disparities B(p) .. B(p) + S(p) - 1
+// from byte offset q(p) = (off(p) + (F + 3) p + 3) & ~3 of each volume
+// (costs and path costs), where B = lo & ~3, E = (lo + w + 3) & ~3 and S = F
+// when E - B <= F (a narrow window: one frame), else S = E - B.  q(p) is a
+// multiple of 4 and q(p+1) - q(p) >= w + F >= S (E - B <= w + 6), so a lane
+// reads and writes whole aligned pairs or quads of slots.  Slots of [B, B+S)
+// outside the window are padding: their cost byte is the marker 255 (a real
+// cost is at most 62), which the path kernels turn into +infinity, and their
+// path costs are never read as results.  A volume needs at most
+// w*h*(D+F+3) + 64 bytes.
+constexpr uint32_t kPadCost = 255;
+__device__ inline uint32_t frame_off(uint32_t off, uint32_t p, uint32_t F) {
+    return (off + (F + 3u) * p + 3u) & ~3u;
+}
+// Costs of two slots (bytes b0 b1 of v, or b2 b3) as a packed pair, with the
+// padding marker 255 raised to 255 + 0x4000: a slot carrying it stays above
+// any in-window path cost + P2 (< 0x4000) and so acts as +infinity, and
+// nothing overflows 16 bits (0x40ff + P2 + P1 < 0x8000).
+__device__ inline uint32_t pad_inf(uint32_t c) {
+    const u16x2 v = as_pk(c);
+    const u16x2 one = __builtin_elementwise_sub_sat(v, u16x2{254, 254});
+    return as_u32(v + (one << u16x2{14, 14}));
+}
 
 // bytes b0 b1 of v -> (b0 | b1 << 16), bytes b2 b3 -> (b2 | b3 << 16)
 __device__ inline uint32_t bytes01(uint32_t v) { return __builtin_amdgcn_perm(0u, v, 0x0C010C00u); }
@@ -1143,29 +1159,62 @@ struct GroupTasks {
     int wave_start[kNumPaths + 1];
 };
 
-// Grouped scanline kernel (ragged windows, quad layout).  A wave walks NG
-// scanlines of one direction at once, lane group g (G lanes) owning
-// scanline g.  Each scanline keeps its previous pixel's path costs in a
-// ping-pong pair of LDS rows indexed by absolute disparity (entry d + 2;
-// +infinity outside the written window, erased after use), as packed u16
-// pairs.  A step of a pixel whose window span fits 2G slots ("narrow") is
-// done by its own group, lane l owning slots B + 2l and B + 2l + 1: the d-1,
-// d, d+1 predecessors are three aligned dword reads and two alignbits.  A
-// pixel with a wider span ("wide": at the sizes used here, the pixels that
-// fall back to the full range) is done by the whole wave, lane L owning the
-// quad B + 4L .. B + 4L + 3, one wide pixel after another.  Window words
-// are prefetched 2*PF steps ahead, narrow costs PF steps ahead, and the
-// costs of the first NW wide pixels of a step PF steps ahead, all into ring
-// slots named at compile time.  A zero predecessor over the first pixel's
+// Raw-buffer offset past any volume: loads there return zero and stores
+// are dropped, for every access width (volumes stay below it).
+constexpr uint32_t kDropWide = 0xffffff00u;
+
+// Loads N dwords at byte offset `at` with the widest buffer loads.
+template <int N>
+__device__ inline void load_dwords(__amdgpu_buffer_rsrc_t buf, uint32_t at, uint32_t (&v)[N]) {
+    if constexpr (N == 1) {
+        v[0] = __builtin_amdgcn_raw_buffer_load_b32(buf, at, 0, 0);
+    } else if constexpr (N == 2) {
+        const u32x2 t = __builtin_amdgcn_raw_buffer_load_b64(buf, at, 0, 0);
+        v[0] = t.x;
+        v[1] = t.y;
+    } else {
+#pragma unroll
+        for (int k = 0; k < N / 4; ++k) {
+            const u32x4 t = __builtin_amdgcn_raw_buffer_load_b128(buf, at + 16u * k, 0, 0);
+            v[4 * k] = t.x;
+            v[4 * k + 1] = t.y;
+            v[4 * k + 2] = t.z;
+            v[4 * k + 3] = t.w;
+        }
+    }
+}
+
+// Grouped scanline kernel (ragged windows, frame layout with F = 2G).  A
+// wave walks NG = 64/G scanlines of one direction at once, lane group g (G
+// lanes) owning scanline g.  Each scanline keeps its previous pixel's path
+// costs in a ping-pong pair of LDS rows indexed by absolute disparity
+// (entry d + 2), as packed u16 pairs; every entry outside what the last
+// step wrote is +infinity (a step erases the row it has read).
+//  - A narrow pixel (window span <= F slots) is one step of its own group:
+//    lane l owns slots B + 2l, B + 2l + 1 of the pixel's frame; the d-1, d,
+//    d+1 predecessors are three aligned dword reads and two alignbits, and
+//    padding slots carry +infinity from their cost marker, so no window
+//    mask is needed.  The group minimum is a DPP reduction.
+//  - A wide pixel (a longer span: at the sizes used here the pixels that
+//    fall back to the full range) is done by the whole wave, lane L owning
+//    the quad B + 4L .. B + 4L + 3, one wide pixel after another.  Its costs
+//    were prefetched by its own group (DMAX/G bytes per lane, a dropped load
+//    when narrow) and are handed to the wave through LDS.
+// Every memory operation of a step is issued unconditionally (out-of-range
+// offsets drop unused loads and stores), so the waits before a use leave
+// the later prefetches in flight.  Window words are prefetched 2*PF steps
+// ahead, costs PF steps ahead.  A zero predecessor over the first pixel's
 // window makes the first step L = C.
 template <int G, int DMAX, int PF>
 __global__ __launch_bounds__(kBlock) void sgm_paths_group_kernel(SgmLaunch a, GroupTasks t) {
     constexpr int NG = 64 / G;
+    constexpr int F = 2 * G;
     constexpr int ROW = DMAX + 2 * G + 8;
     constexpr int RM = 2 * PF;
-    constexpr int NW = 2;
-    static_assert(ROW % 4 == 0, "rows start 8-byte aligned");
+    constexpr int WV = DMAX / G / 4;   // dwords of a wide pixel's costs per lane of its group
+    static_assert(ROW % 4 == 0 && WV >= 1 && (WV <= 2 || WV % 4 == 0), "shapes");
     __shared__ __attribute__((aligned(16))) uint16_t rows_all[kBlock / 64][NG][2][ROW];
+    __shared__ __attribute__((aligned(16))) uint32_t stage_all[kBlock / 64][DMAX / 4];
     const int lane = (int)(threadIdx.x & 63u);
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int gw = (int)blockIdx.x * (kBlock / 64) + wv;
@@ -1194,6 +1243,7 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_group_kernel(SgmLaunch a, Gr
     const int p2 = a.p2;
 
     uint16_t (*rows)[2][ROW] = rows_all[wv];
+    uint32_t* stage = stage_all[wv];
     uint32_t* myrow[2] = {reinterpret_cast<uint32_t*>(rows[g][0]), reinterpret_cast<uint32_t*>(rows[g][1])};
 
     // window words of steps 0 .. RM-1, then one RM steps ahead per step
@@ -1207,26 +1257,14 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_group_kernel(SgmLaunch a, Gr
 #pragma unroll
     for (int k = 0; k < RM; ++k) next_meta(k);
 
-    uint32_t cst[PF];          // narrow: this lane's two cost bytes
-    uint32_t wc[PF][NW];       // wide: this lane's four cost bytes of the k-th prefetched wide pixel
-    int wg[PF][NW];            // wide: group of that pixel (wave-uniform), -1 none
-    // Costs of step `i` (window word mw) into ring slot `s`.  Every load is
-    // issued unconditionally (a step without wide pixels loads offset 0), so
-    // the number of memory operations between a load and its use is fixed
-    // and the waits before a use leave the later prefetches in flight.
+    uint32_t cst[PF];       // narrow: this lane's two cost bytes
+    uint32_t wcs[PF][WV];   // wide: this lane's share of its group's pixel's costs
     auto load_costs = [&](int s, uint64_t mw, int i) {
-        cst[s] = __builtin_amdgcn_raw_buffer_load_b16(cbuf, meta_off(mw) + 2u * (uint32_t)l, 0, 0);
+        const uint32_t o = meta_off(mw);
         const int lo = meta_lo(mw), w = meta_w(mw);
-        const bool wide = i < len && ((lo + w + 3) & ~3) - (lo & ~3) > 2 * G;
-        uint64_t b = __builtin_amdgcn_ballot_w64(wide && l == 0);
-#pragma unroll
-        for (int k = 0; k < NW; ++k) {
-            const int bit = b ? (int)__builtin_ctzll(b) : -1;
-            b &= b - 1;
-            const uint32_t og = bit >= 0 ? (uint32_t)__builtin_amdgcn_readlane((int)meta_off(mw), bit) : 0u;
-            wc[s][k] = __builtin_amdgcn_raw_buffer_load_b32(cbuf, og + 4u * (uint32_t)lane, 0, 0);
-            wg[s][k] = bit >= 0 ? bit / G : -1;
-        }
+        const bool wide = i < len && ((lo + w + 3) & ~3) - (lo & ~3) > F;
+        cst[s] = __builtin_amdgcn_raw_buffer_load_b16(cbuf, o + 2u * (uint32_t)l, 0, 0);
+        load_dwords<WV>(cbuf, wide ? o + 4u * WV * (uint32_t)l : kDropWide, wcs[s]);
     };
 #pragma unroll
     for (int k = 0; k < PF; ++k) load_costs(k, mm[k], k);
@@ -1250,34 +1288,6 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_group_kernel(SgmLaunch a, Gr
     lds_order();
     int m = 0;
 
-    // One wide pixel (group gg's window [lo_g, lo_g + w_g) at quad offset
-    // o_g, predecessor minimum m_g, this lane's cost dword cw) by the whole
-    // wave; returns the new minimum (wave-uniform).
-    auto wide_step = [&](int gg, int lo_g, int w_g, uint32_t o_g, int m_g, uint32_t cw, int par) {
-        const int Bw = lo_g & ~3, Ew = (lo_g + w_g + 3) & ~3;
-        const uint32_t* prg = reinterpret_cast<const uint32_t*>(rows[gg][par ^ 1]);
-        uint32_t* cug = reinterpret_cast<uint32_t*>(rows[gg][par]);
-        const int d = Bw + 4 * lane;
-        const bool in = d < Ew;
-        const int qd = in ? d >> 1 : 0;   // even: 8-byte aligned
-        const u32x2 A = *reinterpret_cast<const u32x2*>(prg + qd);
-        const u32x2 Bq = *reinterpret_cast<const u32x2*>(prg + qd + 2);
-        const uint32_t XM = align16(Bq.x, A.y);
-        const uint32_t m2 = (uint32_t)(m_g + p2) * 0x10001u, mg = (uint32_t)m_g * 0x10001u;
-        const uint32_t t0 = pk_min(pk_min(pk_add(pk_min(align16(A.y, A.x), XM), p1pk), A.y), m2);
-        const uint32_t t1 = pk_min(pk_min(pk_add(pk_min(XM, align16(Bq.y, Bq.x)), p1pk), Bq.x), m2);
-        const uint32_t L0 = pk_max(pk_sub(pk_add(bytes01(cw), t0), mg), pair_mask(d, lo_g, w_g));
-        const uint32_t L1 = pk_max(pk_sub(pk_add(bytes23(cw), t1), mg), pair_mask(d + 2, lo_g, w_g));
-        if (in) {
-            cug[qd + 1] = L0;
-            cug[qd + 2] = L1;
-        }
-        __builtin_amdgcn_raw_buffer_store_b32(pack4(L0, L1), vbuf, in ? o_g + 4u * (uint32_t)lane : kDropOffset,
-                                              0, 0);
-        const uint32_t mm2 = pk_min(L0, L1);
-        return group_min<64>(in ? (int)min(mm2 & 0xffffu, mm2 >> 16) : 0x7fffffff);
-    };
-
     auto step = [&](int i, int ti, int tc, int par) {
         const uint64_t mt = mm[ti];
         const int lo = meta_lo(mt), w = meta_w(mt);
@@ -1285,70 +1295,95 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_group_kernel(SgmLaunch a, Gr
         const bool act = i < len;
         const int B = lo & ~3;
         const int span = ((lo + w + 3) & ~3) - B;
-        const bool nar = span <= 2 * G;
+        const bool nar = span <= F;
         uint32_t* prv = myrow[par ^ 1];
         uint32_t* cur = myrow[par];
         int m_new = m;
-        const int mode = act ? (nar ? 1 : 2) : 0;
-        const int d0 = B + 2 * l;
-        const int qd = d0 >> 1;   // dword of entries d0-2, d0-1
+        const int qd = (B >> 1) + l;   // dword of entries B + 2l - 2, B + 2l - 1
         uint32_t Lm = 0;
         if (act && nar) {
             const uint32_t W0 = prv[qd], W1 = prv[qd + 1], W2 = prv[qd + 2];
             const uint32_t tt = pk_min(pk_min(pk_add(pk_min(align16(W1, W0), align16(W2, W1)), p1pk), W1),
                                        (uint32_t)(m + p2) * 0x10001u);
-            const uint32_t L = pk_sub(pk_add(bytes01(cst[tc]), tt), (uint32_t)m * 0x10001u);
-            Lm = pk_max(L, pair_mask(d0, lo, w));
+            Lm = pk_sub(pk_add(pad_inf(bytes01(cst[tc])), tt), (uint32_t)m * 0x10001u);
             cur[qd + 1] = Lm;
             m_new = small_group_min<G>((int)min(Lm & 0xffffu, Lm >> 16));
         }
-        // unconditional store; lanes past the span or off the narrow path drop it
         __builtin_amdgcn_raw_buffer_store_b16((uint16_t)__builtin_amdgcn_perm(0u, Lm, 0x0C0C0200u), vbuf,
-                                              (act && nar && 2 * l < span) ? o + 2u * (uint32_t)l : kDropOffset,
-                                              0, 0);
-        // wide pixels whose costs were prefetched, then any others
+                                              (act && nar) ? o + 2u * (uint32_t)l : kDropWide, 0, 0);
+        // wide pixels, one after another by the whole wave
         uint64_t wb = __builtin_amdgcn_ballot_w64(act && !nar && l == 0);
-#pragma unroll
-        for (int k = 0; k < NW; ++k) {
-            const int gg = wg[tc][k];
-            if (gg >= 0) {
-                const int bit = gg * G;
-                const int mw = wide_step(gg, __builtin_amdgcn_readlane(lo, bit), __builtin_amdgcn_readlane(w, bit),
-                                         (uint32_t)__builtin_amdgcn_readlane((int)o, bit),
-                                         __builtin_amdgcn_readlane(m, bit), wc[tc][k], par);
-                if (g == gg) m_new = mw;
-                wb &= ~(1ull << bit);
-            }
-        }
         while (wb) {
             const int bit = (int)__builtin_ctzll(wb);
             wb &= wb - 1;
             const int gg = bit / G;
+            // group gg hands its prefetched costs to the wave
+            if (g == gg) {
+#pragma unroll
+                for (int v = 0; v < WV; ++v) stage[WV * l + v] = wcs[tc][v];
+            }
+            lds_order();
+            const uint32_t cw = stage[lane < DMAX / 4 ? lane : 0];
+            lds_order();
+            const int lo_g = __builtin_amdgcn_readlane(lo, bit), w_g = __builtin_amdgcn_readlane(w, bit);
             const uint32_t o_g = (uint32_t)__builtin_amdgcn_readlane((int)o, bit);
-            const uint32_t cw = __builtin_amdgcn_raw_buffer_load_b32(cbuf, o_g + 4u * (uint32_t)lane, 0, 0);
-            const int mw = wide_step(gg, __builtin_amdgcn_readlane(lo, bit), __builtin_amdgcn_readlane(w, bit), o_g,
-                                     __builtin_amdgcn_readlane(m, bit), cw, par);
+            const int m_g = __builtin_amdgcn_readlane(m, bit);
+            const int pm_g = __builtin_amdgcn_readlane(pmode, bit);
+            const int Bw = lo_g & ~3, Ew = (lo_g + w_g + 3) & ~3;
+            const uint32_t* prg = reinterpret_cast<const uint32_t*>(rows[gg][par ^ 1]);
+            uint32_t* cug = reinterpret_cast<uint32_t*>(rows[gg][par]);
+            const int d = Bw + 4 * lane;
+            const bool in = d < Ew;
+            const int qw = in ? d >> 1 : 0;   // even: 8-byte aligned
+            const u32x2 A = *reinterpret_cast<const u32x2*>(prg + qw);
+            const u32x2 Bq = *reinterpret_cast<const u32x2*>(prg + qw + 2);
+            const uint32_t XM = align16(Bq.x, A.y);
+            const uint32_t m2 = (uint32_t)(m_g + p2) * 0x10001u, mg = (uint32_t)m_g * 0x10001u;
+            const uint32_t t0 = pk_min(pk_min(pk_add(pk_min(align16(A.y, A.x), XM), p1pk), A.y), m2);
+            const uint32_t t1 = pk_min(pk_min(pk_add(pk_min(XM, align16(Bq.y, Bq.x)), p1pk), Bq.x), m2);
+            const uint32_t L0 = pk_sub(pk_add(pad_inf(bytes01(cw)), t0), mg);
+            const uint32_t L1 = pk_sub(pk_add(pad_inf(bytes23(cw)), t1), mg);
+            if (pm_g == 2) {
+                // the previous step of this scanline was wide too: erase its span
+                // here (every lane's reads above are issued before these writes)
+                const int pb_g = __builtin_amdgcn_readlane(pb, bit), pe_g = __builtin_amdgcn_readlane(pe, bit);
+                const int de = pb_g + 4 * lane;
+                if (de < pe_g) {
+                    uint32_t* pw = reinterpret_cast<uint32_t*>(rows[gg][par ^ 1]);
+                    pw[(de >> 1) + 1] = kInfPk;
+                    pw[(de >> 1) + 2] = kInfPk;
+                }
+            }
+            if (in) {
+                cug[qw + 1] = L0;
+                cug[qw + 2] = L1;
+            }
+            __builtin_amdgcn_raw_buffer_store_b32(pack4(L0, L1), vbuf, in ? o_g + 4u * (uint32_t)lane : kDropWide,
+                                                  0, 0);
+            const uint32_t mm2 = pk_min(L0, L1);
+            const int mw = group_min<64>(in ? (int)min(mm2 & 0xffffu, mm2 >> 16) : 0x7fffffff);
             if (g == gg) m_new = mw;
         }
         lds_order();
-        // erase what the previous step wrote into the row read now
+        // erase what the previous step wrote into the row read now (a wide
+        // span already erased above when this step is wide too)
         if (pmode == 1) prv[perase] = kInfPk;
-        uint64_t eb = __builtin_amdgcn_ballot_w64(pmode == 2 && l == 0);
+        uint64_t eb = __builtin_amdgcn_ballot_w64(pmode == 2 && !(act && !nar) && l == 0);
         while (eb) {
             const int bit = (int)__builtin_ctzll(eb);
             eb &= eb - 1;
             const int gg = bit / G;
             const int b0 = __builtin_amdgcn_readlane(pb, bit), e0 = __builtin_amdgcn_readlane(pe, bit);
             uint32_t* prg = reinterpret_cast<uint32_t*>(rows[gg][par ^ 1]);
-            const int d = b0 + 4 * lane;
-            if (d < e0) {
-                prg[(d >> 1) + 1] = kInfPk;
-                prg[(d >> 1) + 2] = kInfPk;
+            const int de = b0 + 4 * lane;
+            if (de < e0) {
+                prg[(de >> 1) + 1] = kInfPk;
+                prg[(de >> 1) + 2] = kInfPk;
             }
         }
         lds_order();
         m = m_new;
-        pmode = mode;
+        pmode = act ? (nar ? 1 : 2) : 0;
         pb = B;
         pe = B + span;
         perase = qd + 1;
@@ -1372,17 +1407,19 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_group_kernel(SgmLaunch a, Gr
     }
 }
 
-// Costs in the quad layout.  One block per 64-pixel row segment: the
-// segment's windows (written as window words with the quad offset), then
-// all quads of its pixels spread over the block's threads, one dword of
-// four costs per quad (padding slots get a cost too: 62 past D or the image).
-__global__ __launch_bounds__(kBlock) void cost_quad_kernel(SgmLaunch a) {
+// Costs in the frame layout.  One block per 64-pixel row segment: the
+// segment's windows (written as window words with the frame offset), then
+// all quads of its pixels' spans spread over the block's threads, one dword
+// of four costs per quad: C(p, d) inside the window, the padding marker
+// outside it.
+__global__ __launch_bounds__(kBlock) void cost_frame_kernel(SgmLaunch a) {
     __shared__ uint64_t crs[kSeg + kMaxDisp];
     __shared__ uint64_t cls[kSeg];
     __shared__ uint32_t s_pre[kSeg + 1];   // quads before each pixel of the segment
-    __shared__ int s_b[kSeg];
+    __shared__ int s_b[kSeg], s_lo[kSeg], s_w[kSeg];
     __shared__ uint32_t s_q[kSeg];
     const int W = a.w, D = a.win.max_disp;
+    const uint32_t F = 2u * (uint32_t)a.quad;
     const int y = blockIdx.y, x0 = blockIdx.x * kSeg;
     const int base = x0 - (D - 1);
     const gmem<const uint64_t>* rowl = gptr(a.census_l + (size_t)y * W);
@@ -1395,11 +1432,14 @@ __global__ __launch_bounds__(kBlock) void cost_quad_kernel(SgmLaunch a) {
             const int lo = gptr(a.win.lo)[p], hi = gptr(a.win.hi)[p];
             const uint32_t off = gptr(a.win.off)[p];
             const int w = hi - lo + 1;
-            const uint32_t q = quad_off(off, (uint32_t)p);
+            const uint32_t q = frame_off(off, (uint32_t)p, F);
             gptr(a.meta)[p] = pack_meta(q, lo, w);
+            const int span = ((lo + w + 3) & ~3) - (lo & ~3);
             s_b[i] = lo & ~3;
+            s_lo[i] = lo;
+            s_w[i] = w;
             s_q[i] = q;
-            nq = (uint32_t)((((lo + w + 3) & ~3) - (lo & ~3)) >> 2);
+            nq = (uint32_t)((span <= (int)F ? (int)F : span) >> 2);
         }
         uint32_t inc = nq;
 #pragma unroll
@@ -1426,13 +1466,16 @@ __global__ __launch_bounds__(kBlock) void cost_quad_kernel(SgmLaunch a) {
         const int x = x0 + i;
         const uint32_t qk = k - s_pre[i];
         const int d = s_b[i] + 4 * (int)qk;
+        const int lo = s_lo[i], w = s_w[i];
         const uint64_t cl = cls[i];
         uint32_t word = 0;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int dd = d + b;
-            const int c = (dd < D && x - dd >= 0) ? __popcll(cl ^ crs[i + (D - 1) - dd]) : kCensusBits;
-            word |= (uint32_t)c << (8 * b);
+            uint32_t c = kPadCost;
+            if ((uint32_t)(dd - lo) < (uint32_t)w)
+                c = x - dd >= 0 ? (uint32_t)__popcll(cl ^ crs[i + (D - 1) - dd]) : (uint32_t)kCensusBits;
+            word |= c << (8 * b);
         }
         cost[(s_q[i] >> 2) + qk] = word;
     }
@@ -1606,10 +1649,11 @@ __global__ __launch_bounds__(kBlock) void select_quad_kernel(SgmLaunch a) {
 __global__ __launch_bounds__(kBlock) void copy_quad_slots_kernel(SgmLaunch a, const uint8_t* src, size_t src_stride,
                                                                  uint8_t* dst, size_t dst_stride, int nvol) {
     const int n = a.w * a.h;
+    const uint32_t F = 2u * (uint32_t)a.quad;
     for (int p = (int)(blockIdx.x * kBlock + threadIdx.x); p < n; p += (int)(gridDim.x * kBlock)) {
         const int lo = a.win.lo[p], w = a.win.hi[p] - lo + 1;
         const uint32_t off = a.win.off[p];
-        const uint32_t q = quad_off(off, (uint32_t)p) + (uint32_t)(lo & 3);
+        const uint32_t q = frame_off(off, (uint32_t)p, F) + (uint32_t)(lo & 3);
         for (int v = 0; v < nvol; ++v)
             for (int s = 0; s < w; ++s) dst[v * dst_stride + off + s] = src[v * src_stride + q + s];
     }
@@ -2207,15 +2251,16 @@ hipError_t launch_census_pair(const uint8_t* left, const uint8_t* right, int w, 
 }
 
 size_t quad_volume_bytes(int w, int h, int D) {
+    // frames of up to 32 slots: w*h*(D + 35) + 64 bytes, below the drop offset
     const unsigned long long n = (unsigned long long)w * (unsigned long long)h;
-    const unsigned long long b = n * (unsigned long long)(D + 9) + 8ull;
-    return b < (1ull << 32) ? (size_t)((b + 255ull) & ~255ull) : 0;
+    const unsigned long long b = (n * (unsigned long long)(D + 35) + 64ull + 255ull) & ~255ull;
+    return b < (unsigned long long)kDropWide ? (size_t)b : 0;
 }
 
 hipError_t launch_sgm_cost(const SgmLaunch& a, hipStream_t s) {
     dim3 grid((a.w + kSeg - 1) / kSeg, a.h);
     if (a.quad)
-        cost_quad_kernel<<<grid, kBlock, 0, s>>>(a);
+        cost_frame_kernel<<<grid, kBlock, 0, s>>>(a);
     else if (a.win.lo == nullptr)
         cost_kernel<64, kWinFull><<<grid, kBlock, 0, s>>>(a);
     else
@@ -2260,7 +2305,7 @@ hipError_t launch_sgm_paths(const SgmLaunch& a, hipStream_t s) {
     const int g = a.ragged_group;
     const int sched = a.ragged_schedule;
     if (a.quad) {
-        const int G = sched == 5 ? 16 : 8, NG = 64 / G;
+        const int G = a.quad, NG = 64 / G;
         GroupTasks t{};
         t.n_dirs = a.n_paths == 4 ? 4 : 8;
         t.strided = 1;
@@ -2275,13 +2320,13 @@ hipError_t launch_sgm_paths(const SgmLaunch& a, hipStream_t s) {
             t.wave_start[r + 1] = t.wave_start[r] + (ns[r] + NG - 1) / NG;
         }
         const unsigned nb = (unsigned)((t.wave_start[t.n_dirs] + kBlock / 64 - 1) / (kBlock / 64));
-#define EGOSGM_GRP(GG)                                                                       \
+#define EGOSGM_GRP(GG, PP)                                                                   \
     do {                                                                                     \
-        if (D <= 64) sgm_paths_group_kernel<GG, 64, 4><<<nb, kBlock, 0, s>>>(a, t);           \
-        else if (D <= 128) sgm_paths_group_kernel<GG, 128, 4><<<nb, kBlock, 0, s>>>(a, t);    \
-        else sgm_paths_group_kernel<GG, 256, 4><<<nb, kBlock, 0, s>>>(a, t);                  \
+        if (D <= 64) sgm_paths_group_kernel<GG, 64, PP><<<nb, kBlock, 0, s>>>(a, t);          \
+        else if (D <= 128) sgm_paths_group_kernel<GG, 128, PP><<<nb, kBlock, 0, s>>>(a, t);   \
+        else sgm_paths_group_kernel<GG, 256, PP><<<nb, kBlock, 0, s>>>(a, t);                 \
     } while (0)
-        if (G == 16) EGOSGM_GRP(16); else EGOSGM_GRP(8);
+        if (G == 16) EGOSGM_GRP(16, 4); else EGOSGM_GRP(8, 4);
 #undef EGOSGM_GRP
         return hipGetLastError();
     }

@@ -23,6 +23,8 @@ from paper_1708_06301_amd import pipeline, synth
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
 DEV = "cuda:0"
+# every ragged schedule the benchmark's tuner may pick (its candidates)
+SCHEDULES = (1, 0, 2, 3, 4, 5)
 
 
 def _say(*a):
@@ -55,48 +57,67 @@ def _check_matcher(st, o, what):
     assert np.abs(sub - o["disp_sub"]).max() <= TOL, f"{what}: subpixel"
 
 
-def _run_chain(seq, cfg, n_frames, label):
+def _same_outputs(a, b, what, predicted):
+    """Another launch schedule on the same inputs: every output bit-identical
+    (the prediction and windows too on a predicted frame)."""
+    for k in ("disp_wta", "disp_sub", "var_meas", "disp_right"):
+        assert torch.equal(a.out[k], b.out[k]), f"{what}: {k}"
+    for k in ("d", "p") + (("d_pred", "p_pred", "lo", "hi", "off") if predicted else ()):
+        assert torch.equal(getattr(a, k), getattr(b, k)), f"{what}: {k}"
+
+
+def _run_chain(seq, cfg, n_frames, label, scheds=(1,)):
     """Steps the GPU pipeline over n_frames and checks every frame against
-    the oracle fed with the GPU's previous maps.  Returns the searched
-    fractions of the reduced frames."""
-    eg.set_tuning(**eg.DEFAULT_TUNING)
+    the oracle fed with the GPU's previous maps.  With several ragged
+    schedules, one pipeline per schedule steps the same frames: the first is
+    checked against the oracle, the others must equal it bit for bit.
+    Returns the searched fractions of the reduced frames."""
     w, h = seq.cam.w, seq.cam.h
     calib = pipeline.camera_of(seq)
-    st = pipeline.StreamState(w, h, calib, cfg, DEV)
+    sts = [pipeline.StreamState(w, h, calib, cfg, DEV) for _ in scheds]
+    st = sts[0]
     motions = pipeline.motions(seq)
     fractions = []
-    for k in range(n_frames):
-        _say(label, "frame", k)
-        L, R, _ = seq.frame(k)
-        Lg, Rg = torch.from_numpy(L).to(DEV), torch.from_numpy(R).to(DEV)
-        d_prev, p_prev = (None, None) if k == 0 else (_np(st.d), _np(st.p))
-        win = st.predict(*motions[k]) if k > 0 else st.predict()
-        st.match(Lg, Rg, win)
-        d, p = st.update()
-        torch.cuda.synchronize()
-        if k == 0:
-            o = oracle_frames.match(L, R, cfg)
-            _check_matcher(st, o, f"frame {k}")
-            od, op = oracle_frames.update(None, None, o, cfg)
-        else:
-            Rm, t = motions[k]
-            odp, opp, _ = oracle_frames.predict(d_prev, p_prev, Rm, t, calib, cfg)
-            gdp, gpp = _np(st.d_pred), _np(st.p_pred)
-            _close_maps(gdp, odp, f"frame {k} prediction d")
-            valid = odp >= 0
-            assert np.abs(gpp[valid].astype(np.float64) - opp[valid]).max() <= TOL, f"frame {k} prediction p"
-            wo = oracle_frames.windows(gdp, gpp, cfg)
-            assert np.array_equal(_np(win[0]).ravel(), wo[0]), f"frame {k}: lo"
-            assert np.array_equal(_np(win[1]).ravel(), wo[1]), f"frame {k}: hi"
-            assert np.array_equal(_np(win[2]).view(np.uint32), wo[2]), f"frame {k}: offsets"
-            fractions.append(int(wo[2][-1]) / (w * h * cfg.max_disp))
-            o = oracle_frames.match(L, R, cfg, wo)
-            _check_matcher(st, o, f"frame {k}")
-            od, op = oracle_frames.update(gdp, gpp, o, cfg)
-        _close_maps(_np(d), od, f"frame {k} update d")
-        gp, v = _np(p).astype(np.float64), od >= 0
-        assert np.abs(gp[v] - op[v]).max() <= TOL if v.any() else True, f"frame {k} update p"
-        assert (gp[~v] == 0).all(), f"frame {k}: variance of invalid pixels"
+    try:
+        for k in range(n_frames):
+            _say(label, "frame", k, "schedules", scheds)
+            L, R, _ = seq.frame(k)
+            Lg, Rg = torch.from_numpy(L).to(DEV), torch.from_numpy(R).to(DEV)
+            d_prev, p_prev = (None, None) if k == 0 else (_np(st.d), _np(st.p))
+            for sched, sk in zip(scheds, sts):
+                eg.set_tuning(**{**eg.DEFAULT_TUNING, "ragged_schedule": sched})
+                win = sk.predict(*motions[k]) if k > 0 else sk.predict()
+                sk.match(Lg, Rg, win)
+                sk.update()
+                torch.cuda.synchronize()
+            for sched, sk in zip(scheds[1:], sts[1:]):
+                _same_outputs(st, sk, f"frame {k} schedule {sched}", k > 0)
+            d, p = st.d, st.p
+            if k == 0:
+                o = oracle_frames.match(L, R, cfg)
+                _check_matcher(st, o, f"frame {k}")
+                od, op = oracle_frames.update(None, None, o, cfg)
+            else:
+                Rm, t = motions[k]
+                odp, opp, _ = oracle_frames.predict(d_prev, p_prev, Rm, t, calib, cfg)
+                gdp, gpp = _np(st.d_pred), _np(st.p_pred)
+                _close_maps(gdp, odp, f"frame {k} prediction d")
+                valid = odp >= 0
+                assert np.abs(gpp[valid].astype(np.float64) - opp[valid]).max() <= TOL, f"frame {k} prediction p"
+                wo = oracle_frames.windows(gdp, gpp, cfg)
+                assert np.array_equal(_np(st.lo).ravel(), wo[0]), f"frame {k}: lo"
+                assert np.array_equal(_np(st.hi).ravel(), wo[1]), f"frame {k}: hi"
+                assert np.array_equal(_np(st.off).view(np.uint32), wo[2]), f"frame {k}: offsets"
+                fractions.append(int(wo[2][-1]) / (w * h * cfg.max_disp))
+                o = oracle_frames.match(L, R, cfg, wo)
+                _check_matcher(st, o, f"frame {k}")
+                od, op = oracle_frames.update(gdp, gpp, o, cfg)
+            _close_maps(_np(d), od, f"frame {k} update d")
+            gp, v = _np(p).astype(np.float64), od >= 0
+            assert np.abs(gp[v] - op[v]).max() <= TOL if v.any() else True, f"frame {k} update p"
+            assert (gp[~v] == 0).all(), f"frame {k}: variance of invalid pixels"
+    finally:
+        eg.set_tuning(**eg.DEFAULT_TUNING)
     return fractions
 
 
@@ -107,7 +128,7 @@ def test_street_sequence_20_frames_chained():
     seq = synth.street_sequence(1242, 375, 20, seed=synth.seed_for(1))
     cfg = pipeline.FrameConfig(max_disp=128, p1=10, p2=120, s_max=80, lr_tol=1, q=0.5,
                                r_fixed=4, r_min=0, r_max=256, edge_tol=2.0, fill_tol=1.0)
-    frac = _run_chain(seq, cfg, 20, "street 1242x375")
+    frac = _run_chain(seq, cfg, 20, "street 1242x375", scheds=SCHEDULES)
     assert 0.0 < max(frac) < 0.5
 
 
@@ -119,5 +140,5 @@ def test_highres_sequence_first_frames_chained():
     seq = synth.street_sequence(2048, 1024, 3, seed=synth.seed_for(3))
     cfg = pipeline.FrameConfig(max_disp=256, p1=10, p2=120, s_max=80, lr_tol=1, q=0.5,
                                r_fixed=6, r_min=0, r_max=256, edge_tol=2.0, fill_tol=1.0)
-    frac = _run_chain(seq, cfg, 3, "highres 2048x1024")
+    frac = _run_chain(seq, cfg, 3, "highres 2048x1024", scheds=SCHEDULES)
     assert 0.0 < max(frac) < 0.5
