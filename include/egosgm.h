@@ -397,7 +397,9 @@ typedef struct egosgm_tuning {
                                    by its group, a wider one by the whole wave; the volumes
                                    use an aligned internal layout, and the selection takes
                                    narrow windows 4 lanes per pixel (images whose volumes
-                                   would pass 4 GiB at w*h*(D+9) bytes fall back to 1)      */
+                                   would pass 4 GiB at w*h*(D+35) bytes fall back to 1);
+                                6, 7: the rows as in 1, the columns and diagonals as in
+                                   5 (16 lanes) or 4 (8 lanes), in the same layout          */
     int32_t batch_group;     /* lanes per scanline in batched plans (fixed when a plan is
                                 created): 16, 32, 64                                           */
     int32_t wide_offsets;    /* LDS scanlines of ragged windows: 0 addresses window words and

@@ -182,7 +182,7 @@ int run_sgm(const uint8_t* left, const uint8_t* right, int w, int h, int pitch, 
     // offsets would not fit 32 bits the rows-on-registers schedule runs instead
     a.quad = 0;
     if (win.lo != nullptr && a.ragged_schedule >= 4) {
-        if (L.vol_stride_q != 0) a.quad = a.ragged_schedule == 5 ? 16 : 8;
+        if (L.vol_stride_q != 0) a.quad = (a.ragged_schedule == 5 || a.ragged_schedule == 6) ? 16 : 8;
         else a.ragged_schedule = 1;
     }
     a.vol_stride = a.quad ? L.vol_stride_q : L.vol_stride;
@@ -788,7 +788,7 @@ int egosgm_set_tuning(const egosgm_tuning* t) {
     if (!t) return EGOSGM_EINVAL;
     auto ok = [](int g) { return g == 16 || g == 32 || g == 64; };
     if (!ok(t->full_group) || !ok(t->ragged_group) || !ok(t->batch_group) || t->ragged_schedule < 0 ||
-        t->ragged_schedule > 5 || (t->wide_offsets != 0 && t->wide_offsets != 1))
+        t->ragged_schedule > 7 || (t->wide_offsets != 0 && t->wide_offsets != 1))
         return EGOSGM_EINVAL;
     std::lock_guard<std::mutex> g(g_tuning_mu);
     g_tuning = *t;

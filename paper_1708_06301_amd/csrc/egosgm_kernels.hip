@@ -1152,6 +1152,7 @@ __device__ inline int small_group_min(int v) {
 // takes scanline g*waves + j, so each wave mixes scanlines from every part
 // of the image; diagonals take NG neighbouring scanlines (similar lengths).
 struct GroupTasks {
+    int first_dir;   // directions first_dir .. n_dirs-1 (wave_start[first_dir] = 0)
     int n_dirs;
     int strided;
     int n_scan[kNumPaths];
@@ -1206,7 +1207,7 @@ __device__ inline void load_dwords(__amdgpu_buffer_rsrc_t buf, uint32_t at, uint
 // ahead, costs PF steps ahead.  A zero predecessor over the first pixel's
 // window makes the first step L = C.
 template <int G, int DMAX, int PF>
-__global__ __launch_bounds__(kBlock) void sgm_paths_group_kernel(SgmLaunch a, GroupTasks t) {
+__device__ inline void group_scanlines(const SgmLaunch& a, const GroupTasks& t, int gw) {
     constexpr int NG = 64 / G;
     constexpr int F = 2 * G;
     constexpr int ROW = DMAX + 2 * G + 8;
@@ -1217,9 +1218,8 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_group_kernel(SgmLaunch a, Gr
     __shared__ __attribute__((aligned(16))) uint32_t stage_all[kBlock / 64][DMAX / 4];
     const int lane = (int)(threadIdx.x & 63u);
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int gw = (int)blockIdx.x * (kBlock / 64) + wv;
     if (gw >= t.wave_start[t.n_dirs]) return;
-    int dir = 0;
+    int dir = t.first_dir;
     while (gw >= t.wave_start[dir + 1]) ++dir;
     const int wl = gw - t.wave_start[dir];
     const int nwav = t.wave_start[dir + 1] - t.wave_start[dir];
@@ -1260,8 +1260,8 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_group_kernel(SgmLaunch a, Gr
     uint32_t cst[PF];       // narrow: this lane's two cost bytes
     uint32_t wcs[PF][WV];   // wide: this lane's share of its group's pixel's costs
     auto load_costs = [&](int s, uint64_t mw, int i) {
-        const uint32_t o = meta_off(mw);
         const int lo = meta_lo(mw), w = meta_w(mw);
+        const uint32_t o = meta_off(mw) - (uint32_t)(lo & 3);   // the frame's first slot
         const bool wide = i < len && ((lo + w + 3) & ~3) - (lo & ~3) > F;
         cst[s] = __builtin_amdgcn_raw_buffer_load_b16(cbuf, o + 2u * (uint32_t)l, 0, 0);
         load_dwords<WV>(cbuf, wide ? o + 4u * WV * (uint32_t)l : kDropWide, wcs[s]);
@@ -1291,7 +1291,7 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_group_kernel(SgmLaunch a, Gr
     auto step = [&](int i, int ti, int tc, int par) {
         const uint64_t mt = mm[ti];
         const int lo = meta_lo(mt), w = meta_w(mt);
-        const uint32_t o = meta_off(mt);
+        const uint32_t o = meta_off(mt) - (uint32_t)(lo & 3);   // the frame's first slot
         const bool act = i < len;
         const int B = lo & ~3;
         const int span = ((lo + w + 3) & ~3) - B;
@@ -1407,6 +1407,31 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_group_kernel(SgmLaunch a, Gr
     }
 }
 
+template <int G, int DMAX, int PF>
+__global__ __launch_bounds__(kBlock) void sgm_paths_group_kernel(SgmLaunch a, GroupTasks t) {
+    group_scanlines<G, DMAX, PF>(a, t, (int)blockIdx.x * (kBlock / 64) +
+                                           __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)));
+}
+
+// Hybrid: blocks below n_row_blocks walk the image rows, one wave each on
+// windowed packed registers over all disparities (branch-free steps, the
+// shortest step latency for the longest scanlines, at a higher issue
+// priority); the other blocks run the grouped scanlines of the columns and
+// diagonals (t.first_dir = 2).
+template <int G, int DMAX, int PF, int NP>
+__global__ __launch_bounds__(kBlock) void sgm_paths_hybrid_kernel(SgmLaunch a, GroupTasks t, int n_row_blocks) {
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if ((int)blockIdx.x < n_row_blocks) {
+        __builtin_amdgcn_s_setprio(2);
+        const int task = (int)blockIdx.x * (kBlock / 64) + wv;
+        if (task >= 2 * a.h) return;
+        win_scanline<NP, kWinRagged, PF, 4 * PF>(a, scan_of(task, a.w, a.h), (int)(threadIdx.x & 63u));
+    } else {
+        __builtin_amdgcn_s_setprio(1);
+        group_scanlines<G, DMAX, PF>(a, t, ((int)blockIdx.x - n_row_blocks) * (kBlock / 64) + wv);
+    }
+}
+
 // Costs in the frame layout.  One block per 64-pixel row segment: the
 // segment's windows (written as window words with the frame offset), then
 // all quads of its pixels' spans spread over the block's threads, one dword
@@ -1433,7 +1458,9 @@ __global__ __launch_bounds__(kBlock) void cost_frame_kernel(SgmLaunch a) {
             const uint32_t off = gptr(a.win.off)[p];
             const int w = hi - lo + 1;
             const uint32_t q = frame_off(off, (uint32_t)p, F);
-            gptr(a.meta)[p] = pack_meta(q, lo, w);
+            // the window word's offset addresses slot lo (q + d - B for slot d),
+            // as in the ragged layout, so every path kernel can read this layout
+            gptr(a.meta)[p] = pack_meta(q + (uint32_t)(lo & 3), lo, w);
             const int span = ((lo + w + 3) & ~3) - (lo & ~3);
             s_b[i] = lo & ~3;
             s_lo[i] = lo;
@@ -1580,7 +1607,7 @@ __global__ __launch_bounds__(kBlock) void select_quad_kernel(SgmLaunch a) {
     const int p = y * W + min(x, W - 1);
     const uint64_t mt = gptr(a.meta)[p];
     const int lo = meta_lo(mt), w = meta_w(mt);
-    const uint32_t q = meta_off(mt);
+    const uint32_t q = meta_off(mt) - (uint32_t)(lo & 3);   // slot B
     const int B = lo & ~3;
     const int span = ((lo + w + 3) & ~3) - B;
     const bool nar = span <= 16;
@@ -2305,21 +2332,37 @@ hipError_t launch_sgm_paths(const SgmLaunch& a, hipStream_t s) {
     const int g = a.ragged_group;
     const int sched = a.ragged_schedule;
     if (a.quad) {
+        // schedules 6, 7: the rows on windowed registers, the rest grouped
+        const bool hybrid = sched >= 6;
         const int G = a.quad, NG = 64 / G;
         GroupTasks t{};
+        t.first_dir = hybrid ? 2 : 0;
         t.n_dirs = a.n_paths == 4 ? 4 : 8;
         t.strided = 1;
         const int W = a.w, H = a.h;
         const int ns[kNumPaths] = {H, H, W, W, W + H - 1, W + H - 1, W + H - 1, W + H - 1};
         int task = 0;
-        t.wave_start[0] = 0;
-        for (int r = 0; r < t.n_dirs; ++r) {
+        for (int r = 0; r < t.first_dir; ++r) task += ns[r];
+        t.wave_start[t.first_dir] = 0;
+        for (int r = t.first_dir; r < t.n_dirs; ++r) {
             t.n_scan[r] = ns[r];
             t.first_task[r] = task;
             task += ns[r];
             t.wave_start[r + 1] = t.wave_start[r] + (ns[r] + NG - 1) / NG;
         }
         const unsigned nb = (unsigned)((t.wave_start[t.n_dirs] + kBlock / 64 - 1) / (kBlock / 64));
+        if (hybrid) {
+            const int nrb = (2 * H + kBlock / 64 - 1) / (kBlock / 64);
+#define EGOSGM_HYB(GG)                                                                                     \
+    do {                                                                                                   \
+        if (D <= 64) sgm_paths_hybrid_kernel<GG, 64, 4, 1><<<nb + nrb, kBlock, 0, s>>>(a, t, nrb);          \
+        else if (D <= 128) sgm_paths_hybrid_kernel<GG, 128, 4, 1><<<nb + nrb, kBlock, 0, s>>>(a, t, nrb);   \
+        else sgm_paths_hybrid_kernel<GG, 256, 4, 2><<<nb + nrb, kBlock, 0, s>>>(a, t, nrb);                 \
+    } while (0)
+            if (G == 16) EGOSGM_HYB(16); else EGOSGM_HYB(8);
+#undef EGOSGM_HYB
+            return hipGetLastError();
+        }
 #define EGOSGM_GRP(GG, PP)                                                                   \
     do {                                                                                     \
         if (D <= 64) sgm_paths_group_kernel<GG, 64, PP><<<nb, kBlock, 0, s>>>(a, t);          \
