@@ -485,27 +485,14 @@ def batch_section(dev, n_pairs, steps, log):
         return a.elapsed_time(bb) / reps
 
     reps = max(3, steps)
-    # Lanes per scanline are fixed when a plan is built: build one plan per
-    # candidate and keep the fastest, for the reduced and the full batch.
-    base = eg.get_tuning()
-
-    def best_plan(cs):
-        best, times = None, {}
-        for g in (16, 32, 64):
-            eg.set_tuning(batch_group=g)
-            p = eg.Plan(cs, prm)
-            times[g] = timed(p.run, reps)
-            if best is None or times[g] < times[best[0]]:
-                if best is not None:
-                    best[1].close()
-                best = (g, p)
-            else:
-                p.close()
-        eg.set_tuning(**base)
-        return best[0], best[1], times
-
-    best_g, plan, group_ms = best_plan(cases)
-    best_gf, plan_full, group_ms_full = best_plan(full_cases)
+    # Lanes per scanline are fixed when a plan is built: the autotuner builds
+    # one plan per candidate and keeps the fastest (cached per batch shape),
+    # for the reduced and the full batch.
+    from paper_1708_06301_amd import autotune
+    shape = "+".join(f"{w}x{h}D{D}" for w, h, D in sizes) + f"x{n_pairs}"
+    best_g, plan, group_ms = autotune.tune_plan(lambda: eg.Plan(cases, prm), "ragged|" + shape, reps=reps, log=log)
+    best_gf, plan_full, group_ms_full = autotune.tune_plan(lambda: eg.Plan(full_cases, prm), "full|" + shape,
+                                                           reps=reps, log=log)
     ms_red = timed(plan.run, reps)
     ms_full = timed(plan_full.run, reps)
     singles = [dict(left=c["left"], right=c["right"], win=c["windows"],
@@ -533,14 +520,13 @@ def batch_section(dev, n_pairs, steps, log):
                     "r=clamp(ceil(3 sqrt(p)),2,16) from each pair's frame-1 prediction, one graph launch",
         "gcups": round(8 * slots / (ms_red * 1e-3) / 1e9, 1),
         "ms_per_batch": round(ms_red, 4),
-        "lanes_per_scanline": best_g,
-        "ms_per_batch_by_lanes": {str(g): round(v, 4) for g, v in group_ms.items()},
+        "plan_tuning": best_g,
+        "ms_per_batch_by_plan_tuning": {k: round(v, 4) for k, v in group_ms.items()},
         "pairs_per_s": round(n_pairs / (ms_red * 1e-3), 1),
         "search_fraction": round(slots / full_slots, 4),
         "full_range": {"gcups": round(8 * full_slots / (ms_full * 1e-3) / 1e9, 1),
-                       "ms_per_batch": round(ms_full, 4), "lanes_per_scanline": best_gf,
-                       "ms_per_batch_by_lanes": {str(g): round(v, 4)
-                                                 for g, v in group_ms_full.items()}},
+                       "ms_per_batch": round(ms_full, 4), "plan_tuning": best_gf,
+                       "ms_per_batch_by_plan_tuning": {k: round(v, 4) for k, v in group_ms_full.items()}},
         "speedup_vs_full": round(ms_full / ms_red, 3),
         "single_pair_calls_ms": round(ms_single, 4),
         "speedup_vs_single_calls": round(ms_single / ms_red, 3),

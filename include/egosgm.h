@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define EGOSGM_ABI_VERSION 3
+#define EGOSGM_ABI_VERSION 4
 
 /* Largest disparity range and the census window (9 wide, 7 tall: 62 bits). */
 #define EGOSGM_MAX_DISP 256
@@ -343,8 +343,14 @@ size_t egosgm_plan_workspace_bytes(const egosgm_pair* pairs, int n);
 /* Validates the pairs, lays out the workspace (device memory of at least
  * egosgm_plan_workspace_bytes), uploads the per-pair tables (synchronously)
  * and captures census, cost, paths, selection and left-right check of all
- * pairs into one graph.  params: p1, p2, s_max, lr_tol shared by all pairs
- * (max_disp is taken from each pair).  *out: the new plan. */
+ * pairs into one graph.  The path stage is one launch over the scanline
+ * tasks of every pair (rows, then columns, then diagonals): one block per
+ * 256/G tasks, or, with egosgm_tuning.batch_persistent, a persistent grid of
+ * only as many blocks as fit on the device at once whose waves take runs of
+ * tasks from work counters in the workspace until none is left.  params:
+ * p1, p2, s_max, lr_tol shared by all pairs (max_disp is taken from each
+ * pair).  Lanes per scanline (G) and the persistent choice come from the
+ * tuning at creation.  *out: the new plan. */
 int sgm_plan_create(const egosgm_pair* pairs, int n, const egosgm_sgm_params* params,
                     void* workspace, size_t workspace_bytes, egosgm_plan** out);
 /* One launch of the captured graph on `stream`. */
@@ -381,7 +387,7 @@ int sgm_plan_destroy(egosgm_plan* plan);
 /* ------------------------------------------------------------------ tuning
  * Launch shapes and schedules of the path kernels, process-wide (the second
  * piece of state the library keeps; set it before enqueueing work, e.g. from
- * an autotuner).  Results never depend on it.  Defaults: {64, 32, 1, 16, 0}. */
+ * an autotuner).  Results never depend on it.  Defaults: {64, 32, 1, 16, 0, 0}. */
 typedef struct egosgm_tuning {
     int32_t full_group;      /* lanes per scanline, full-range kernel: 16, 32, 64             */
     int32_t ragged_group;    /* lanes per scanline, ragged windows through LDS: 16, 32, 64    */
@@ -406,6 +412,8 @@ typedef struct egosgm_tuning {
                                 path costs by 32-bit offsets wherever the image allows it
                                 (w*h < 2^27 and the eight path volumes within 4 GiB); 1 uses
                                 64-bit addresses everywhere, the form larger images take        */
+    int32_t batch_persistent; /* batched plans (fixed when a plan is created): 0 one block per
+                                256/G scanline tasks; 1 a persistent path grid                  */
 } egosgm_tuning;
 
 int egosgm_set_tuning(const egosgm_tuning* tuning);

@@ -114,3 +114,47 @@ def tune(run, w, h, max_disp, tag="", candidates=None, reps=3, use_cache=True, l
         cache[key] = {"tuning": best, "times": {str(k): v for k, v in times.items()}}
         _store(cache)
     return best, times
+
+
+# batched plans: lanes per scanline x persistent path grid
+PLAN_CANDIDATES = [dict(batch_group=g, batch_persistent=p) for g in (16, 32, 64) for p in (0, 1)]
+
+
+def tune_plan(make_plan, key_tag, reps=3, use_cache=True, log=None):
+    """Lanes per scanline and the persistent path grid of a batched plan,
+    both fixed when the plan is built: builds one plan per candidate
+    (make_plan() under that tuning), times its graph launch and keeps the
+    fastest, cached under key_tag (the caller names the batch's shapes).
+    Returns (candidate, plan, {"<group>/<persistent>": ms}); the other plans
+    are closed."""
+    key = _key(0, 0, 0, "plan|" + key_tag)
+    cache = _load() if use_cache else {}
+    base = eg.get_tuning()
+    if use_cache and key in cache:
+        best = cache[key]["tuning"]
+        eg.set_tuning(**best)
+        plan = make_plan()
+        eg.set_tuning(**base)
+        return best, plan, cache[key].get("times", {})
+    best, times = None, {}
+    for c in PLAN_CANDIDATES:
+        eg.set_tuning(**c)
+        p = make_plan()
+        p.run()
+        torch.cuda.synchronize()
+        name = f"{c['batch_group']}/{c['batch_persistent']}"
+        times[name] = time_workload(p.run, reps)
+        if log:
+            log(f"plan {c}: {times[name]:.3f} ms")
+        if best is None or times[name] < best[2]:
+            if best is not None:
+                best[1].close()
+            best = (c, p, times[name])
+        else:
+            p.close()
+    eg.set_tuning(**base)
+    if use_cache:
+        cache = _load()
+        cache[key] = {"tuning": best[0], "times": times}
+        _store(cache)
+    return best[0], best[1], times

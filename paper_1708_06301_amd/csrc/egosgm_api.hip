@@ -88,7 +88,7 @@ hipError_t window_scratch(uint32_t** out) {
 }
 
 // Launch-shape choices (set by egosgm_set_tuning; read at every launch).
-egosgm_tuning g_tuning = {64, 32, 1, 16, 0};
+egosgm_tuning g_tuning = {64, 32, 1, 16, 0, 0};
 std::mutex g_tuning_mu;
 
 constexpr size_t kAlign = 256;
@@ -261,7 +261,7 @@ int check_pair(const egosgm_pair& p) {
 }
 
 struct PlanLayout {
-    size_t pairs, census_prefix, seg_prefix, pix_prefix, task_start, task_pair, task_local, task_count;
+    size_t pairs, census_prefix, seg_prefix, pix_prefix, task_start, task_pair, task_local, task_count, work;
     size_t data, total;
     int n_ranges;
 };
@@ -278,6 +278,7 @@ PlanLayout plan_layout(const egosgm_pair* pairs, int n) {
     P.task_pair = o;     o += align_up((size_t)P.n_ranges * sizeof(int));
     P.task_local = o;    o += align_up((size_t)P.n_ranges * sizeof(int));
     P.task_count = o;    o += align_up((size_t)P.n_ranges * sizeof(int));
+    P.work = o;          o += align_up((size_t)kBatchShards * kBatchShardStride);
     P.data = o;
     for (int i = 0; i < n; ++i) o += pair_bytes(pairs[i]);
     P.total = o;
@@ -396,9 +397,11 @@ int sgm_plan_create(const egosgm_pair* pairs, int n, const egosgm_sgm_params* pa
     t.task_pair = reinterpret_cast<const int*>(base + P.task_pair);
     t.task_local = reinterpret_cast<const int*>(base + P.task_local);
     t.task_count = reinterpret_cast<const int*>(base + P.task_count);
+    t.work = reinterpret_cast<unsigned*>(base + P.work);
     {
         std::lock_guard<std::mutex> g(g_tuning_mu);
         t.group = g_tuning.batch_group;
+        t.persistent = g_tuning.batch_persistent;
     }
     t.n = n;
     t.n_paths = prm.n_paths == 4 ? 4 : 8;
@@ -407,6 +410,8 @@ int sgm_plan_create(const egosgm_pair* pairs, int n, const egosgm_sgm_params* pa
     t.host_census_blocks = (int)tiles;
     t.host_seg_blocks = (int)segs;
     t.host_pixels = (int)pixels;
+    t.host_path_blocks = t.persistent ? batch_path_blocks(t.group, max_disp, t.n_tasks) : 0;
+    if (t.persistent && t.host_path_blocks <= 0) return EGOSGM_EDEVICE;
 
     egosgm_plan* plan = new egosgm_plan;
     plan->n = n;
@@ -788,7 +793,8 @@ int egosgm_set_tuning(const egosgm_tuning* t) {
     if (!t) return EGOSGM_EINVAL;
     auto ok = [](int g) { return g == 16 || g == 32 || g == 64; };
     if (!ok(t->full_group) || !ok(t->ragged_group) || !ok(t->batch_group) || t->ragged_schedule < 0 ||
-        t->ragged_schedule > 7 || (t->wide_offsets != 0 && t->wide_offsets != 1))
+        t->ragged_schedule > 7 || (t->wide_offsets != 0 && t->wide_offsets != 1) ||
+        (t->batch_persistent != 0 && t->batch_persistent != 1))
         return EGOSGM_EINVAL;
     std::lock_guard<std::mutex> g(g_tuning_mu);
     g_tuning = *t;

@@ -79,6 +79,10 @@ struct PlanPatches {
     int n;
 };
 
+// Work lists of the persistent batched path kernel.
+constexpr int kBatchShards = 32;
+constexpr int kBatchShardStride = 256;
+
 // Device tables of a batched launch (all pointers into device memory),
 // plus the host-side launch sizes.
 struct BatchTables {
@@ -91,10 +95,18 @@ struct BatchTables {
     const int* task_local;      // n_ranges: first local task of each range
     const int* task_count;      // n_ranges: real tasks of each range (the rest is padding)
     int n, n_ranges, n_tasks;
+    unsigned* work;             // kBatchShards work counters, kBatchShardStride bytes apart
+                                // (reset by the cost pass)
     int group;                  // lanes per scanline of the path kernel (16, 32, 64)
+    int persistent;             // 1: persistent path grid over work counters
     int n_paths;                // 8, or 4 (no diagonal tasks, 4 volumes summed)
     int host_census_blocks, host_seg_blocks, host_pixels;
+    int host_path_blocks;       // persistent path grid: blocks resident at once (at most)
 };
+
+// Blocks of the persistent batched path kernel: as many as fit on the
+// current device at once, at most one per 4 waves of tasks (0 on failure).
+int batch_path_blocks(int group, int max_disp, int n_tasks);
 
 hipError_t launch_sgm_batch(const BatchTables& t, int max_disp, hipStream_t s);
 hipError_t launch_plan_patch(SgmLaunch* pairs, const PlanPatches& p, hipStream_t s);

@@ -1932,6 +1932,9 @@ __global__ __launch_bounds__(kBlock) void census_batch_kernel(BatchTables t) {
 }
 
 __global__ __launch_bounds__(kBlock) void cost_batch_kernel(BatchTables t) {
+    // the path pass that follows takes its scanline tasks from these counters
+    if (blockIdx.x == 0 && threadIdx.x < (unsigned)kBatchShards)
+        t.work[threadIdx.x * (kBatchShardStride / sizeof(unsigned))] = 0u;
     const int i = last_leq(t.seg_prefix, t.n, (int)blockIdx.x);
     const SgmLaunch a = pair_of(t, i);
     if (!a.active) return;
@@ -1940,9 +1943,10 @@ __global__ __launch_bounds__(kBlock) void cost_batch_kernel(BatchTables t) {
     cost_segment<16, kWinAny>(a, local % segs_x, local / segs_x);
 }
 
-// Task ranges start at multiples of 4 (padded with idle tasks), so the
-// lane groups of one wave always belong to the same pair and the pair's
-// descriptor stays wave-uniform for any G.
+// Batched scanlines, one block per 256/G tasks (the hardware dispatches
+// blocks as earlier ones retire).  Task ranges start at multiples of 4
+// (padded with idle tasks), so the lane groups of one wave always belong to
+// the same pair and the pair's descriptor stays wave-uniform for any G.
 template <int G, int K, int PF>
 __global__ __launch_bounds__(kBlock) void paths_batch_kernel(BatchTables t) {
     constexpr int GPB = kBlock / G;
@@ -1959,6 +1963,46 @@ __global__ __launch_bounds__(kBlock) void paths_batch_kernel(BatchTables t) {
     if (!a.active) return;
     lds_scanline<G, K, kWinAny, PF, G == 32>(a, scan_of(t.task_local[r] + rel, a.w, a.h), lane, lds[grp][0],
                                               lds[grp][1]);
+}
+
+// Persistent: the grid holds only as many blocks as fit on the GPU at once
+// (sized at plan creation).  The runs of 64/G scanline tasks are dealt to
+// kBatchShards interleaved lists (run j to list j mod kBatchShards), each
+// with its own work counter on its own 256-byte line (reset by the cost
+// pass): wave v serves list v mod kBatchShards, takes its first run there
+// without an atomic, then the list's next free run until none is left.
+// Tasks are ordered rows, then columns, then diagonals, of every pair, so
+// the longest scanlines start first and a wave that finishes early takes
+// more work.  Same task layout and results as paths_batch_kernel.
+template <int G, int K, int PF>
+__global__ __launch_bounds__(kBlock) void paths_batch_persistent_kernel(BatchTables t) {
+    constexpr int GPB = kBlock / G;
+    constexpr int GPW = 64 / G;   // tasks per wave
+    __shared__ uint16_t lds[GPB][2][lds_row(G, K)];
+    const int grp = threadIdx.x / G, lane = threadIdx.x % G;
+    const int n_waves = (int)gridDim.x * (kBlock / 64);
+    const int v = (int)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int shard = v % kBatchShards;
+    // waves serving this list, and this wave's static first pick in it
+    const int served = n_waves / kBatchShards + (shard < n_waves % kBatchShards ? 1 : 0);
+    int k = v / kBatchShards;
+    unsigned* counter = t.work + shard * (kBatchShardStride / sizeof(unsigned));
+    for (;;) {
+        const int run = shard + kBatchShards * k;
+        if (run * GPW >= t.n_tasks) break;
+        const int task0 = run * GPW;
+        const int task = task0 + grp % GPW;
+        const int r = __builtin_amdgcn_readfirstlane(last_leq(t.task_start, t.n_ranges, task0));
+        const int i = __builtin_amdgcn_readfirstlane(t.task_pair[r]);
+        const int rel = task - t.task_start[r];
+        const SgmLaunch a = pair_of(t, i);
+        if (task < t.n_tasks && rel < t.task_count[r] && a.active)   // else padding or an inactive pair
+            lds_scanline<G, K, kWinAny, PF, G == 32>(a, scan_of(t.task_local[r] + rel, a.w, a.h), lane,
+                                                      lds[grp][0], lds[grp][1]);
+        unsigned got = 0;
+        if ((threadIdx.x & 63u) == 0u) got = atomicAdd(counter, 1u);
+        k = served + (int)__builtin_amdgcn_readfirstlane(got);
+    }
 }
 
 template <int K, int NPATH>
@@ -2484,6 +2528,30 @@ hipError_t launch_plan_patch(SgmLaunch* pairs, const PlanPatches& p, hipStream_t
     return hipGetLastError();
 }
 
+int batch_path_blocks(int group, int max_disp, int n_tasks) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    hipError_t e = hipSuccess;
+#define EGOSGM_OCC(GG)                                                                                  \
+    do {                                                                                                \
+        if (max_disp <= 64)                                                                             \
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, paths_batch_persistent_kernel<GG, 64 / GG, 4>, kBlock, 0); \
+        else if (max_disp <= 128)                                                                       \
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, paths_batch_persistent_kernel<GG, 128 / GG, 4>, kBlock, 0); \
+        else                                                                                            \
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, paths_batch_persistent_kernel<GG, 256 / GG, 4>, kBlock, 0); \
+    } while (0)
+    if (group == 16) EGOSGM_OCC(16);
+    else if (group == 32) EGOSGM_OCC(32);
+    else EGOSGM_OCC(64);
+#undef EGOSGM_OCC
+    if (e != hipSuccess || per_cu <= 0) return 0;
+    const int waves = (n_tasks + 64 / group - 1) / (64 / group);
+    return std::max(1, std::min(cus * per_cu, (waves + kBlock / 64 - 1) / (kBlock / 64)));
+}
+
 hipError_t launch_batch_stage(const BatchTables& t, int max_disp, int stage, hipStream_t s) {
     switch (stage) {
         case 0:
@@ -2493,13 +2561,21 @@ hipError_t launch_batch_stage(const BatchTables& t, int max_disp, int stage, hip
             cost_batch_kernel<<<t.host_seg_blocks, kBlock, 0, s>>>(t);
             break;
         case 2: {
+            // persistent: host_path_blocks resident blocks; else one block per 256/G tasks
             const int g = t.group;
-            const unsigned pb = (unsigned)((t.n_tasks + kBlock / g - 1) / (kBlock / g));
-#define EGOSGM_PB(GG)                                                                   \
-    do {                                                                                \
-        if (max_disp <= 64) paths_batch_kernel<GG, 64 / GG, 4><<<pb, kBlock, 0, s>>>(t);   \
-        else if (max_disp <= 128) paths_batch_kernel<GG, 128 / GG, 4><<<pb, kBlock, 0, s>>>(t); \
-        else paths_batch_kernel<GG, 256 / GG, 4><<<pb, kBlock, 0, s>>>(t);                 \
+            const unsigned pb = t.persistent ? (unsigned)t.host_path_blocks
+                                             : (unsigned)((t.n_tasks + kBlock / g - 1) / (kBlock / g));
+#define EGOSGM_PB(GG)                                                                                         \
+    do {                                                                                                      \
+        if (t.persistent) {                                                                                   \
+            if (max_disp <= 64) paths_batch_persistent_kernel<GG, 64 / GG, 4><<<pb, kBlock, 0, s>>>(t);         \
+            else if (max_disp <= 128) paths_batch_persistent_kernel<GG, 128 / GG, 4><<<pb, kBlock, 0, s>>>(t);  \
+            else paths_batch_persistent_kernel<GG, 256 / GG, 4><<<pb, kBlock, 0, s>>>(t);                       \
+        } else {                                                                                              \
+            if (max_disp <= 64) paths_batch_kernel<GG, 64 / GG, 4><<<pb, kBlock, 0, s>>>(t);                    \
+            else if (max_disp <= 128) paths_batch_kernel<GG, 128 / GG, 4><<<pb, kBlock, 0, s>>>(t);             \
+            else paths_batch_kernel<GG, 256 / GG, 4><<<pb, kBlock, 0, s>>>(t);                                  \
+        }                                                                                                     \
     } while (0)
             if (g == 16) EGOSGM_PB(16);
             else if (g == 32) EGOSGM_PB(32);

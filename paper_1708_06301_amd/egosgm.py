@@ -61,7 +61,7 @@ STAGES = ("census", "windows", "cost", "paths", "select", "warp", "kalman", "ref
           "batch_census", "batch_cost", "batch_paths", "batch_select")
 
 
-ABI_VERSION = 3   # EGOSGM_ABI_VERSION of include/egosgm.h
+ABI_VERSION = 4   # EGOSGM_ABI_VERSION of include/egosgm.h
 
 
 def lib():
@@ -107,20 +107,21 @@ class SgmDebug(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("full_group", C.c_int32), ("ragged_group", C.c_int32),
                 ("ragged_schedule", C.c_int32), ("batch_group", C.c_int32),
-                ("wide_offsets", C.c_int32)]
+                ("wide_offsets", C.c_int32), ("batch_persistent", C.c_int32)]
 
 
-DEFAULT_TUNING = dict(full_group=64, ragged_group=32, ragged_schedule=1, batch_group=16, wide_offsets=0)
+DEFAULT_TUNING = dict(full_group=64, ragged_group=32, ragged_schedule=1, batch_group=16, wide_offsets=0,
+                      batch_persistent=0)
 
 
 def set_tuning(full_group: int | None = None, ragged_group: int | None = None,
                ragged_schedule: int | None = None, batch_group: int | None = None,
-               wide_offsets: int | None = None):
+               wide_offsets: int | None = None, batch_persistent: int | None = None):
     """Sets the launch shapes; every argument left None keeps its current
     value (the library's own default until something else was set)."""
     cur = get_tuning()
     new = dict(full_group=full_group, ragged_group=ragged_group, ragged_schedule=ragged_schedule,
-               batch_group=batch_group, wide_offsets=wide_offsets)
+               batch_group=batch_group, wide_offsets=wide_offsets, batch_persistent=batch_persistent)
     t = Tuning(**{k: cur[k] if v is None else int(v) for k, v in new.items()})
     _check(lib().egosgm_set_tuning(C.byref(t)), "egosgm_set_tuning")
 
@@ -130,7 +131,7 @@ def get_tuning() -> dict:
     _check(lib().egosgm_get_tuning(C.byref(t)), "egosgm_get_tuning")
     return dict(full_group=t.full_group, ragged_group=t.ragged_group,
                 ragged_schedule=t.ragged_schedule, batch_group=t.batch_group,
-                wide_offsets=t.wide_offsets)
+                wide_offsets=t.wide_offsets, batch_persistent=t.batch_persistent)
 
 
 @dataclass

@@ -26,7 +26,7 @@ def test_every_declared_symbol_is_exported():
     lib = eg.lib()
     for n in names:
         assert hasattr(lib, n), n
-    assert eg.abi_version() == 3
+    assert eg.abi_version() == 4
 
 
 def test_workspace_sizes():
@@ -138,10 +138,11 @@ def test_tuning_validation():
     # arguments left out keep their current value (wide_offsets = 1 from above)
     eg.set_tuning(16, 64, 0, 32)
     assert eg.get_tuning() == dict(full_group=16, ragged_group=64, ragged_schedule=0, batch_group=32,
-                                   wide_offsets=1)
-    eg.set_tuning(wide_offsets=0)
+                                   wide_offsets=1, batch_persistent=0)
+    eg.set_tuning(wide_offsets=0, batch_persistent=1)
     assert eg.get_tuning() == dict(full_group=16, ragged_group=64, ragged_schedule=0, batch_group=32,
-                                   wide_offsets=0)
+                                   wide_offsets=0, batch_persistent=1)
+    assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, 1, 16, 0, 2))) == -1
     eg.set_tuning(**before)
 
 

@@ -453,12 +453,13 @@ def _same(a, b):
     return None
 
 
+@pytest.mark.parametrize("persistent", [0, 1])
 @pytest.mark.parametrize("group,n_paths", [(16, 8), (32, 8), (64, 8), (16, 4)])
-def test_plan_matches_single_pairs(group, n_paths):
-    _say("plan of 7 mixed pairs, lanes per scanline", group, "paths", n_paths)
+def test_plan_matches_single_pairs(group, n_paths, persistent):
+    _say("plan of 7 mixed pairs, lanes per scanline", group, "paths", n_paths, "persistent", persistent)
     cases = _batch_cases()
     prm = eg.MatchParams(max_disp=256, p1=9, p2=110, s_max=70, lr_tol=1, n_paths=n_paths)
-    eg.set_tuning(**{**eg.DEFAULT_TUNING, "batch_group": group})
+    eg.set_tuning(**{**eg.DEFAULT_TUNING, "batch_group": group, "batch_persistent": persistent})
     try:
         plan = eg.Plan(cases, prm)
     finally:
@@ -487,11 +488,16 @@ def test_plan_matches_single_pairs(group, n_paths):
     plan.close()
 
 
-def test_plan_graph_replays_and_window_updates():
-    _say("plan replays")
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_plan_graph_replays_and_window_updates(persistent):
+    _say("plan replays, persistent", persistent)
     cases = _batch_cases()[:4]
     prm = eg.MatchParams()
-    plan = eg.Plan(cases, prm)
+    eg.set_tuning(**{**eg.DEFAULT_TUNING, "batch_persistent": persistent})
+    try:
+        plan = eg.Plan(cases, prm)
+    finally:
+        eg.set_tuning(**eg.DEFAULT_TUNING)
     refs = [_single(c, prm) for c in cases]
     for rep in range(3):
         for o in plan.outputs:
