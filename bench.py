@@ -81,9 +81,11 @@ def measured_valu_active(w, h, D, kernel_name):
 def kernel_symbol(stage, tuning, D):
     """rocprofv3 name of the kernel a reduced frame launches for `stage`."""
     if stage == "paths":
-        if tuning["ragged_schedule"] in (4, 5, 6, 7):
+        if tuning["ragged_schedule"] in (4, 5, 6, 7, 8):
             g = 16 if tuning["ragged_schedule"] in (5, 6) else 8
             dm = 64 if D <= 64 else (128 if D <= 128 else 256)
+            if tuning["ragged_schedule"] == 8:
+                return f"sgm_paths_regroup_kernel<{dm}, 4>"
             if tuning["ragged_schedule"] >= 6:
                 return f"sgm_paths_hybrid_kernel<{g}, {dm}, 4, {1 if D <= 128 else 2}>"
             return f"sgm_paths_group_kernel<{g}, {dm}, 4>"
@@ -94,7 +96,7 @@ def kernel_symbol(stage, tuning, D):
         return (f"sgm_paths_ragged_kernel<{tuning['ragged_schedule']}, {1 if D <= 128 else 2}, {g}, "
                 f"{dr // g}, 4>")
     if stage == "select":
-        if tuning["ragged_schedule"] in (4, 5, 6, 7):
+        if tuning["ragged_schedule"] in (4, 5, 6, 7, 8):
             return "select_quad_kernel<8>"
         k = 1 if D <= 16 else (4 if D <= 64 else (8 if D <= 128 else 16))
         return f"sgm_select_kernel<16, {k}, 0, 8>"

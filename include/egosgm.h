@@ -405,7 +405,12 @@ typedef struct egosgm_tuning {
                                    narrow windows 4 lanes per pixel (images whose volumes
                                    would pass 4 GiB at w*h*(D+35) bytes fall back to 1);
                                 6, 7: the rows as in 1, the columns and diagonals as in
-                                   5 (16 lanes) or 4 (8 lanes), in the same layout          */
+                                   5 (16 lanes) or 4 (8 lanes), in the same layout;
+                                8: grouped scanlines (4 per wave, 16 lanes) whose state
+                                   stays in registers: a narrow window as one packed pair
+                                   per lane, a wide one over the full range as the
+                                   full-range kernel holds it, changes of form through
+                                   LDS; same layout                                          */
     int32_t batch_group;     /* lanes per scanline in batched plans (fixed when a plan is
                                 created): 16, 32, 64                                           */
     int32_t wide_offsets;    /* LDS scanlines of ragged windows: 0 addresses window words and

@@ -20,11 +20,11 @@ from . import egosgm as eg
 CACHE = os.environ.get("EGOSGM_TUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "egosgm_tuning.json"))
 
-# schedules 4-7 (grouped scanlines, alone or beside row scanlines) take no ragged_group
+# schedules 4-8 (grouped scanlines, alone or beside row scanlines) take no ragged_group
 CANDIDATES = ([dict(full_group=f, ragged_group=r, ragged_schedule=s)
                for f, r, s in itertools.product((16, 32, 64), (16, 32, 64), (0, 1, 2, 3))] +
               [dict(full_group=f, ragged_group=32, ragged_schedule=s)
-               for f, s in itertools.product((16, 32, 64), (4, 5, 6, 7))])
+               for f, s in itertools.product((16, 32, 64), (4, 5, 6, 7, 8))])
 
 
 def _kernel_version():

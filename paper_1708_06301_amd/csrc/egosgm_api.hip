@@ -102,7 +102,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // quad layout of the grouped kernels (stride vol_stride_q; 0 when its
 // offsets would not fit 32 bits, and those kernels are then not used).
 struct WsLayout {
-    size_t census_l, census_r, key_r, meta, cost, vol, vol_stride, vol_stride_q, total;
+    size_t census_l, census_r, key_r, meta, frame, cost, vol, vol_stride, vol_stride_q, total;
 };
 
 bool ws_layout(int w, int h, int D, WsLayout& L) {
@@ -115,7 +115,8 @@ bool ws_layout(int w, int h, int D, WsLayout& L) {
     L.census_r = L.census_l + align_up(n * sizeof(uint64_t));
     L.key_r = L.census_r + align_up(n * sizeof(uint64_t));
     L.meta = L.key_r + align_up(n * sizeof(uint32_t));
-    L.cost = L.meta + align_up(n * sizeof(uint64_t));
+    L.frame = L.meta + align_up(n * sizeof(uint64_t));
+    L.cost = L.frame + align_up(n * sizeof(uint64_t));
     L.vol = L.cost + align_up(vbytes);
     L.total = L.vol + align_up((size_t)kNumPaths * vbytes);
     return true;
@@ -177,12 +178,14 @@ int run_sgm(const uint8_t* left, const uint8_t* right, int w, int h, int pitch, 
     a.cost = base + L.cost;
     a.key_r = reinterpret_cast<uint32_t*>(base + L.key_r);
     a.meta = reinterpret_cast<uint64_t*>(base + L.meta);
+    a.frame = reinterpret_cast<uint64_t*>(base + L.frame);
     a.vol = base + L.vol;
     // grouped scanlines (schedules 4, 5) need the quad layout; where its
     // offsets would not fit 32 bits the rows-on-registers schedule runs instead
     a.quad = 0;
     if (win.lo != nullptr && a.ragged_schedule >= 4) {
-        if (L.vol_stride_q != 0) a.quad = (a.ragged_schedule == 5 || a.ragged_schedule == 6) ? 16 : 8;
+        if (L.vol_stride_q != 0)
+            a.quad = (a.ragged_schedule == 5 || a.ragged_schedule == 6 || a.ragged_schedule == 8) ? 16 : 8;
         else a.ragged_schedule = 1;
     }
     a.vol_stride = a.quad ? L.vol_stride_q : L.vol_stride;
@@ -793,7 +796,7 @@ int egosgm_set_tuning(const egosgm_tuning* t) {
     if (!t) return EGOSGM_EINVAL;
     auto ok = [](int g) { return g == 16 || g == 32 || g == 64; };
     if (!ok(t->full_group) || !ok(t->ragged_group) || !ok(t->batch_group) || t->ragged_schedule < 0 ||
-        t->ragged_schedule > 7 || (t->wide_offsets != 0 && t->wide_offsets != 1) ||
+        t->ragged_schedule > 8 || (t->wide_offsets != 0 && t->wide_offsets != 1) ||
         (t->batch_persistent != 0 && t->batch_persistent != 1))
         return EGOSGM_EINVAL;
     std::lock_guard<std::mutex> g(g_tuning_mu);

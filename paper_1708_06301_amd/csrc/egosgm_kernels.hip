@@ -1094,21 +1094,33 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_ragged_kernel(SgmLaunch a, i
 }
 
 // ------------------------------------------------------------------ grouped scanlines
-// Frame slot layout (ragged windows on the grouped kernels, frames of F
-// slots).  Pixel p owns the slots of disparities B(p) .. B(p) + S(p) - 1
-// from byte offset q(p) = (off(p) + (F + 3) p + 3) & ~3 of each volume
-// (costs and path costs), where B = lo & ~3, E = (lo + w + 3) & ~3 and S = F
-// when E - B <= F (a narrow window: one frame), else S = E - B.  q(p) is a
-// multiple of 4 and q(p+1) - q(p) >= w + F >= S (E - B <= w + 6), so a lane
-// reads and writes whole aligned pairs or quads of slots.  Slots of [B, B+S)
-// outside the window are padding: their cost byte is the marker 255 (a real
-// cost is at most 62), which the path kernels turn into +infinity, and their
-// path costs are never read as results.  A volume needs at most
-// w*h*(D+F+3) + 64 bytes.
-constexpr uint32_t kPadCost = 255;
-__device__ inline uint32_t frame_off(uint32_t off, uint32_t p, uint32_t F) {
-    return (off + (F + 3u) * p + 3u) & ~3u;
+// Frame slot layout (ragged windows on the grouped kernels, frames of F <= 32
+// slots).  Pixel p with window [lo, lo+w) owns the slots of disparities
+// base .. base + span - 1 from byte offset q(p) = (off(p) + 35 p + 3) & ~3 of
+// each volume (costs and path costs):
+//  - narrow (the window and its two neighbours, [lo-1, lo+w], fit F slots
+//    from base = (lo-1) & ~3, or 0 when lo = 0): one frame, span = F;
+//  - wide (otherwise): base = lo & ~15, span = roundup16(lo + w) - base.
+// q(p) is a multiple of 4 and q(p+1) - q(p) >= w + 32 >= span (a wide span is
+// at most w + 30), so a lane reads and writes whole aligned pairs, quads or
+// 16-slot pieces.  Slots of [base, base+span) outside the window are
+// padding: their cost byte is the marker 255 (a real cost is at most 62),
+// which the path kernels turn into +infinity, and their path costs are
+// never read as results.  The window word holds the address of slot lo,
+// q(p) + lo - base, as in the ragged layout.  A volume needs at most
+// w*h*(D+35) + 64 bytes.
+struct Frame {
+    int base, span;
+    bool narrow;
+};
+__device__ inline Frame frame_of(int lo, int w, int F) {
+    const int bn = lo > 0 ? ((lo - 1) & ~3) : 0;
+    if (lo - bn + w + 1 <= F) return Frame{bn, F, true};
+    const int bw = lo & ~15;
+    return Frame{bw, ((lo + w + 15) & ~15) - bw, false};
 }
+__device__ inline uint32_t frame_off(uint32_t off, uint32_t p) { return (off + 35u * p + 3u) & ~3u; }
+constexpr uint32_t kPadCost = 255;
 // Costs of two slots (bytes b0 b1 of v, or b2 b3) as a packed pair, with the
 // padding marker 255 raised to 255 + 0x4000: a slot carrying it stays above
 // any in-window path cost + P2 (< 0x4000) and so acts as +infinity, and
@@ -1261,8 +1273,9 @@ __device__ inline void group_scanlines(const SgmLaunch& a, const GroupTasks& t, 
     uint32_t wcs[PF][WV];   // wide: this lane's share of its group's pixel's costs
     auto load_costs = [&](int s, uint64_t mw, int i) {
         const int lo = meta_lo(mw), w = meta_w(mw);
-        const uint32_t o = meta_off(mw) - (uint32_t)(lo & 3);   // the frame's first slot
-        const bool wide = i < len && ((lo + w + 3) & ~3) - (lo & ~3) > F;
+        const Frame fr = frame_of(lo, w, F);
+        const uint32_t o = meta_off(mw) - (uint32_t)(lo - fr.base);   // the frame's first slot
+        const bool wide = i < len && !fr.narrow;
         cst[s] = __builtin_amdgcn_raw_buffer_load_b16(cbuf, o + 2u * (uint32_t)l, 0, 0);
         load_dwords<WV>(cbuf, wide ? o + 4u * WV * (uint32_t)l : kDropWide, wcs[s]);
     };
@@ -1282,7 +1295,7 @@ __device__ inline void group_scanlines(const SgmLaunch& a, const GroupTasks& t, 
         const int lo = meta_lo(mm[0]), w = meta_w(mm[0]);
         for (int s = l; s < w; s += G) rows[g][1][lo + s + 2] = 0;
         pmode = 2;
-        pb = lo & ~3;
+        pb = lo & ~3;   // the written entries' quads
         pe = (lo + w + 3) & ~3;
     }
     lds_order();
@@ -1291,11 +1304,12 @@ __device__ inline void group_scanlines(const SgmLaunch& a, const GroupTasks& t, 
     auto step = [&](int i, int ti, int tc, int par) {
         const uint64_t mt = mm[ti];
         const int lo = meta_lo(mt), w = meta_w(mt);
-        const uint32_t o = meta_off(mt) - (uint32_t)(lo & 3);   // the frame's first slot
+        const Frame fr = frame_of(lo, w, F);
+        const uint32_t o = meta_off(mt) - (uint32_t)(lo - fr.base);   // the frame's first slot
         const bool act = i < len;
-        const int B = lo & ~3;
-        const int span = ((lo + w + 3) & ~3) - B;
-        const bool nar = span <= F;
+        const int B = fr.base;
+        const int span = fr.span;
+        const bool nar = fr.narrow;
         uint32_t* prv = myrow[par ^ 1];
         uint32_t* cur = myrow[par];
         int m_new = m;
@@ -1329,7 +1343,8 @@ __device__ inline void group_scanlines(const SgmLaunch& a, const GroupTasks& t, 
             const uint32_t o_g = (uint32_t)__builtin_amdgcn_readlane((int)o, bit);
             const int m_g = __builtin_amdgcn_readlane(m, bit);
             const int pm_g = __builtin_amdgcn_readlane(pmode, bit);
-            const int Bw = lo_g & ~3, Ew = (lo_g + w_g + 3) & ~3;
+            const Frame fw = frame_of(lo_g, w_g, F);
+            const int Bw = fw.base, Ew = fw.base + fw.span;
             const uint32_t* prg = reinterpret_cast<const uint32_t*>(rows[gg][par ^ 1]);
             uint32_t* cug = reinterpret_cast<uint32_t*>(rows[gg][par]);
             const int d = Bw + 4 * lane;
@@ -1409,8 +1424,14 @@ __device__ inline void group_scanlines(const SgmLaunch& a, const GroupTasks& t, 
 
 template <int G, int DMAX, int PF>
 __global__ __launch_bounds__(kBlock) void sgm_paths_group_kernel(SgmLaunch a, GroupTasks t) {
-    group_scanlines<G, DMAX, PF>(a, t, (int)blockIdx.x * (kBlock / 64) +
-                                           __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)));
+    const int gw = (int)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    // the rows (the first waves, 2*H-step... W-step chains) issue first when
+    // their SIMD is shared: they set the kernel's length
+    if (gw < t.wave_start[t.first_dir + 2 <= t.n_dirs && t.first_dir == 0 ? 2 : t.first_dir])
+        __builtin_amdgcn_s_setprio(2);
+    else
+        __builtin_amdgcn_s_setprio(1);
+    group_scanlines<G, DMAX, PF>(a, t, gw);
 }
 
 // Hybrid: blocks below n_row_blocks walk the image rows, one wave each on
@@ -1429,6 +1450,214 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_hybrid_kernel(SgmLaunch a, G
     } else {
         __builtin_amdgcn_s_setprio(1);
         group_scanlines<G, DMAX, PF>(a, t, ((int)blockIdx.x - n_row_blocks) * (kBlock / 64) + wv);
+    }
+}
+
+// Register-resident grouped scanlines (ragged windows, frame layout with
+// F = 32; schedule 8).  A wave walks four scanlines of one direction, lane
+// group g (16 lanes, one DPP row) owning scanline g.  The previous pixel's
+// path costs stay in registers, in one of two forms:
+//  - narrow: one packed pair per lane, slots base + 2l, base + 2l + 1 of the
+//    pixel's frame (the window and its two neighbours lie inside it, so the
+//    frame edges never need a value from outside);
+//  - wide: NPW = DMAX/32 packed pairs per lane, the absolute slots
+//    2*NPW*l .. 2*NPW*l + 2*NPW - 1 (the full range, as the full-range
+//    kernel holds it), +infinity outside the window.
+// A step is the recurrence on that form: the d-1 / d+1 neighbours are
+// alignbits within a lane plus one DPP row shift across lanes, the minimum
+// is a DPP row reduction.  Narrow groups update one register, wide groups
+// NPW registers, all wide groups of the wave in the same pass.  A change of
+// form goes through a per-group LDS row (absolute disparity, +infinity
+// except during the change); a narrow frame that moves is shifted by a lane
+// permute.  Costs: narrow pairs, and a wide pixel's 2*NPW bytes per lane
+// (the out-of-span lanes read a run of padding markers at the end of the
+// cost volume), prefetched PF steps ahead; window words 2*PF steps ahead.
+// The first step uses a zero predecessor, so it gives L = C.
+template <int DMAX, int PF>
+__global__ __launch_bounds__(kBlock) void sgm_paths_regroup_kernel(SgmLaunch a, GroupTasks t) {
+    constexpr int G = 16, NG = 4, F = 32;
+    constexpr int NPW = DMAX / 32;   // wide registers per lane
+    constexpr int WD = NPW / 2;      // wide cost dwords per lane
+    constexpr int RM = 2 * PF;
+    constexpr int ROWD = DMAX / 2 + 16;   // LDS row dwords (entries 0 .. DMAX+31)
+    static_assert(NPW == 2 || NPW == 4 || NPW == 8, "DMAX 64, 128 or 256");
+    __shared__ __attribute__((aligned(16))) uint32_t rows_all[kBlock / 64][NG][ROWD];
+    const int lane = (int)(threadIdx.x & 63u);
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int gw = (int)blockIdx.x * (kBlock / 64) + wv;
+    if (gw >= t.wave_start[t.n_dirs]) return;
+    int dir = t.first_dir;
+    while (gw >= t.wave_start[dir + 1]) ++dir;
+    const int wl = gw - t.wave_start[dir];
+    const int nwav = t.wave_start[dir + 1] - t.wave_start[dir];
+    const int g = lane / G, l = lane % G;
+    const int j = (t.strided && dir < 4) ? g * nwav + wl : wl * NG + g;
+    const bool has = j < t.n_scan[dir];
+    Scan sc{dir, 0, 0, 0};
+    if (has) sc = scan_of(t.first_task[dir] + j, a.w, a.h);
+    const int len = has ? sc.len : 0;
+    int nmax = 0;
+#pragma unroll
+    for (int k = 0; k < NG; ++k) nmax = max(nmax, __builtin_amdgcn_readlane(len, k * G));
+    const int dp = sc.dp, p0 = sc.p0;
+    const int p_last = len > 0 ? p0 + (len - 1) * dp : p0;
+
+    const uint32_t cap = (uint32_t)a.vol_stride;
+    const uint32_t pad_run = cap - 64u;   // 64 padding markers written by the cost pass
+    const __amdgpu_buffer_rsrc_t cbuf = byte_buffer(a.cost, cap);
+    const __amdgpu_buffer_rsrc_t vbuf = byte_buffer(a.vol + (size_t)dir * a.vol_stride, cap);
+    const __amdgpu_buffer_rsrc_t mbuf = byte_buffer(a.frame, (uint32_t)a.w * (uint32_t)a.h * 8u);
+    const uint32_t p1pk = (uint32_t)a.p1 * 0x10001u;
+    const int p2 = a.p2;
+    uint32_t* row = rows_all[wv][g];
+
+    uint64_t mm[RM];
+    const int q_lo = 8 * min(p0, p_last), q_hi = 8 * max(p0, p_last), dq = 8 * dp;
+    int q_next = 8 * p0;
+    auto next_meta = [&](int k) {
+        mm[k] = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(mbuf, min(max(q_next, q_lo), q_hi), 0, 0));
+        q_next += dq;
+    };
+#pragma unroll
+    for (int k = 0; k < RM; ++k) next_meta(k);
+
+    uint32_t cst[PF];       // narrow: this lane's two cost bytes
+    uint32_t wcs[PF][WD];   // wide: this lane's 2*NPW cost bytes
+    // each pixel's frame, decoded once when its costs are requested: the
+    // frame's first slot offset, and base | form << 16 (form: 0 inactive,
+    // 1 narrow, 2 wide) | (this lane's wide slots inside the span) << 18
+    uint32_t f_off[PF], f_inf[PF];
+    const int d0 = 2 * NPW * l;   // this lane's first wide slot
+    // mw: the pixel's frame word (frame offset | base << 32 | form << 48 | span/16 << 50)
+    auto load_costs = [&](int s, uint64_t mw, int i) {
+        const uint32_t o = (uint32_t)mw, hi = (uint32_t)(mw >> 32);
+        const int base = (int)(hi & 0xffffu);
+        const uint32_t form = (hi >> 16) & 3u;
+        // wide and active: this lane inside the span (a finished or empty
+        // scanline must never store: an empty one sits on pixel 0)
+        const bool in = i < len && (unsigned)(d0 - base) < ((hi >> 18) << 4);
+        f_off[s] = o;
+        f_inf[s] = (hi & 0x3ffffu & (i < len ? 0xffffffffu : 0xffffu)) | ((uint32_t)in << 18);
+        cst[s] = __builtin_amdgcn_raw_buffer_load_b16(cbuf, o + 2u * (uint32_t)l, 0, 0);
+        load_dwords<WD>(cbuf, in && form == 2u ? o + (uint32_t)(d0 - base) : pad_run, wcs[s]);
+    };
+#pragma unroll
+    for (int k = 0; k < PF; ++k) load_costs(k, mm[k], k);
+
+    for (int e = l; e < ROWD; e += G) row[e] = kInfPk;
+    lds_order();
+
+    // state: the first step's predecessor is zero everywhere (L = C)
+    uint32_t N = 0;
+    uint32_t Wr[NPW];
+#pragma unroll
+    for (int k = 0; k < NPW; ++k) Wr[k] = 0;
+    int m = 0;
+    int mode = (int)((f_inf[0] >> 16) & 3u), Bp = (int)(f_inf[0] & 0xffffu);   // step 0: no change of form
+
+    auto step = [&](int i, int ti, int tc) {
+        const uint32_t o = f_off[tc];
+        const int fbase = (int)(f_inf[tc] & 0xffffu);
+        const int mc = (int)((f_inf[tc] >> 16) & 3u);
+        const bool act = mc != 0;
+        const bool in = (f_inf[tc] >> 18) & 1u;
+        // changes of form or frame (the whole wave takes this branch only when a
+        // group needs it)
+        if (__builtin_amdgcn_ballot_w64(act && (mode != mc || (mc == 1 && fbase != Bp))) != 0) {
+            const bool shift = mode == 1 && mc == 1 && fbase != Bp;
+            const bool n2w = mode == 1 && mc == 2;
+            const bool w2n = mode == 2 && mc == 1;
+            const int src = l + (shift ? (fbase - Bp) >> 1 : 0);
+            const uint32_t v = (uint32_t)__builtin_amdgcn_ds_bpermute(((lane & ~15) + (src & 15)) << 2, (int)N);
+            if (shift) N = (unsigned)src < 16u ? v : kInfPk;
+            if (n2w) row[(Bp >> 1) + l] = N;
+            if (w2n) {
+#pragma unroll
+                for (int k = 0; k < NPW; ++k) row[NPW * l + k] = Wr[k];
+            }
+            lds_order();
+            if (n2w) {
+#pragma unroll
+                for (int k = 0; k < NPW; ++k) Wr[k] = row[NPW * l + k];
+            }
+            if (w2n) N = row[(fbase >> 1) + l];
+            lds_order();
+            if (n2w) row[(Bp >> 1) + l] = kInfPk;
+            if (w2n) {
+#pragma unroll
+                for (int k = 0; k < NPW; ++k) row[NPW * l + k] = kInfPk;
+            }
+            lds_order();
+        }
+        const uint32_t m2 = (uint32_t)(m + p2) * 0x10001u, mp = (uint32_t)m * 0x10001u;
+        int m_new = m;
+        if (mc == 1) {
+            const uint32_t prv = __builtin_amdgcn_update_dpp(kInfPk, N, 0x111, 0xF, 0xF, false);   // row_shr:1
+            const uint32_t nxt = __builtin_amdgcn_update_dpp(kInfPk, N, 0x101, 0xF, 0xF, false);   // row_shl:1
+            const uint32_t tt = pk_min(pk_min(pk_add(pk_min(align16(N, prv), align16(nxt, N)), p1pk), N), m2);
+            N = pk_sub(pk_add(pad_inf(bytes01(cst[tc])), tt), mp);
+            m_new = row_min16((int)min(N & 0xffffu, N >> 16));
+        }
+        __builtin_amdgcn_raw_buffer_store_b16((uint16_t)__builtin_amdgcn_perm(0u, N, 0x0C0C0200u), vbuf,
+                                              mc == 1 ? o + 2u * (uint32_t)l : kDropWide, 0, 0);
+        if (__builtin_amdgcn_ballot_w64(mc == 2) != 0) {
+            if (mc == 2) {
+                const uint32_t prv = __builtin_amdgcn_update_dpp(kInfPk, Wr[NPW - 1], 0x111, 0xF, 0xF, false);
+                const uint32_t nxt = __builtin_amdgcn_update_dpp(kInfPk, Wr[0], 0x101, 0xF, 0xF, false);
+                uint32_t Ln[NPW];
+#pragma unroll
+                for (int k = 0; k < NPW; ++k) {
+                    const uint32_t lm1 = align16(Wr[k], k > 0 ? Wr[k - 1] : prv);
+                    const uint32_t lp1 = align16(k + 1 < NPW ? Wr[k + 1] : nxt, Wr[k]);
+                    const uint32_t tt = pk_min(pk_min(pk_add(pk_min(lm1, lp1), p1pk), Wr[k]), m2);
+                    const uint32_t c = (k & 1) ? bytes23(wcs[tc][k >> 1]) : bytes01(wcs[tc][k >> 1]);
+                    Ln[k] = pk_sub(pk_add(pad_inf(c), tt), mp);
+                }
+                uint32_t mv = Ln[0];
+#pragma unroll
+                for (int k = 0; k < NPW; ++k) {
+                    Wr[k] = Ln[k];
+                    mv = pk_min(mv, Ln[k]);
+                }
+                m_new = row_min16((int)min(mv & 0xffffu, mv >> 16));
+            }
+            uint32_t pk[WD];
+#pragma unroll
+            for (int q = 0; q < WD; ++q) pk[q] = pack4(Wr[2 * q], Wr[2 * q + 1]);
+            const uint32_t at = in ? o + (uint32_t)(d0 - fbase) : kDropWide;
+            if constexpr (WD == 1) {
+                __builtin_amdgcn_raw_buffer_store_b32(pk[0], vbuf, at, 0, 0);
+            } else if constexpr (WD == 2) {
+                __builtin_amdgcn_raw_buffer_store_b64(u32x2{pk[0], pk[1]}, vbuf, at, 0, 0);
+            } else {
+#pragma unroll
+                for (int q = 0; q < WD / 4; ++q)
+                    __builtin_amdgcn_raw_buffer_store_b128(u32x4{pk[4 * q], pk[4 * q + 1], pk[4 * q + 2], pk[4 * q + 3]},
+                                                           vbuf, at + 16u * q, 0, 0);
+            }
+        }
+        m = m_new;
+        if (act) {
+            mode = mc;
+            Bp = fbase;
+        }
+    };
+
+    int i = 0;
+    for (; i + RM <= nmax; i += RM) {
+#pragma unroll
+        for (int u = 0; u < RM; ++u) {
+            step(i + u, u, u % PF);
+            load_costs(u % PF, mm[(u + PF) % RM], i + u + PF);
+            next_meta(u);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < RM; ++u) {
+        if (i + u < nmax) {
+            step(i + u, u, u % PF);
+            if (u + PF < RM) load_costs(u % PF, mm[u + PF], i + u + PF);
+        }
     }
 }
 
@@ -1457,16 +1686,18 @@ __global__ __launch_bounds__(kBlock) void cost_frame_kernel(SgmLaunch a) {
             const int lo = gptr(a.win.lo)[p], hi = gptr(a.win.hi)[p];
             const uint32_t off = gptr(a.win.off)[p];
             const int w = hi - lo + 1;
-            const uint32_t q = frame_off(off, (uint32_t)p, F);
-            // the window word's offset addresses slot lo (q + d - B for slot d),
-            // as in the ragged layout, so every path kernel can read this layout
-            gptr(a.meta)[p] = pack_meta(q + (uint32_t)(lo & 3), lo, w);
-            const int span = ((lo + w + 3) & ~3) - (lo & ~3);
-            s_b[i] = lo & ~3;
+            const uint32_t q = frame_off(off, (uint32_t)p);
+            const Frame fr = frame_of(lo, w, (int)F);
+            // the window word's offset addresses slot lo (q + d - base for slot
+            // d), as in the ragged layout, so every path kernel can read it
+            gptr(a.meta)[p] = pack_meta(q + (uint32_t)(lo - fr.base), lo, w);
+            gptr(a.frame)[p] = (uint64_t)q | ((uint64_t)fr.base << 32) | ((uint64_t)(fr.narrow ? 1 : 2) << 48) |
+                               ((uint64_t)(fr.narrow ? 0 : fr.span >> 4) << 50);
+            s_b[i] = fr.base;
             s_lo[i] = lo;
             s_w[i] = w;
             s_q[i] = q;
-            nq = (uint32_t)((span <= (int)F ? (int)F : span) >> 2);
+            nq = (uint32_t)(fr.span >> 2);
         }
         uint32_t inc = nq;
 #pragma unroll
@@ -1485,6 +1716,10 @@ __global__ __launch_bounds__(kBlock) void cost_frame_kernel(SgmLaunch a) {
     __syncthreads();
     const uint32_t total = s_pre[kSeg];
     gmem<uint32_t>* cost = reinterpret_cast<gmem<uint32_t>*>(gptr(a.cost));
+    // a run of 64 padding markers at the end of the volume, which lanes of
+    // a wide pixel outside its span read as their costs
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 16)
+        cost[((uint32_t)a.vol_stride - 64u) / 4u + threadIdx.x] = 0xffffffffu;
     for (uint32_t k = threadIdx.x; k < total; k += kBlock) {
         int i = 0;
 #pragma unroll
@@ -1676,11 +1911,10 @@ __global__ __launch_bounds__(kBlock) void select_quad_kernel(SgmLaunch a) {
 __global__ __launch_bounds__(kBlock) void copy_quad_slots_kernel(SgmLaunch a, const uint8_t* src, size_t src_stride,
                                                                  uint8_t* dst, size_t dst_stride, int nvol) {
     const int n = a.w * a.h;
-    const uint32_t F = 2u * (uint32_t)a.quad;
     for (int p = (int)(blockIdx.x * kBlock + threadIdx.x); p < n; p += (int)(gridDim.x * kBlock)) {
         const int lo = a.win.lo[p], w = a.win.hi[p] - lo + 1;
         const uint32_t off = a.win.off[p];
-        const uint32_t q = frame_off(off, (uint32_t)p, F) + (uint32_t)(lo & 3);
+        const uint32_t q = meta_off(a.meta[p]);   // slot lo
         for (int v = 0; v < nvol; ++v)
             for (int s = 0; s < w; ++s) dst[v * dst_stride + off + s] = src[v * src_stride + q + s];
     }
@@ -2376,8 +2610,9 @@ hipError_t launch_sgm_paths(const SgmLaunch& a, hipStream_t s) {
     const int g = a.ragged_group;
     const int sched = a.ragged_schedule;
     if (a.quad) {
-        // schedules 6, 7: the rows on windowed registers, the rest grouped
-        const bool hybrid = sched >= 6;
+        // schedules 6, 7: the rows on windowed registers, the rest grouped;
+        // 8: grouped scanlines with register-resident state (16 lanes)
+        const bool hybrid = sched == 6 || sched == 7;
         const int G = a.quad, NG = 64 / G;
         GroupTasks t{};
         t.first_dir = hybrid ? 2 : 0;
@@ -2395,6 +2630,12 @@ hipError_t launch_sgm_paths(const SgmLaunch& a, hipStream_t s) {
             t.wave_start[r + 1] = t.wave_start[r] + (ns[r] + NG - 1) / NG;
         }
         const unsigned nb = (unsigned)((t.wave_start[t.n_dirs] + kBlock / 64 - 1) / (kBlock / 64));
+        if (sched == 8) {
+            if (D <= 64) sgm_paths_regroup_kernel<64, 4><<<nb, kBlock, 0, s>>>(a, t);
+            else if (D <= 128) sgm_paths_regroup_kernel<128, 4><<<nb, kBlock, 0, s>>>(a, t);
+            else sgm_paths_regroup_kernel<256, 4><<<nb, kBlock, 0, s>>>(a, t);
+            return hipGetLastError();
+        }
         if (hybrid) {
             const int nrb = (2 * H + kBlock / 64 - 1) / (kBlock / 64);
 #define EGOSGM_HYB(GG)                                                                                     \

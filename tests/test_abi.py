@@ -128,9 +128,9 @@ def test_tuning_validation():
     assert lib.egosgm_set_tuning(C.byref(bad)) == -1
     assert lib.egosgm_set_tuning(None) == -1
     assert eg.get_tuning() == before
-    assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, 8, 16))) == -1
+    assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, 9, 16))) == -1
     assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, -1, 16))) == -1
-    assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, 7, 16))) == 0
+    assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, 8, 16))) == 0
     assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, 3, 16))) == 0
     assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, 0, 8))) == -1
     assert lib.egosgm_set_tuning(C.byref(eg.Tuning(32, 32, 1, 16, 2))) == -1

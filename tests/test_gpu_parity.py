@@ -104,7 +104,7 @@ def _random_windows(w, h, D, seed, rmax=6, frac_full=0.1, kind="random"):
     return d, p
 
 
-@pytest.mark.parametrize("sched", [0, 1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("sched", [0, 1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("w,h,D,seed,kind,rmax", [
     (37, 19, 16, 1, "random", 6), (64, 20, 64, 2, "random", 6), (91, 27, 128, 3, "random", 6),
     (33, 5, 256, 4, "random", 6), (150, 23, 128, 5, "smooth", 6), (97, 17, 256, 6, "wide", 60),
@@ -129,7 +129,7 @@ def test_sgm_reduced_ragged(w, h, D, seed, kind, rmax, sched):
     _check_sgm(g, o, int(wo[2][-1]))
 
 
-@pytest.mark.parametrize("ragged,sched", [(False, 1), (True, 1), (True, 4), (True, 5), (True, 6), (True, 7)])
+@pytest.mark.parametrize("ragged,sched", [(False, 1), (True, 1), (True, 4), (True, 5), (True, 6), (True, 7), (True, 8)])
 @pytest.mark.parametrize("D", [64, 100, 128])
 def test_four_path_variant(ragged, sched, D):
     """n_paths = 4: directions 0-3 only (path volumes 0-3 and S bit-exact)."""
@@ -162,7 +162,7 @@ def test_four_path_variant(ragged, sched, D):
         assert np.array_equal(paths[k, :total].astype(np.int32), o["paths"][k]), f"path {k}"
 
 
-@pytest.mark.parametrize("sched", [1, 4, 6])
+@pytest.mark.parametrize("sched", [1, 4, 6, 8])
 @pytest.mark.parametrize("s_max", [0, 7, 80, 600])
 @pytest.mark.parametrize("rmax,D", [(7, 64), (12, 128), (40, 128)])
 def test_selection_walk_every_pixel(s_max, rmax, D, sched):
@@ -411,7 +411,7 @@ def test_tuning_never_changes_results(D):
     prm = eg.MatchParams(max_disp=D)
     try:
         # wide_offsets = 1 runs the 64-bit addressing that images of 2^27 pixels take
-        for fg, rg, pr, wo_ in itertools.product((16, 32, 64), (16, 32, 64), (0, 1, 2, 3, 4, 5, 6, 7), (0, 1)):
+        for fg, rg, pr, wo_ in itertools.product((16, 32, 64), (16, 32, 64), (0, 1, 2, 3, 4, 5, 6, 7, 8), (0, 1)):
             eg.set_tuning(fg, rg, pr, wide_offsets=wo_)
             a = eg.sgm_full(L, R, prm)
             b = eg.sgm_reduced(L, R, lo, hi, off, prm)
