@@ -53,7 +53,7 @@ struct SgmLaunch {
     uint64_t* meta;          // w*h packed windows (offset | lo << 32 | width << 48), written by
                              // the cost pass for ragged windows, read by the path kernels
     uint64_t* frame;         // w*h frame words of the frame layout (frame offset | base << 32 |
-                             // form << 48 | span/16 << 50), written by the frame cost pass
+                             // form << 48 | span << 50), written by the frame cost pass
     uint8_t* vol;            // 8 path volumes, direction-major
     size_t vol_stride;       // entries per direction block (w*h*D)
     int16_t* disp_wta;

@@ -1500,49 +1500,48 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_regroup_kernel(SgmLaunch a, 
 #pragma unroll
     for (int k = 0; k < NG; ++k) nmax = max(nmax, __builtin_amdgcn_readlane(len, k * G));
     const int dp = sc.dp, p0 = sc.p0;
-    const int p_last = len > 0 ? p0 + (len - 1) * dp : p0;
 
     const uint32_t cap = (uint32_t)a.vol_stride;
     const uint32_t pad_run = cap - 64u;   // 64 padding markers written by the cost pass
     const __amdgpu_buffer_rsrc_t cbuf = byte_buffer(a.cost, cap);
     const __amdgpu_buffer_rsrc_t vbuf = byte_buffer(a.vol + (size_t)dir * a.vol_stride, cap);
     const __amdgpu_buffer_rsrc_t mbuf = byte_buffer(a.frame, (uint32_t)a.w * (uint32_t)a.h * 8u);
-    const uint32_t p1pk = (uint32_t)a.p1 * 0x10001u;
-    const int p2 = a.p2;
+    const uint32_t p1pk = (uint32_t)a.p1 * 0x10001u, p2pk = (uint32_t)a.p2 * 0x10001u;
     uint32_t* row = rows_all[wv][g];
 
+    // window words of pixels 0 .. len-1; past the end of the scanline the
+    // load is out of range and returns zero (form 0: inactive, no span), so
+    // a finished or empty scanline never stores (an empty one sits on pixel 0)
     uint64_t mm[RM];
-    const int q_lo = 8 * min(p0, p_last), q_hi = 8 * max(p0, p_last), dq = 8 * dp;
-    int q_next = 8 * p0;
-    auto next_meta = [&](int k) {
-        mm[k] = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(mbuf, min(max(q_next, q_lo), q_hi), 0, 0));
+    const uint32_t dq = 8u * (uint32_t)dp;
+    uint32_t q_next = 8u * (uint32_t)p0;
+    auto next_meta = [&](int k, int i) {
+        mm[k] = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(mbuf, i < len ? q_next : kDropWide, 0, 0));
         q_next += dq;
     };
 #pragma unroll
-    for (int k = 0; k < RM; ++k) next_meta(k);
+    for (int k = 0; k < RM; ++k) next_meta(k, k);
 
     uint32_t cst[PF];       // narrow: this lane's two cost bytes
     uint32_t wcs[PF][WD];   // wide: this lane's 2*NPW cost bytes
     // each pixel's frame, decoded once when its costs are requested: the
     // frame's first slot offset, and base | form << 16 (form: 0 inactive,
-    // 1 narrow, 2 wide) | (this lane's wide slots inside the span) << 18
+    // 1 narrow, 2 wide) | span << 18 | (this lane's wide slots inside the span) << 31
     uint32_t f_off[PF], f_inf[PF];
     const int d0 = 2 * NPW * l;   // this lane's first wide slot
-    // mw: the pixel's frame word (frame offset | base << 32 | form << 48 | span/16 << 50)
-    auto load_costs = [&](int s, uint64_t mw, int i) {
+    // mw: the pixel's frame word (frame offset | base << 32 | form << 48 | span << 50,
+    // span 0 for a narrow frame)
+    auto load_costs = [&](int s, uint64_t mw) {
         const uint32_t o = (uint32_t)mw, hi = (uint32_t)(mw >> 32);
         const int base = (int)(hi & 0xffffu);
-        const uint32_t form = (hi >> 16) & 3u;
-        // wide and active: this lane inside the span (a finished or empty
-        // scanline must never store: an empty one sits on pixel 0)
-        const bool in = i < len && (unsigned)(d0 - base) < ((hi >> 18) << 4);
+        const bool in = (unsigned)(d0 - base) < (hi >> 18);
         f_off[s] = o;
-        f_inf[s] = (hi & 0x3ffffu & (i < len ? 0xffffffffu : 0xffffu)) | ((uint32_t)in << 18);
+        f_inf[s] = hi | ((uint32_t)in << 31);
         cst[s] = __builtin_amdgcn_raw_buffer_load_b16(cbuf, o + 2u * (uint32_t)l, 0, 0);
-        load_dwords<WD>(cbuf, in && form == 2u ? o + (uint32_t)(d0 - base) : pad_run, wcs[s]);
+        load_dwords<WD>(cbuf, in ? o + (uint32_t)(d0 - base) : pad_run, wcs[s]);
     };
 #pragma unroll
-    for (int k = 0; k < PF; ++k) load_costs(k, mm[k], k);
+    for (int k = 0; k < PF; ++k) load_costs(k, mm[k]);
 
     for (int e = l; e < ROWD; e += G) row[e] = kInfPk;
     lds_order();
@@ -1560,10 +1559,11 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_regroup_kernel(SgmLaunch a, 
         const int fbase = (int)(f_inf[tc] & 0xffffu);
         const int mc = (int)((f_inf[tc] >> 16) & 3u);
         const bool act = mc != 0;
-        const bool in = (f_inf[tc] >> 18) & 1u;
+        const bool in = f_inf[tc] >> 31;
+        const bool nar = mc == 1;
         // changes of form or frame (the whole wave takes this branch only when a
-        // group needs it)
-        if (__builtin_amdgcn_ballot_w64(act && (mode != mc || (mc == 1 && fbase != Bp))) != 0) {
+        // group needs it); bitwise operators keep the test free of branches
+        if (__builtin_amdgcn_ballot_w64(act & ((mode != mc) | (nar & (fbase != Bp)))) != 0) {
             const bool shift = mode == 1 && mc == 1 && fbase != Bp;
             const bool n2w = mode == 1 && mc == 2;
             const bool w2n = mode == 2 && mc == 1;
@@ -1589,37 +1589,53 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_regroup_kernel(SgmLaunch a, 
             }
             lds_order();
         }
-        const uint32_t m2 = (uint32_t)(m + p2) * 0x10001u, mp = (uint32_t)m * 0x10001u;
-        int m_new = m;
-        if (mc == 1) {
+        const uint32_t mp = __builtin_amdgcn_perm((uint32_t)m, (uint32_t)m, 0x05040100u);   // m in both halves
+        const uint32_t m2 = pk_add(mp, p2pk);
+        // the narrow update runs in every lane (one basic block with the
+        // prefetches around it) and is kept where the pixel is narrow
+        int m_new;
+        {
+            // the last slot of a narrow frame is always padding, so what the
+            // group's last lane receives from above does not matter (the first
+            // slot is padding too, except in a frame that starts at d = 0)
             const uint32_t prv = __builtin_amdgcn_update_dpp(kInfPk, N, 0x111, 0xF, 0xF, false);   // row_shr:1
-            const uint32_t nxt = __builtin_amdgcn_update_dpp(kInfPk, N, 0x101, 0xF, 0xF, false);   // row_shl:1
+            const uint32_t nxt = __builtin_amdgcn_mov_dpp(N, 0x101, 0xF, 0xF, true);                // row_shl:1
             const uint32_t tt = pk_min(pk_min(pk_add(pk_min(align16(N, prv), align16(nxt, N)), p1pk), N), m2);
-            N = pk_sub(pk_add(pad_inf(bytes01(cst[tc])), tt), mp);
-            m_new = row_min16((int)min(N & 0xffffu, N >> 16));
+            const uint32_t Nn = pk_sub(pk_add(pad_inf(bytes01(cst[tc])), tt), mp);
+            const int mn = row_min16((int)min(Nn & 0xffffu, Nn >> 16));
+            N = nar ? Nn : N;
+            m_new = nar ? mn : m;
         }
         __builtin_amdgcn_raw_buffer_store_b16((uint16_t)__builtin_amdgcn_perm(0u, N, 0x0C0C0200u), vbuf,
-                                              mc == 1 ? o + 2u * (uint32_t)l : kDropWide, 0, 0);
+                                              nar ? o + 2u * (uint32_t)l : kDropWide, 0, 0);
         if (__builtin_amdgcn_ballot_w64(mc == 2) != 0) {
             if (mc == 2) {
                 const uint32_t prv = __builtin_amdgcn_update_dpp(kInfPk, Wr[NPW - 1], 0x111, 0xF, 0xF, false);
                 const uint32_t nxt = __builtin_amdgcn_update_dpp(kInfPk, Wr[0], 0x101, 0xF, 0xF, false);
+                // one operation over all registers at a time: no packed
+                // operation waits on the one just before it
                 uint32_t Ln[NPW];
 #pragma unroll
-                for (int k = 0; k < NPW; ++k) {
-                    const uint32_t lm1 = align16(Wr[k], k > 0 ? Wr[k - 1] : prv);
-                    const uint32_t lp1 = align16(k + 1 < NPW ? Wr[k + 1] : nxt, Wr[k]);
-                    const uint32_t tt = pk_min(pk_min(pk_add(pk_min(lm1, lp1), p1pk), Wr[k]), m2);
-                    const uint32_t c = (k & 1) ? bytes23(wcs[tc][k >> 1]) : bytes01(wcs[tc][k >> 1]);
-                    Ln[k] = pk_sub(pk_add(pad_inf(c), tt), mp);
-                }
-                uint32_t mv = Ln[0];
+                for (int k = 0; k < NPW; ++k)
+                    Ln[k] = pk_min(align16(Wr[k], k > 0 ? Wr[k - 1] : prv), align16(k + 1 < NPW ? Wr[k + 1] : nxt, Wr[k]));
 #pragma unroll
-                for (int k = 0; k < NPW; ++k) {
-                    Wr[k] = Ln[k];
-                    mv = pk_min(mv, Ln[k]);
+                for (int k = 0; k < NPW; ++k) Ln[k] = pk_add(Ln[k], p1pk);
+#pragma unroll
+                for (int k = 0; k < NPW; ++k) Ln[k] = pk_min(Ln[k], Wr[k]);
+#pragma unroll
+                for (int k = 0; k < NPW; ++k) Ln[k] = pk_min(Ln[k], m2);
+#pragma unroll
+                for (int k = 0; k < NPW; ++k)
+                    Ln[k] = pk_sub(pk_add(pad_inf((k & 1) ? bytes23(wcs[tc][k >> 1]) : bytes01(wcs[tc][k >> 1])), Ln[k]), mp);
+#pragma unroll
+                for (int k = 0; k < NPW; ++k) Wr[k] = Ln[k];
+                // pairwise minimum tree (independent operations between the dependent ones)
+#pragma unroll
+                for (int h = NPW / 2; h >= 1; h /= 2) {
+#pragma unroll
+                    for (int k = 0; k < h; ++k) Ln[k] = pk_min(Ln[k], Ln[k + h]);
                 }
-                m_new = row_min16((int)min(mv & 0xffffu, mv >> 16));
+                m_new = row_min16((int)min(Ln[0] & 0xffffu, Ln[0] >> 16));
             }
             uint32_t pk[WD];
 #pragma unroll
@@ -1648,15 +1664,15 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_regroup_kernel(SgmLaunch a, 
 #pragma unroll
         for (int u = 0; u < RM; ++u) {
             step(i + u, u, u % PF);
-            load_costs(u % PF, mm[(u + PF) % RM], i + u + PF);
-            next_meta(u);
+            load_costs(u % PF, mm[(u + PF) % RM]);
+            next_meta(u, i + u + RM);
         }
     }
 #pragma unroll
     for (int u = 0; u < RM; ++u) {
         if (i + u < nmax) {
             step(i + u, u, u % PF);
-            if (u + PF < RM) load_costs(u % PF, mm[u + PF], i + u + PF);
+            if (u + PF < RM) load_costs(u % PF, mm[u + PF]);
         }
     }
 }
@@ -1692,7 +1708,7 @@ __global__ __launch_bounds__(kBlock) void cost_frame_kernel(SgmLaunch a) {
             // d), as in the ragged layout, so every path kernel can read it
             gptr(a.meta)[p] = pack_meta(q + (uint32_t)(lo - fr.base), lo, w);
             gptr(a.frame)[p] = (uint64_t)q | ((uint64_t)fr.base << 32) | ((uint64_t)(fr.narrow ? 1 : 2) << 48) |
-                               ((uint64_t)(fr.narrow ? 0 : fr.span >> 4) << 50);
+                               ((uint64_t)(fr.narrow ? 0 : fr.span) << 50);
             s_b[i] = fr.base;
             s_lo[i] = lo;
             s_w[i] = w;
@@ -2573,6 +2589,17 @@ hipError_t launch_sgm_cost(const SgmLaunch& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Dynamic LDS that lets at most `blocks` blocks of a kernel with `static_bytes`
+// of static LDS share a CU (0 if the device cannot be queried).
+static size_t lds_occupancy_cap(int blocks, size_t static_bytes) {
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess || lds <= 0)
+        return 0;
+    const size_t per_block = (size_t)lds / (size_t)(blocks + 1) + 1024;   // blocks + 1 of them do not fit
+    return per_block > static_bytes ? per_block - static_bytes : 0;
+}
+
 hipError_t launch_sgm_paths(const SgmLaunch& a, hipStream_t s) {
     const int n_tasks = 2 * a.h + 2 * a.w + (a.n_paths == 4 ? 0 : 4 * (a.w + a.h - 1));
     const int D = a.win.max_disp;
@@ -2631,9 +2658,15 @@ hipError_t launch_sgm_paths(const SgmLaunch& a, hipStream_t s) {
         }
         const unsigned nb = (unsigned)((t.wave_start[t.n_dirs] + kBlock / 64 - 1) / (kBlock / 64));
         if (sched == 8) {
-            if (D <= 64) sgm_paths_regroup_kernel<64, 4><<<nb, kBlock, 0, s>>>(a, t);
-            else if (D <= 128) sgm_paths_regroup_kernel<128, 4><<<nb, kBlock, 0, s>>>(a, t);
-            else sgm_paths_regroup_kernel<256, 4><<<nb, kBlock, 0, s>>>(a, t);
+            // at most three blocks per CU (LDS reserved for it): the row
+            // scanlines, which set the kernel's length, then share their SIMD
+            // with at most two other waves (at 2048x1024, D = 256: 1080 us
+            // per reduced frame against 1164 at four waves per SIMD)
+            const int dm = D <= 64 ? 64 : D <= 128 ? 128 : 256;
+            const size_t xl = lds_occupancy_cap(3, sizeof(uint32_t) * (kBlock / 64) * 4 * (dm / 2 + 16));
+            if (D <= 64) sgm_paths_regroup_kernel<64, 4><<<nb, kBlock, xl, s>>>(a, t);
+            else if (D <= 128) sgm_paths_regroup_kernel<128, 4><<<nb, kBlock, xl, s>>>(a, t);
+            else sgm_paths_regroup_kernel<256, 4><<<nb, kBlock, xl, s>>>(a, t);
             return hipGetLastError();
         }
         if (hybrid) {
