@@ -2666,7 +2666,7 @@ hipError_t launch_sgm_paths(const SgmLaunch& a, hipStream_t s) {
             const size_t xl = lds_occupancy_cap(3, sizeof(uint32_t) * (kBlock / 64) * 4 * (dm / 2 + 16));
             if (D <= 64) sgm_paths_regroup_kernel<64, 4><<<nb, kBlock, xl, s>>>(a, t);
             else if (D <= 128) sgm_paths_regroup_kernel<128, 4><<<nb, kBlock, xl, s>>>(a, t);
-            else sgm_paths_regroup_kernel<256, 4><<<nb, kBlock, xl, s>>>(a, t);
+            else sgm_paths_regroup_kernel<256, 6><<<nb, kBlock, xl, s>>>(a, t);
             return hipGetLastError();
         }
         if (hybrid) {
