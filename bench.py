@@ -85,7 +85,7 @@ def kernel_symbol(stage, tuning, D):
             g = 16 if tuning["ragged_schedule"] in (5, 6) else 8
             dm = 64 if D <= 64 else (128 if D <= 128 else 256)
             if tuning["ragged_schedule"] == 8:
-                return f"sgm_paths_regroup_kernel<{dm}, 4>"
+                return f"sgm_paths_regroup_kernel<{dm}, {6 if dm == 256 else 4}>"
             if tuning["ragged_schedule"] >= 6:
                 return f"sgm_paths_hybrid_kernel<{g}, {dm}, 4, {1 if D <= 128 else 2}>"
             return f"sgm_paths_group_kernel<{g}, {dm}, 4>"
