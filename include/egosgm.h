@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define EGOSGM_ABI_VERSION 4
+#define EGOSGM_ABI_VERSION 5
 
 /* Largest disparity range and the census window (9 wide, 7 tall: 62 bits). */
 #define EGOSGM_MAX_DISP 256
@@ -287,6 +287,64 @@ int egosgm_right_motion(const double* R, const double* t, double baseline, doubl
  * to float, device arrays of n elements.  EINVAL on NULL or n <= 0. */
 int disparity_to_float(const int16_t* d, float* out, int n, void* stream);
 
+/* ------------------------------------------------------------------ ego-motion
+ * Ego-motion from images (step 1 of Sec. 2, the T of Sec. 2.1 that the warp
+ * consumes).  The paper obtains it from a visual odometry algorithm it cites
+ * and does not describe; this front end is the library's own direct stereo
+ * odometry: with the previous left image I^{k-1}, its disparity map D^{k-1}
+ * and the current left image I^k, it minimises the Huber-weighted
+ * photometric error sum_p rho(I^k(pi(R P_p + t)) - I^{k-1}(p)) over the
+ * pixels with D^{k-1}(p) >= min_disp, P_p = the pixel lifted with
+ * Z = f b / d (Eq. 1) and pi the pinhole projection, by Gauss-Newton on an
+ * image pyramid, coarse to fine, iters[l] iterations at level l (level 0 =
+ * full size; level l halves level l-1 by 2x2 means, disparities by the
+ * sample at (2x, 2y) halved; its camera is f/2^l, (c + 0.5)/2^l - 0.5).
+ * Updates are left-multiplicative, T <- exp(xi) T, xi = (rho, phi), with the
+ * 6x6 system (H + 1e-9 trace(H)/6 I) xi = -g solved by Cholesky in double
+ * (no update on a level step with fewer than 16 pixels).  The lift, motion
+ * and projection are float32 in the order
+ *   Z = fb/d, X = ((x - cx) Z)/f, Y = ((y - cy) Z)/f,
+ *   P'_i = ((R_i0 X + R_i1 Y) + R_i2 Z) + t_i,
+ *   x' = (f X')/Z' + cx, y' = (f Y')/Z' + cy,
+ * and a pixel enters the sum when Z' > 0, 1 <= x' < w_l - 2 and
+ * 1 <= y' < h_l - 2; the image and its central-difference gradients are
+ * sampled bilinearly there.  The result depends on nothing but the inputs
+ * (fixed reduction order).
+ * prev_left, cur_left: uint8 w x h, row pitch `pitch` >= w; prev_disp: w*h
+ * float (<= 0: no disparity).  f, cx, cy, baseline: the level-0 camera
+ * (f, baseline > 0).  pose: DEVICE, 12 doubles (R row-major, then t), the
+ * motion M_k = R M_{k-1} + t: on entry the initial guess (e.g. the previous
+ * frame's motion), on return (once the stream is synchronised) the estimate.
+ * workspace: at least egosgm_vo_workspace_bytes(w, h, prm) bytes.
+ * EINVAL on NULL, pitch < w, w < 16, h < 8, w*h >= 2^31, levels outside
+ * 1..EGOSGM_VO_MAX_LEVELS, a coarsest level below 16 x 8, iters outside
+ * 0..64, huber <= 0, min_disp < 0, non-finite values; EWORKSPACE when the
+ * workspace is NULL or too small. */
+#define EGOSGM_VO_MAX_LEVELS 6
+typedef struct egosgm_vo_params {
+    int levels;                       /* pyramid levels (1..6)                      */
+    int iters[EGOSGM_VO_MAX_LEVELS];  /* Gauss-Newton iterations per level, finest first */
+    float huber;                      /* Huber threshold, intensity units (> 0)     */
+    float min_disp;                   /* smallest disparity used, level-0 pixels    */
+} egosgm_vo_params;
+/* Workspace bytes of estimate_motion / vo_normal_equations; 0 for invalid
+ * sizes or parameters.  Host only. */
+size_t egosgm_vo_workspace_bytes(int w, int h, const egosgm_vo_params* prm);
+int estimate_motion(const uint8_t* prev_left, const uint8_t* cur_left, int w, int h, int pitch,
+                    const float* prev_disp, double f, double cx, double cy, double baseline,
+                    const egosgm_vo_params* prm, double* pose, void* workspace, size_t workspace_bytes,
+                    void* stream);
+/* The normal equations of one level at a given pose, for checking: builds
+ * the pyramids like estimate_motion, then writes H (36 doubles, row-major,
+ * symmetric), g (6), the weighted cost sum rho and the pixel count (44
+ * doubles, DEVICE `out`) of level `level` at `pose` (DEVICE, 12 doubles,
+ * read only).  EINVAL also when level is outside 0..levels-1 or out is
+ * NULL. */
+int vo_normal_equations(const uint8_t* prev_left, const uint8_t* cur_left, int w, int h, int pitch,
+                        const float* prev_disp, double f, double cx, double cy, double baseline,
+                        const egosgm_vo_params* prm, int level, const double* pose, double* out, void* workspace,
+                        size_t workspace_bytes, void* stream);
+
 /* ------------------------------------------------------------------ SAD check
  * Second outlier filter of Sec. 2.4.1 (the paper names it beside the
  * left-right check, without window or threshold): for every pixel with
@@ -444,7 +502,8 @@ typedef enum egosgm_stage {
     EGOSGM_STAGE_BATCH_COST = 9,    /* cost                                      */
     EGOSGM_STAGE_BATCH_PATHS = 10,  /* 8-path aggregation                        */
     EGOSGM_STAGE_BATCH_SELECT = 11, /* selection and left-right check            */
-    EGOSGM_STAGE_COUNT = 12
+    EGOSGM_STAGE_VO = 12,           /* ego-motion estimate (estimate_motion)     */
+    EGOSGM_STAGE_COUNT = 13
 } egosgm_stage;
 
 int egosgm_timing_enable(int on);

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(PKG, "libegosgm.so")
-SOURCES = ["egosgm_kernels.hip", "egosgm_api.hip"]
+SOURCES = ["egosgm_kernels.hip", "egosgm_api.hip", "egosgm_vo.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -792,6 +792,73 @@ int kalman_update(const float* d_pred, const float* p_pred, const float* d_meas,
                : EGOSGM_EDEVICE;
 }
 
+// ------------------------------------------------------------------ ego-motion
+namespace {
+bool vo_params_ok(int w, int h, const egosgm_vo_params* prm) {
+    if (!prm || prm->levels < 1 || prm->levels > EGOSGM_VO_MAX_LEVELS) return false;
+    if (w < 16 || h < 8 || (long long)w * h >= (1ll << 31)) return false;
+    if ((w >> (prm->levels - 1)) < 16 || (h >> (prm->levels - 1)) < 8) return false;
+    for (int l = 0; l < prm->levels; ++l)
+        if (prm->iters[l] < 0 || prm->iters[l] > 64) return false;
+    return std::isfinite(prm->huber) && prm->huber > 0.0f && std::isfinite(prm->min_disp) && prm->min_disp >= 0.0f;
+}
+
+int vo_call(const uint8_t* prev_left, const uint8_t* cur_left, int w, int h, int pitch, const float* prev_disp,
+            double f, double cx, double cy, double baseline, const egosgm_vo_params* prm, int level,
+            double* pose, double* out, void* workspace, size_t workspace_bytes, void* stream) {
+    if (!prev_left || !cur_left || !prev_disp || !pose || !vo_params_ok(w, h, prm) || pitch < w)
+        return EGOSGM_EINVAL;
+    if (!(std::isfinite(f) && f > 0.0 && std::isfinite(baseline) && baseline > 0.0 && std::isfinite(cx) &&
+          std::isfinite(cy)))
+        return EGOSGM_EINVAL;
+    if (level >= prm->levels || (level >= 0 && !out)) return EGOSGM_EINVAL;
+    if (!workspace || workspace_bytes < vo_workspace_bytes(w, h, prm->levels)) return EGOSGM_EWORKSPACE;
+    VoArgs v{};
+    v.prev = prev_left;
+    v.cur = cur_left;
+    v.w = w;
+    v.h = h;
+    v.pitch = pitch;
+    v.prev_disp = prev_disp;
+    v.f = f;
+    v.cx = cx;
+    v.cy = cy;
+    v.baseline = baseline;
+    v.levels = prm->levels;
+    for (int l = 0; l < prm->levels; ++l) v.iters[l] = prm->iters[l];
+    v.huber = prm->huber;
+    v.min_disp = prm->min_disp;
+    v.pose = pose;
+    v.out = out;
+    v.only_level = level;
+    v.workspace = workspace;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return timed(EGOSGM_STAGE_VO, s, [&] { return launch_vo(v, s); }) == hipSuccess ? EGOSGM_OK : EGOSGM_EDEVICE;
+}
+}  // namespace
+
+size_t egosgm_vo_workspace_bytes(int w, int h, const egosgm_vo_params* prm) {
+    if (!vo_params_ok(w, h, prm)) return 0;
+    return vo_workspace_bytes(w, h, prm->levels);
+}
+
+int estimate_motion(const uint8_t* prev_left, const uint8_t* cur_left, int w, int h, int pitch,
+                    const float* prev_disp, double f, double cx, double cy, double baseline,
+                    const egosgm_vo_params* prm, double* pose, void* workspace, size_t workspace_bytes,
+                    void* stream) {
+    return vo_call(prev_left, cur_left, w, h, pitch, prev_disp, f, cx, cy, baseline, prm, -1, pose, nullptr,
+                   workspace, workspace_bytes, stream);
+}
+
+int vo_normal_equations(const uint8_t* prev_left, const uint8_t* cur_left, int w, int h, int pitch,
+                        const float* prev_disp, double f, double cx, double cy, double baseline,
+                        const egosgm_vo_params* prm, int level, const double* pose, double* out, void* workspace,
+                        size_t workspace_bytes, void* stream) {
+    if (level < 0) return EGOSGM_EINVAL;
+    return vo_call(prev_left, cur_left, w, h, pitch, prev_disp, f, cx, cy, baseline, prm, level,
+                   const_cast<double*>(pose), out, workspace, workspace_bytes, stream);
+}
+
 int egosgm_set_tuning(const egosgm_tuning* t) {
     if (!t) return EGOSGM_EINVAL;
     auto ok = [](int g) { return g == 16 || g == 32 || g == 64; };

@@ -153,4 +153,24 @@ hipError_t launch_kalman(const float* d_pred, const float* p_pred, const float* 
                          const float* r, int n, int keep, float* d_out, float* p_out,
                          hipStream_t s);
 
+// Ego-motion front end (egosgm_vo.hip): one estimate, or the normal
+// equations of one level at the pose given (only_level >= 0, written to out).
+constexpr int kVoMaxLevels = 6;
+struct VoArgs {
+    const uint8_t* prev;      // previous left image
+    const uint8_t* cur;       // current left image
+    int w, h, pitch;
+    const float* prev_disp;   // previous disparity map (w*h, <= 0 invalid)
+    double f, cx, cy, baseline;
+    int levels;
+    int iters[kVoMaxLevels];  // per level, finest first
+    float huber, min_disp;
+    double* pose;             // 12 doubles: R row-major, t (in: guess, out: estimate)
+    double* out;              // only_level >= 0: H (36), g (6), cost, count
+    int only_level;
+    void* workspace;
+};
+size_t vo_workspace_bytes(int w, int h, int levels);
+hipError_t launch_vo(const VoArgs& v, hipStream_t s);
+
 }  // namespace egosgm

@@ -55,13 +55,17 @@ _SIGS = {
     "egosgm_get_tuning": ([_vp], _i),
     "egosgm_timing_enable": ([_i], _i),
     "egosgm_timing_read": ([_vp, _vp, _i], _i),
+    "egosgm_vo_workspace_bytes": ([_i, _i, _vp], _sz),
+    "estimate_motion": ([_vp, _vp, _i, _i, _i, _vp, _d, _d, _d, _d, _vp, _vp, _vp, _sz, _vp], _i),
+    "vo_normal_equations": ([_vp, _vp, _i, _i, _i, _vp, _d, _d, _d, _d, _vp, _i, _vp, _vp, _vp, _sz, _vp],
+                            _i),
 }
 
 STAGES = ("census", "windows", "cost", "paths", "select", "warp", "kalman", "refine",
-          "batch_census", "batch_cost", "batch_paths", "batch_select")
+          "batch_census", "batch_cost", "batch_paths", "batch_select", "vo")
 
 
-ABI_VERSION = 4   # EGOSGM_ABI_VERSION of include/egosgm.h
+ABI_VERSION = 5   # EGOSGM_ABI_VERSION of include/egosgm.h
 
 
 def lib():
@@ -480,6 +484,90 @@ def kalman_update(d_pred, p_pred, d_meas, r_meas, keep_unmeasured=0, out=None):
                              int(keep_unmeasured), _ptr(out[0]), _ptr(out[1]), _stream())
     _check(rc, "kalman_update")
     return out
+
+
+# ------------------------------------------------------------------ ego-motion
+VO_MAX_LEVELS = 6
+
+
+class VOParams(C.Structure):
+    """egosgm_vo_params: pyramid levels, Gauss-Newton iterations per level
+    (finest first), Huber threshold, smallest disparity used."""
+    _fields_ = [("levels", C.c_int), ("iters", C.c_int * VO_MAX_LEVELS), ("huber", C.c_float),
+                ("min_disp", C.c_float)]
+
+
+def vo_params(levels=5, iters=(2, 4, 8, 10, 10, 10), huber=8.0, min_disp=1.0) -> VOParams:
+    it = list(iters)[:VO_MAX_LEVELS] + [0] * (VO_MAX_LEVELS - len(iters))
+    return VOParams(int(levels), (C.c_int * VO_MAX_LEVELS)(*it), float(huber), float(min_disp))
+
+
+def vo_levels_for(w, h, max_levels=6, min_w=64):
+    """Pyramid levels so that the coarsest level stays at least min_w x 16."""
+    n = 1
+    while n < max_levels and (w >> n) >= min_w and (h >> n) >= 16:
+        n += 1
+    return n
+
+
+def vo_workspace(w, h, prm: VOParams, device="cuda"):
+    n = lib().egosgm_vo_workspace_bytes(w, h, C.byref(prm))
+    if n == 0:
+        raise EgoSgmError("egosgm_vo_workspace_bytes: invalid size or parameters")
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def _vo_args(prev_left, cur_left, prev_disp, prm):
+    h, w = cur_left.shape
+    _need(prev_left, torch.uint8, name="prev_left")
+    _need(cur_left, torch.uint8, name="cur_left")
+    if prev_left.shape != cur_left.shape:
+        raise EgoSgmError("prev_left and cur_left differ in shape")
+    _need(prev_disp, torch.float32, h * w, "prev_disp")
+    return w, h
+
+
+def estimate_motion(prev_left, cur_left, prev_disp, calib, prm: VOParams, pose=None, R0=None, t0=None,
+                    workspace=None):
+    """Ego-motion (R, t), M_k = R M_{k-1} + t, from the previous left image
+    and disparity map and the current left image (estimate_motion).
+    calib: (f, cx, cy, baseline).  pose: optional device float64 tensor of 12
+    (R row-major, t) holding the initial guess and receiving the estimate;
+    else one is made from R0, t0 (identity, zero by default).  Returns the
+    pose tensor; pose_to_host() reads it (a synchronisation)."""
+    w, h = _vo_args(prev_left, cur_left, prev_disp, prm)
+    if pose is None:
+        R0 = np.eye(3) if R0 is None else np.asarray(R0, np.float64)
+        t0 = np.zeros(3) if t0 is None else np.asarray(t0, np.float64)
+        pose = torch.tensor(np.concatenate([R0.ravel(), t0.ravel()]), dtype=torch.float64,
+                            device=cur_left.device)
+    _need(pose, torch.float64, 12, "pose")
+    ws = workspace if workspace is not None else vo_workspace(w, h, prm, cur_left.device)
+    f, cx, cy, b = calib
+    _check(lib().estimate_motion(_ptr(prev_left), _ptr(cur_left), w, h, w, _ptr(prev_disp), float(f), float(cx),
+                                 float(cy), float(b), C.byref(prm), _ptr(pose), _ptr(ws), ws.numel(), _stream()),
+           "estimate_motion")
+    return pose
+
+
+def pose_to_host(pose):
+    v = pose.cpu().numpy().astype(np.float64)
+    return v[:9].reshape(3, 3), v[9:12].copy()
+
+
+def vo_normal_equations(prev_left, cur_left, prev_disp, calib, prm: VOParams, level, R, t, workspace=None):
+    """(H 6x6, g 6, cost, count) of one pyramid level at the pose (R, t)."""
+    w, h = _vo_args(prev_left, cur_left, prev_disp, prm)
+    pose = torch.tensor(np.concatenate([np.asarray(R, np.float64).ravel(), np.asarray(t, np.float64).ravel()]),
+                        dtype=torch.float64, device=cur_left.device)
+    out = torch.zeros(44, dtype=torch.float64, device=cur_left.device)
+    ws = workspace if workspace is not None else vo_workspace(w, h, prm, cur_left.device)
+    f, cx, cy, b = calib
+    _check(lib().vo_normal_equations(_ptr(prev_left), _ptr(cur_left), w, h, w, _ptr(prev_disp), float(f), float(cx),
+                                     float(cy), float(b), C.byref(prm), int(level), _ptr(pose), _ptr(out), _ptr(ws),
+                                     ws.numel(), _stream()), "vo_normal_equations")
+    o = out.cpu().numpy()
+    return o[:36].reshape(6, 6), o[36:42].copy(), float(o[42]), int(round(o[43]))
 
 
 # ------------------------------------------------------------------ timing

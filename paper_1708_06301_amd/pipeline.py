@@ -49,6 +49,11 @@ class FrameConfig:
     lr_predict: bool = False  # left-right check of the prediction against the warped right map
     lr_predict_tol: float = 1.0
     overlap_census: bool = False  # step(): census on a second stream (measured 2% slower here)
+    vo: bool = False          # step(): ego-motion from the images (estimate_motion) instead of R, t given
+    vo_levels: int = 0        # pyramid levels (0: the coarsest level stays >= 64 x 16)
+    vo_iters: tuple = (2, 4, 8, 10, 10, 10)   # Gauss-Newton iterations per level, finest first
+    vo_huber: float = 8.0
+    vo_min_disp: float = 1.0
 
     def match(self) -> eg.MatchParams:
         return eg.MatchParams(self.max_disp, self.p1, self.p2, self.s_max, self.lr_tol,
@@ -97,11 +102,20 @@ class StreamState:
             self.p_rwarp = torch.empty((h, w), **f32)
             self.d_rpred = torch.empty((h, w), **f32)
             self.p_rpred = torch.empty((h, w), **f32)
+        if cfg.vo:   # previous left image, the motion estimate (kept as the next guess)
+            levels = cfg.vo_levels or eg.vo_levels_for(w, h)
+            self.vo_prm = eg.vo_params(levels, cfg.vo_iters[:levels], cfg.vo_huber, cfg.vo_min_disp)
+            self.vo_ws = eg.vo_workspace(w, h, self.vo_prm, dev)
+            self.prev_left = torch.empty((h, w), dtype=torch.uint8, device=dev)
+            self.vo_pose = torch.zeros(12, dtype=torch.float64, device=dev)
+            self.vo_motion = None
         self.frame = 0
 
     def reset(self):
         """Drop the prediction: the next frame searches the full range."""
         self.frame = 0
+        if self.cfg.vo:
+            self.vo_motion = None
 
     def full_range_next(self) -> bool:
         return self.frame == 0 or self.cfg.full_range_only
@@ -188,16 +202,36 @@ class StreamState:
         ts = [self.d, self.p, self.d_pred, self.p_pred, self.zbuf,
               self.lo, self.hi, self.off, self.invalid, self.zeros, *self.out.values(),
               *[getattr(self, k, None) for k in ("d_r", "d_rwarp", "p_rwarp", "d_rpred", "p_rpred")],
-              self.ws.sgm, self.ws.win, getattr(self.ws, "ref", None)]
+              self.ws.sgm, self.ws.win, getattr(self.ws, "ref", None),
+              *[getattr(self, k, None) for k in ("vo_ws", "prev_left", "vo_pose")]]
         return sum(t.numel() * t.element_size() for t in ts if t is not None)
+
+    def estimate_motion(self, left: torch.Tensor):
+        """Ego-motion from the previous left image and disparity map to this
+        left image (estimate_motion), starting from the previous frame's
+        estimate; reads the result to the host (a synchronisation), since the
+        warp takes the motion as host values."""
+        if self.vo_motion is None:
+            self.vo_pose.copy_(torch.tensor(np.concatenate([np.eye(3).ravel(), np.zeros(3)]),
+                                            dtype=torch.float64))
+        c = self.calib
+        eg.estimate_motion(self.prev_left, left, self.d, (c.f, c.cx, c.cy, c.baseline), self.vo_prm,
+                           pose=self.vo_pose, workspace=self.vo_ws)
+        self.vo_motion = eg.pose_to_host(self.vo_pose)
+        return self.vo_motion
 
     def step(self, left: torch.Tensor, right: torch.Tensor, R=None, t=None):
         """Processes one stereo frame; R, t map the previous camera frame to
-        this one (M_k = R M_{k-1} + t).  Returns the updated (d, p) maps."""
+        this one (M_k = R M_{k-1} + t); with FrameConfig.vo they are
+        estimated from the images instead.  Returns the updated (d, p) maps."""
+        if self.cfg.vo and not self.full_range_next():
+            R, t = self.estimate_motion(left)
         if self.side is not None:
             self.census_ahead(left, right)
         win = self.predict(R, t)
         self.match(left, right, win)
+        if self.cfg.vo:
+            self.prev_left.copy_(left)
         return self.update()
 
     def searched_slots(self) -> int:

@@ -26,7 +26,7 @@ def test_every_declared_symbol_is_exported():
     lib = eg.lib()
     for n in names:
         assert hasattr(lib, n), n
-    assert eg.abi_version() == 4
+    assert eg.abi_version() == 5
 
 
 def test_workspace_sizes():
@@ -230,3 +230,34 @@ def test_plans_reject_a_precomputed_census():
     P = (eg.PairDesc * 1)()
     out = C.c_void_p()
     assert lib.sgm_plan_create(P, 1, C.byref(prm), FAKE, 1 << 40, C.byref(out)) == -1
+
+
+def test_vo_workspace_and_validation():
+    """estimate_motion / vo_normal_equations validate sizes and parameters on
+    the host; the workspace size covers five float images per level."""
+    lib = eg.lib()
+    prm = eg.vo_params(levels=4, iters=(2, 4, 8, 10))
+    n = lib.egosgm_vo_workspace_bytes(1242, 375, C.byref(prm))
+    assert n >= 4 * 5 * 1242 * 375
+    assert lib.egosgm_vo_workspace_bytes(15, 375, C.byref(prm)) == 0
+    assert lib.egosgm_vo_workspace_bytes(100, 100, C.byref(eg.vo_params(levels=4))) == 0   # coarsest 12 x 12
+    bad = [eg.vo_params(levels=0), eg.vo_params(levels=7), eg.vo_params(levels=2, iters=(65, 1)),
+           eg.vo_params(levels=2, iters=(-1, 1)), eg.vo_params(levels=2, huber=0.0),
+           eg.vo_params(levels=2, min_disp=-1.0), eg.vo_params(levels=2, huber=float("nan"))]
+    for b in bad:
+        assert lib.egosgm_vo_workspace_bytes(640, 192, C.byref(b)) == 0
+        rc = lib.estimate_motion(FAKE, FAKE, 640, 192, 640, FAKE, 500.0, 320.0, 96.0, 0.5, C.byref(b), FAKE,
+                                 FAKE, 1 << 40, None)
+        assert rc == -1
+    ok = eg.vo_params(levels=3, iters=(1, 1, 1))
+    args = (640, 192, 640, FAKE, 500.0, 320.0, 96.0, 0.5, C.byref(ok))
+    assert lib.estimate_motion(None, FAKE, *args, FAKE, FAKE, 1 << 40, None) == -1          # NULL image
+    assert lib.estimate_motion(FAKE, FAKE, 640, 192, 639, FAKE, 500.0, 320.0, 96.0, 0.5, C.byref(ok), FAKE,
+                               FAKE, 1 << 40, None) == -1                                    # pitch < w
+    assert lib.estimate_motion(FAKE, FAKE, 640, 192, 640, FAKE, -1.0, 320.0, 96.0, 0.5, C.byref(ok), FAKE,
+                               FAKE, 1 << 40, None) == -1                                    # f <= 0
+    assert lib.estimate_motion(FAKE, FAKE, *args, FAKE, FAKE, 16, None) == -2                # small workspace
+    assert lib.estimate_motion(FAKE, FAKE, *args, FAKE, None, 1 << 40, None) == -2           # no workspace
+    assert lib.vo_normal_equations(FAKE, FAKE, *args, 3, FAKE, FAKE, FAKE, 1 << 40, None) == -1   # level
+    assert lib.vo_normal_equations(FAKE, FAKE, *args, -1, FAKE, FAKE, FAKE, 1 << 40, None) == -1
+    assert lib.vo_normal_equations(FAKE, FAKE, *args, 0, FAKE, None, FAKE, 1 << 40, None) == -1   # out

@@ -1,0 +1,134 @@
+"""The ego-motion front end on the GPU (estimate_motion, vo_normal_equations)
+against the oracle (oracle/vo.py), and against the renderer's exact motion."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import vo
+from paper_1708_06301_amd import egosgm as eg
+from paper_1708_06301_amd import pipeline, synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _say(*a):
+    print("CASE", *a, flush=True)
+
+
+def _pair(w, h, k, noise=True, n=4):
+    seq = synth.street_sequence(w, h, n, seed=synth.seed_for(1))
+    L0, _, gt0 = seq.frame(k - 1, noise=noise)
+    L1, _, _ = seq.frame(k, noise=noise)
+    return seq, L0, L1, gt0.astype(np.float32)
+
+
+def _gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _calib(cam):
+    return cam.f, cam.cx, cam.cy, cam.baseline
+
+
+def _pose_diff(R, t, Rg, tg):
+    dR = R @ Rg.T
+    ang = np.degrees(np.arccos(np.clip((np.trace(dR) - 1.0) / 2.0, -1.0, 1.0)))
+    return float(np.linalg.norm(t - tg)), float(ang)
+
+
+@pytest.mark.parametrize("w,h,levels", [(640, 192, 4), (1242, 375, 5), (2048, 1024, 5)])
+def test_normal_equations_follow_the_oracle(w, h, levels):
+    """Every level's H, g, cost and pixel count at a pose near the true one:
+    the count exactly (both sides decide in float32), the sums within 1e-4 of
+    their Cauchy-Schwarz scale (float32 terms and block sums here, float64
+    there)."""
+    _say("vo normal equations", w, h, levels)
+    seq, L0, L1, gt0 = _pair(w, h, 1)
+    iters = (2, 4, 8, 10, 10)[:levels]
+    prm = eg.vo_params(levels, iters)
+    oprm = vo.VOParams(levels=levels, iters=iters)
+    Rg, tg = seq.motion(1)
+    Rd, td = vo.se3_exp([0.01, -0.005, 0.02, 0.002, -0.001, 0.0015])
+    R, t = Rd @ Rg, Rd @ tg + td
+    ref = vo.Levels(L0, L1, gt0, *_calib(seq.cam), oprm)
+    g0, g1, gd = _gpu(L0), _gpu(L1), _gpu(gt0)
+    for l in range(levels):
+        H, g, cost, n = eg.vo_normal_equations(g0, g1, gd, _calib(seq.cam), prm, l, R, t)
+        Ho, go, co, no = ref.normal(l, R, t)
+        assert n == no and n > 100, (l, n, no)
+        dH = np.sqrt(np.abs(np.outer(np.diag(Ho), np.diag(Ho))))
+        assert np.all(np.abs(H - Ho) <= 1e-4 * dH + 1e-9), l
+        assert np.all(np.abs(g - go) <= 1e-4 * np.sqrt(np.diag(Ho) * co) + 1e-9), l
+        assert abs(cost - co) <= 1e-4 * co, l
+
+
+@pytest.mark.parametrize("w,h,levels", [(640, 192, 4), (1242, 375, 5)])
+@pytest.mark.parametrize("k", [1, 3])
+def test_estimate_follows_the_oracle_and_the_renderer(w, h, levels, k):
+    """A whole estimate from the identity: within 1e-5 m and 1e-5 degrees of
+    the oracle's, and within 5 mm and 0.02 degrees of the renderer's motion."""
+    _say("vo estimate", w, h, levels, k)
+    seq, L0, L1, gt0 = _pair(w, h, k)
+    iters = (2, 4, 8, 10, 10)[:levels]
+    pose = eg.estimate_motion(_gpu(L0), _gpu(L1), _gpu(gt0), _calib(seq.cam), eg.vo_params(levels, iters))
+    R, t = eg.pose_to_host(pose)
+    Ro, to = vo.estimate_motion(L0, L1, gt0, *_calib(seq.cam), vo.VOParams(levels=levels, iters=iters))
+    dt, da = _pose_diff(R, t, Ro, to)
+    assert dt < 1e-5 and da < 1e-5, (dt, da)
+    et, ea = _pose_diff(R, t, *seq.motion(k))
+    assert et < 0.005 and ea < 0.02, (et, ea)
+
+
+def test_estimate_at_2048x1024():
+    _say("vo estimate 2048x1024")
+    seq, L0, L1, gt0 = _pair(2048, 1024, 2)
+    levels = eg.vo_levels_for(2048, 1024)
+    assert levels == 6
+    R, t = eg.pose_to_host(eg.estimate_motion(_gpu(L0), _gpu(L1), _gpu(gt0), _calib(seq.cam),
+                                              eg.vo_params(levels, (2, 4, 8, 10, 10, 10))))
+    et, ea = _pose_diff(R, t, *seq.motion(2))
+    assert et < 0.005 and ea < 0.02, (et, ea)
+
+
+def test_estimate_keeps_a_good_guess_and_is_repeatable():
+    """Started at the true motion the estimate stays there; two runs give
+    the same bits (fixed reduction order)."""
+    _say("vo repeatable")
+    seq, L0, L1, gt0 = _pair(640, 192, 2, noise=False)
+    Rg, tg = seq.motion(2)
+    prm = eg.vo_params(4, (2, 4, 8, 10))
+    a = eg.estimate_motion(_gpu(L0), _gpu(L1), _gpu(gt0), _calib(seq.cam), prm, R0=Rg, t0=tg)
+    b = eg.estimate_motion(_gpu(L0), _gpu(L1), _gpu(gt0), _calib(seq.cam), prm, R0=Rg, t0=tg)
+    assert torch.equal(a, b)
+    et, ea = _pose_diff(*eg.pose_to_host(a), Rg, tg)
+    assert et < 0.003 and ea < 0.01, (et, ea)
+
+
+def test_pipeline_with_visual_odometry():
+    """The frame loop with FrameConfig.vo: each frame's motion comes from the
+    previous left image and the pipeline's own filtered disparity map; it
+    follows the oracle on the same inputs and the renderer's motion."""
+    _say("vo pipeline 640x192")
+    w, h, nf = 640, 192, 6
+    seq = synth.street_sequence(w, h, nf, seed=synth.seed_for(1))
+    cfg = pipeline.FrameConfig(max_disp=64, r_fixed=4, vo=True)
+    st = pipeline.StreamState(w, h, pipeline.camera_of(seq), cfg, DEV)
+    oprm = vo.VOParams(levels=st.vo_prm.levels, iters=tuple(st.vo_prm.iters[:st.vo_prm.levels]))
+    for k in range(nf):
+        L, R, _ = seq.frame(k)
+        if k > 0:
+            d_prev = st.d.cpu().numpy()
+            guess = st.vo_motion
+        st.step(_gpu(L), _gpu(R))
+        if k > 0:
+            Rk, tk = st.vo_motion
+            R0, t0 = guess if guess is not None else (np.eye(3), np.zeros(3))
+            Ro, to = vo.estimate_motion(prev_L, L, d_prev, *_calib(seq.cam), oprm, R0, t0)
+            dt, da = _pose_diff(Rk, tk, Ro, to)
+            assert dt < 1e-4 and da < 1e-4, (k, dt, da)
+            et, ea = _pose_diff(Rk, tk, *seq.motion(k))
+            assert et < 0.03 and ea < 0.1, (k, et, ea)
+        prev_L = L
+    torch.cuda.synchronize()
+    assert (st.d.cpu().numpy() > 0).mean() > 0.8
