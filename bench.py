@@ -605,6 +605,65 @@ def variants_section(w, h, calib, cfg, frames, motions, gts, dev, reps=3):
     return out
 
 
+def vo_section(w, h, calib, cfg, frames, motions, gts, dev, reps=3):
+    """Ego-motion from the images (FrameConfig.vo, estimate_motion) in place
+    of the renderer's exact motion on the same sequence: per-frame pose error
+    against that motion, the search fraction and the filtered map's bad-pixel
+    rates beside the exact-motion pipeline's, the estimate's own time per
+    frame (library stage events) and the time per step (median of reps, HIP
+    events; each frame reads its estimate back to the host for the warp)."""
+    import torch
+    from paper_1708_06301_amd import egosgm as eg, pipeline
+    from paper_1708_06301_amd.quality import bad_pixels, summarise
+    st = pipeline.StreamState(w, h, calib, pipeline.FrameConfig(**{**cfg.__dict__, "vo": True}), dev)
+    gt_st = pipeline.StreamState(w, h, calib, cfg, dev)
+    t_err, r_err, frac, frac_gt, q, q_gt = [], [], [], [], [], []
+    st.reset()
+    gt_st.reset()
+    for k, (L, R) in enumerate(frames):
+        d, _ = st.step(L, R)
+        d_gt, _ = gt_st.step(L, R, *(motions[k] if k > 0 else (None, None)))
+        torch.cuda.synchronize()
+        if k == 0:
+            continue
+        Re, te = st.vo_motion
+        Rg, tg = motions[k]
+        dR = Re @ np.asarray(Rg).T
+        t_err.append(float(np.linalg.norm(te - np.asarray(tg))))
+        r_err.append(float(np.degrees(np.arccos(np.clip((np.trace(dR) - 1.0) / 2.0, -1.0, 1.0)))))
+        frac.append(st.searched_slots() / (w * h * cfg.max_disp))
+        frac_gt.append(gt_st.searched_slots() / (w * h * cfg.max_disp))
+        q.append(bad_pixels(d, gts[k], cfg.max_disp))
+        q_gt.append(bad_pixels(d_gt, gts[k], cfg.max_disp))
+    times = []
+    for _ in range(reps + 1):
+        a, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        st.reset()
+        a.record()
+        for L, R in frames:
+            st.step(L, R)
+        b_.record()
+        b_.synchronize()
+        times.append(a.elapsed_time(b_))
+    ms = sorted(times[1:])[len(times[1:]) // 2]
+    eg.timing_enable(True)
+    eg.timing_read()
+    st.reset()
+    for L, R in frames:
+        st.step(L, R)
+    torch.cuda.synchronize()
+    stg = eg.timing_read()
+    eg.timing_enable(False)
+    vo_ms = stg["vo"][0] / max(1, stg["vo"][1])
+    return {"frames": f"1..{len(frames) - 1}", "levels": int(st.vo_prm.levels),
+            "iters": list(st.vo_prm.iters[:st.vo_prm.levels]),
+            "translation_error_m": {"mean": round(float(np.mean(t_err)), 5), "max": round(float(np.max(t_err)), 5)},
+            "rotation_error_deg": {"mean": round(float(np.mean(r_err)), 5), "max": round(float(np.max(r_err)), 5)},
+            "estimate_ms_per_frame": round(vo_ms, 4), "ms_per_step": round(ms, 3),
+            "search_fraction": {"vo": round(float(np.mean(frac)), 4), "exact_motion": round(float(np.mean(frac_gt)), 4)},
+            "quality_filtered": {"vo": summarise(q), "exact_motion": summarise(q_gt)}}
+
+
 def serve_section(dev, n_frames, log, budget_gib=32.0):
     """16 camera streams (8 at 1242x375 D=128, 8 at 640x192 D=64), n_frames
     synthetic street frames each, arriving at 30 fps with Poisson jitter,
@@ -714,6 +773,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the variants section (its 4-path runs share the path kernel's symbol)")
     ap.add_argument("--no-quality", action="store_true")
+    ap.add_argument("--no-vo", action="store_true", help="skip the ego-motion-from-images sections")
     ap.add_argument("--serve-frames", type=int, default=300)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (counter calibration)")
@@ -772,6 +832,10 @@ def run(args, pool):
     if not args.only_headline and not args.no_quality:
         out["quality"] = quality_section(hctx["red"], hctx["full"], hctx["frames"], hctx["motions"],
                                          hctx["gts"], head["max_disp"])
+    if not args.only_headline and not args.no_vo:
+        out["vo"] = vo_section(head["w"], head["h"], hctx["calib"], hctx["cfg"], hctx["frames"], hctx["motions"],
+                               hctx["gts"], dev)
+        log(f"vo: {out['vo']}")
     cpu = None
     if not args.no_cpu_baseline:
         # the oracle gets host copies of the frames; the GPU state is released first
@@ -784,6 +848,9 @@ def run(args, pool):
         if not args.no_quality:
             sec["quality"] = quality_section(sctx["red"], sctx["full"], sctx["frames"], sctx["motions"],
                                              sctx["gts"], sec["max_disp"])
+        if not args.no_vo:
+            sec["vo"] = vo_section(sec["w"], sec["h"], sctx["calib"], sctx["cfg"], sctx["frames"], sctx["motions"],
+                                   sctx["gts"], dev)
         if not args.no_variants:
             sec["variants"] = variants_section(sec["w"], sec["h"], sctx["calib"], sctx["cfg"],
                                                sctx["frames"], sctx["motions"], sctx["gts"], dev)

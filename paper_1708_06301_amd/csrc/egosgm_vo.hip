@@ -11,12 +11,14 @@
 // motion from a feature-based odometry it cites; this front end is the
 // library's own.)
 //
-// Per level: one kernel evaluates every pixel's residual and Jacobian and
-// reduces the normal equations (21 + 6 + cost + count terms) per block in
-// float32; one single-block kernel sums the block partials in double in a
-// fixed order, solves the 6x6 system by Cholesky and updates the pose, which
-// stays in device memory (12 doubles) from the first level to the last, so a
-// whole estimate is a fixed sequence of launches with no host round trip.
+// Per iteration of a large level: one kernel evaluates every pixel's
+// residual and Jacobian and reduces the normal equations (21 + 6 + cost +
+// count terms) per block in float32; one single-block kernel sums the block
+// partials in double in a fixed order, solves the 6x6 system by Cholesky and
+// updates the pose.  A small level (at most 8 Ki pixels) runs all its
+// iterations in one block, the pose in LDS between them.  The pose stays in
+// device memory (12 doubles) from the first level to the last, so a whole
+// estimate is a fixed sequence of launches with no host round trip.
 #include "egosgm_internal.h"
 
 #include <math.h>
@@ -27,6 +29,7 @@ namespace {
 constexpr int kVoBlock = 256;
 constexpr int kVoPix = 4;       // pixels per thread in the normal-equation pass
 constexpr int kVoTerms = 29;    // 21 (upper triangle of H) + 6 (g) + cost + count
+constexpr int kVoSmallLevel = 1 << 13;   // levels of at most this many pixels run in one block
 
 __global__ __launch_bounds__(kVoBlock) void vo_level0_kernel(const uint8_t* prev, const uint8_t* cur, int w, int h,
                                                               int pitch, float* ref0, float* cur0) {
@@ -74,6 +77,48 @@ __device__ inline float bilinear(const float* I, int w, int x0, int y0, float fx
     return (1.0f - fy) * ((1.0f - fx) * r0[0] + fx * r0[1]) + fy * ((1.0f - fx) * r1[0] + fx * r1[1]);
 }
 
+// Adds pixel i's terms (upper triangle of w J^T J, w J r, w r^2, 1) to acc
+// when it enters the sum at the motion (R, t).
+__device__ inline void add_pixel(const VoLevel& L, const float (&R)[9], const float (&t)[3], int i,
+                                 float (&acc)[kVoTerms]) {
+    const float d = L.disp[i];
+    if (!(d >= L.min_disp)) return;
+    const int y = i / L.w, x = i - y * L.w;
+    // the lift, the motion and the projection in float32, in this order
+    const float Z = L.fb / d;
+    const float X = (((float)x - L.cx) * Z) / L.f;
+    const float Y = (((float)y - L.cy) * Z) / L.f;
+    const float Xp = ((R[0] * X + R[1] * Y) + R[2] * Z) + t[0];
+    const float Yp = ((R[3] * X + R[4] * Y) + R[5] * Z) + t[1];
+    const float Zp = ((R[6] * X + R[7] * Y) + R[8] * Z) + t[2];
+    if (!(Zp > 0.0f)) return;
+    const float up = (L.f * Xp) / Zp + L.cx;
+    const float vp = (L.f * Yp) / Zp + L.cy;
+    if (!(up >= 1.0f && up < (float)(L.w - 2) && vp >= 1.0f && vp < (float)(L.h - 2))) return;
+    const float x0f = floorf(up), y0f = floorf(vp);
+    const int x0 = (int)x0f, y0 = (int)y0f;
+    const float fx = up - x0f, fy = vp - y0f;
+    const float r = bilinear(L.cur, L.w, x0, y0, fx, fy) - L.ref[i];
+    const float gx = bilinear(L.gx, L.w, x0, y0, fx, fy);
+    const float gy = bilinear(L.gy, L.w, x0, y0, fx, fy);
+    const float ju = gx * L.f / Zp, jv = gy * L.f / Zp;
+    const float jz = -(gx * L.f * Xp + gy * L.f * Yp) / (Zp * Zp);
+    const float J[6] = {ju, jv, jz, Yp * jz - Zp * jv, Zp * ju - Xp * jz, Xp * jv - Yp * ju};
+    const float a = fabsf(r);
+    const float wgt = a <= L.huber ? 1.0f : L.huber / a;
+    int q = 0;
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+        const float wj = wgt * J[u];
+#pragma unroll
+        for (int v = u; v < 6; ++v) acc[q++] += wj * J[v];
+    }
+#pragma unroll
+    for (int u = 0; u < 6; ++u) acc[21 + u] += wgt * J[u] * r;
+    acc[27] += wgt * r * r;
+    acc[28] += 1.0f;
+}
+
 // Normal equations of one level at the pose in `pose` (12 doubles, device):
 // every thread takes kVoPix pixels (strided by the grid), the block sums its
 // threads' terms in LDS and writes kVoTerms floats to part[block].
@@ -89,44 +134,8 @@ __global__ __launch_bounds__(kVoBlock) void vo_normal_kernel(VoLevel L, const do
     for (int k = 0; k < kVoTerms; ++k) acc[k] = 0.0f;
     const int n = L.w * L.h;
     const int stride = (int)(gridDim.x * kVoBlock);
-    for (int k = 0, i = (int)(blockIdx.x * kVoBlock + threadIdx.x); k < kVoPix && i < n; ++k, i += stride) {
-        const float d = L.disp[i];
-        if (!(d >= L.min_disp)) continue;
-        const int y = i / L.w, x = i - y * L.w;
-        // the lift, the motion and the projection in float32, in this order
-        const float Z = L.fb / d;
-        const float X = (((float)x - L.cx) * Z) / L.f;
-        const float Y = (((float)y - L.cy) * Z) / L.f;
-        const float Xp = ((R[0] * X + R[1] * Y) + R[2] * Z) + t[0];
-        const float Yp = ((R[3] * X + R[4] * Y) + R[5] * Z) + t[1];
-        const float Zp = ((R[6] * X + R[7] * Y) + R[8] * Z) + t[2];
-        if (!(Zp > 0.0f)) continue;
-        const float up = (L.f * Xp) / Zp + L.cx;
-        const float vp = (L.f * Yp) / Zp + L.cy;
-        if (!(up >= 1.0f && up < (float)(L.w - 2) && vp >= 1.0f && vp < (float)(L.h - 2))) continue;
-        const float x0f = floorf(up), y0f = floorf(vp);
-        const int x0 = (int)x0f, y0 = (int)y0f;
-        const float fx = up - x0f, fy = vp - y0f;
-        const float r = bilinear(L.cur, L.w, x0, y0, fx, fy) - L.ref[i];
-        const float gx = bilinear(L.gx, L.w, x0, y0, fx, fy);
-        const float gy = bilinear(L.gy, L.w, x0, y0, fx, fy);
-        const float ju = gx * L.f / Zp, jv = gy * L.f / Zp;
-        const float jz = -(gx * L.f * Xp + gy * L.f * Yp) / (Zp * Zp);
-        const float J[6] = {ju, jv, jz, Yp * jz - Zp * jv, Zp * ju - Xp * jz, Xp * jv - Yp * ju};
-        const float a = fabsf(r);
-        const float wgt = a <= L.huber ? 1.0f : L.huber / a;
-        int q = 0;
-#pragma unroll
-        for (int u = 0; u < 6; ++u) {
-            const float wj = wgt * J[u];
-#pragma unroll
-            for (int v = u; v < 6; ++v) acc[q++] += wj * J[v];
-        }
-#pragma unroll
-        for (int u = 0; u < 6; ++u) acc[21 + u] += wgt * J[u] * r;
-        acc[27] += wgt * r * r;
-        acc[28] += 1.0f;
-    }
+    for (int k = 0, i = (int)(blockIdx.x * kVoBlock + threadIdx.x); k < kVoPix && i < n; ++k, i += stride)
+        add_pixel(L, R, t, i, acc);
 #pragma unroll
     for (int k = 0; k < kVoTerms; ++k) red[k][threadIdx.x] = acc[k];
     __syncthreads();
@@ -169,34 +178,21 @@ __device__ inline void se3_exp(const double xi[6], double Rd[9], double td[3]) {
     for (int i = 0; i < 3; ++i) td[i] = V[3 * i] * xi[0] + V[3 * i + 1] * xi[1] + V[3 * i + 2] * xi[2];
 }
 
-// Sums the block partials in double (thread j takes blocks j, j + 256, ...,
-// then a fixed tree), and either writes H (36), g (6), cost, count to `out`,
+// From the summed terms: either writes H (36), g (6), cost, count to `out`,
 // or takes the Gauss-Newton step xi = -(H + lambda I)^-1 g, lambda =
-// 1e-9 trace(H) / 6 (none below 16 pixels), and sets pose <- exp(xi) pose.
-__global__ __launch_bounds__(kVoBlock) void vo_solve_kernel(const float* part, int n_blocks, double* pose, double* out) {
-    __shared__ double red[kVoTerms][kVoBlock];
-    double acc[kVoTerms];
-    for (int k = 0; k < kVoTerms; ++k) acc[k] = 0.0;
-    for (int b = (int)threadIdx.x; b < n_blocks; b += kVoBlock)
-        for (int k = 0; k < kVoTerms; ++k) acc[k] += (double)part[(size_t)b * kVoTerms + k];
-    for (int k = 0; k < kVoTerms; ++k) red[k][threadIdx.x] = acc[k];
-    __syncthreads();
-    for (int s = kVoBlock / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int k = 0; k < kVoTerms; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x != 0) return;
+// 1e-9 trace(H) / 6 (none below 16 pixels, or when H + lambda I is not
+// positive definite), and sets pose <- exp(xi) pose.  One thread.
+__device__ inline void finish_level_step(const double (&sum)[kVoTerms], double* pose, double* out) {
     double H[36], g[6];
     int q = 0;
     for (int u = 0; u < 6; ++u)
         for (int v = u; v < 6; ++v) {
-            H[6 * u + v] = red[q][0];
-            H[6 * v + u] = red[q][0];
+            H[6 * u + v] = sum[q];
+            H[6 * v + u] = sum[q];
             ++q;
         }
-    for (int u = 0; u < 6; ++u) g[u] = red[21 + u][0];
-    const double cost = red[27][0], count = red[28][0];
+    for (int u = 0; u < 6; ++u) g[u] = sum[21 + u];
+    const double cost = sum[27], count = sum[28];
     if (out != nullptr) {
         for (int k = 0; k < 36; ++k) out[k] = H[k];
         for (int k = 0; k < 6; ++k) out[36 + k] = g[k];
@@ -211,7 +207,7 @@ __global__ __launch_bounds__(kVoBlock) void vo_solve_kernel(const float* part, i
     for (int j = 0; j < 6; ++j) {
         double s = H[6 * j + j];
         for (int k = 0; k < j; ++k) s -= H[6 * j + k] * H[6 * j + k];
-        if (!(s > 0.0)) return;   // not positive definite: no update
+        if (!(s > 0.0)) return;
         const double ljj = sqrt(s);
         H[6 * j + j] = ljj;
         for (int i = j + 1; i < 6; ++i) {
@@ -241,6 +237,78 @@ __global__ __launch_bounds__(kVoBlock) void vo_solve_kernel(const float* part, i
             pose[3 * i + j] = Rd[3 * i] * R[j] + Rd[3 * i + 1] * R[3 + j] + Rd[3 * i + 2] * R[6 + j];
         pose[9 + i] = Rd[3 * i] * t[0] + Rd[3 * i + 1] * t[1] + Rd[3 * i + 2] * t[2] + td[i];
     }
+}
+
+// Sums the block partials of vo_normal_kernel in double (thread j takes
+// blocks j, j + 256, ..., then a fixed tree) and finishes the step.
+__global__ __launch_bounds__(kVoBlock) void vo_solve_kernel(const float* part, int n_blocks, double* pose, double* out) {
+    __shared__ double red[kVoTerms][kVoBlock];
+    double acc[kVoTerms];
+    for (int k = 0; k < kVoTerms; ++k) acc[k] = 0.0;
+    for (int b = (int)threadIdx.x; b < n_blocks; b += kVoBlock)
+        for (int k = 0; k < kVoTerms; ++k) acc[k] += (double)part[(size_t)b * kVoTerms + k];
+    for (int k = 0; k < kVoTerms; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int s = kVoBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < kVoTerms; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    double sum[kVoTerms];
+    for (int k = 0; k < kVoTerms; ++k) sum[k] = red[k][0];
+    finish_level_step(sum, pose, out);
+}
+
+// Every iteration of one small level in one block of kVoSmallBlock threads:
+// the pose lives in LDS between iterations; per iteration each thread sums
+// its pixels (stride kVoSmallBlock) in float32, each wave folds its lanes by
+// an xor butterfly, and thread 0 adds the waves in double and takes the step.
+constexpr int kVoSmallBlock = 1024;
+__global__ __launch_bounds__(kVoSmallBlock) void vo_small_level_kernel(VoLevel L, int iters, double* pose, double* out) {
+    __shared__ float wsum[kVoSmallBlock / 64][kVoTerms];
+    __shared__ double pose_s[12];
+    __shared__ double dsum[kVoTerms];
+    const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid < 12) pose_s[tid] = pose[tid];
+    __syncthreads();
+    const int n = L.w * L.h;
+    for (int it = 0; it < iters; ++it) {
+        float R[9], t[3];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) R[k] = (float)pose_s[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) t[k] = (float)pose_s[9 + k];
+        float acc[kVoTerms];
+#pragma unroll
+        for (int k = 0; k < kVoTerms; ++k) acc[k] = 0.0f;
+        for (int i = tid; i < n; i += kVoSmallBlock) add_pixel(L, R, t, i, acc);
+#pragma unroll
+        for (int k = 0; k < kVoTerms; ++k) {
+            float v = acc[k];
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+            acc[k] = v;
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < kVoTerms; ++k) wsum[wave][k] = acc[k];
+        }
+        __syncthreads();
+        if (tid < kVoTerms) {   // one term per thread, the waves in order
+            double v = 0.0;
+            for (int w = 0; w < kVoSmallBlock / 64; ++w) v += (double)wsum[w][tid];
+            dsum[tid] = v;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double sum[kVoTerms];
+            for (int k = 0; k < kVoTerms; ++k) sum[k] = dsum[k];
+            finish_level_step(sum, pose_s, out);
+        }
+        __syncthreads();
+    }
+    if (tid < 12) pose[tid] = pose_s[tid];
 }
 
 unsigned vo_grid(int n) { return (unsigned)((n + kVoBlock - 1) / kVoBlock); }
@@ -309,9 +377,16 @@ hipError_t launch_vo(const VoArgs& v, hipStream_t s) {
                   (float)(v.f / sc * v.baseline), (float)(v.min_disp / sc), v.huber};
         const int nb = (int)vo_partial_blocks(wl, hl);
         const int iters = v.only_level >= 0 ? 1 : v.iters[l];
+        double* out = v.only_level >= 0 ? v.out : nullptr;
+        if (iters == 0) continue;
+        if (wl * hl <= kVoSmallLevel) {
+            // a small level: all its iterations in one block, one launch
+            vo_small_level_kernel<<<1, kVoSmallBlock, 0, s>>>(L, iters, v.pose, out);
+            continue;
+        }
         for (int it = 0; it < iters; ++it) {
             vo_normal_kernel<<<(unsigned)nb, kVoBlock, 0, s>>>(L, v.pose, part);
-            vo_solve_kernel<<<1, kVoBlock, 0, s>>>(part, nb, v.pose, v.only_level >= 0 ? v.out : nullptr);
+            vo_solve_kernel<<<1, kVoBlock, 0, s>>>(part, nb, v.pose, out);
         }
     }
     return hipGetLastError();

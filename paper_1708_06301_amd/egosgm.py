@@ -497,7 +497,7 @@ class VOParams(C.Structure):
                 ("min_disp", C.c_float)]
 
 
-def vo_params(levels=5, iters=(2, 4, 8, 10, 10, 10), huber=8.0, min_disp=1.0) -> VOParams:
+def vo_params(levels=5, iters=(2, 4, 8, 10, 20, 30), huber=8.0, min_disp=1.0) -> VOParams:
     it = list(iters)[:VO_MAX_LEVELS] + [0] * (VO_MAX_LEVELS - len(iters))
     return VOParams(int(levels), (C.c_int * VO_MAX_LEVELS)(*it), float(huber), float(min_disp))
 

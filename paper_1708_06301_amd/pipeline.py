@@ -51,7 +51,10 @@ class FrameConfig:
     overlap_census: bool = False  # step(): census on a second stream (measured 2% slower here)
     vo: bool = False          # step(): ego-motion from the images (estimate_motion) instead of R, t given
     vo_levels: int = 0        # pyramid levels (0: the coarsest level stays >= 64 x 16)
-    vo_iters: tuple = (2, 4, 8, 10, 10, 10)   # Gauss-Newton iterations per level, finest first
+    # Gauss-Newton iterations per level, finest first, starting from the previous frame's motion
+    # (more gave the same poses on the street sequences), and without one to start from
+    vo_iters: tuple = (1, 2, 2, 2, 2, 2)
+    vo_iters_first: tuple = (2, 4, 8, 10, 20, 30)
     vo_huber: float = 8.0
     vo_min_disp: float = 1.0
 
@@ -105,6 +108,7 @@ class StreamState:
         if cfg.vo:   # previous left image, the motion estimate (kept as the next guess)
             levels = cfg.vo_levels or eg.vo_levels_for(w, h)
             self.vo_prm = eg.vo_params(levels, cfg.vo_iters[:levels], cfg.vo_huber, cfg.vo_min_disp)
+            self.vo_prm_first = eg.vo_params(levels, cfg.vo_iters_first[:levels], cfg.vo_huber, cfg.vo_min_disp)
             self.vo_ws = eg.vo_workspace(w, h, self.vo_prm, dev)
             self.prev_left = torch.empty((h, w), dtype=torch.uint8, device=dev)
             self.vo_pose = torch.zeros(12, dtype=torch.float64, device=dev)
@@ -211,12 +215,13 @@ class StreamState:
         left image (estimate_motion), starting from the previous frame's
         estimate; reads the result to the host (a synchronisation), since the
         warp takes the motion as host values."""
-        if self.vo_motion is None:
+        first = self.vo_motion is None
+        if first:   # no previous estimate: start at rest, with more iterations on the coarse levels
             self.vo_pose.copy_(torch.tensor(np.concatenate([np.eye(3).ravel(), np.zeros(3)]),
                                             dtype=torch.float64))
         c = self.calib
-        eg.estimate_motion(self.prev_left, left, self.d, (c.f, c.cx, c.cy, c.baseline), self.vo_prm,
-                           pose=self.vo_pose, workspace=self.vo_ws)
+        eg.estimate_motion(self.prev_left, left, self.d, (c.f, c.cx, c.cy, c.baseline),
+                           self.vo_prm_first if first else self.vo_prm, pose=self.vo_pose, workspace=self.vo_ws)
         self.vo_motion = eg.pose_to_host(self.vo_pose)
         return self.vo_motion
 

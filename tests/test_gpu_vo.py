@@ -115,6 +115,7 @@ def test_pipeline_with_visual_odometry():
     cfg = pipeline.FrameConfig(max_disp=64, r_fixed=4, vo=True)
     st = pipeline.StreamState(w, h, pipeline.camera_of(seq), cfg, DEV)
     oprm = vo.VOParams(levels=st.vo_prm.levels, iters=tuple(st.vo_prm.iters[:st.vo_prm.levels]))
+    oprm1 = vo.VOParams(levels=st.vo_prm.levels, iters=tuple(st.vo_prm_first.iters[:st.vo_prm.levels]))
     for k in range(nf):
         L, R, _ = seq.frame(k)
         if k > 0:
@@ -124,7 +125,8 @@ def test_pipeline_with_visual_odometry():
         if k > 0:
             Rk, tk = st.vo_motion
             R0, t0 = guess if guess is not None else (np.eye(3), np.zeros(3))
-            Ro, to = vo.estimate_motion(prev_L, L, d_prev, *_calib(seq.cam), oprm, R0, t0)
+            Ro, to = vo.estimate_motion(prev_L, L, d_prev, *_calib(seq.cam), oprm if guess is not None else oprm1,
+                                        R0, t0)
             dt, da = _pose_diff(Rk, tk, Ro, to)
             assert dt < 1e-4 and da < 1e-4, (k, dt, da)
             et, ea = _pose_diff(Rk, tk, *seq.motion(k))
