@@ -1762,8 +1762,8 @@ __global__ __launch_bounds__(kBlock) void cost_frame_kernel(SgmLaunch a) {
 // Selection in the quad layout (same results as select_segment).  One block
 // per 64-pixel row segment, wave v taking pixels 16v .. 16v+15: a pixel whose
 // window span fits 16 slots is done by a group of 4 lanes (lane j owning the
-// quad B + 4j), each wider one by the whole wave (lane L owning B + 4L), one
-// after another.  S is summed from the path volumes a dword (four slots) per
+// quad B + 4j), the wider ones four at a time by 16-lane groups (lane l
+// owning the four quads B + 16l ..).  S is summed from the path volumes a dword (four slots) per
 // direction and lane; the winner key (S << 9 | d) is a minimum over the
 // group; the pixel's S row is staged in LDS for the parabola and the
 // uncertainty walk of Eq. 9 (lane 0 of the group); each slot offers its key
@@ -1773,7 +1773,7 @@ template <int NPATH>
 __global__ __launch_bounds__(kBlock) void select_quad_kernel(SgmLaunch a) {
     __shared__ uint32_t keyR[kSeg + kMaxDisp];
     __shared__ __attribute__((aligned(16))) uint16_t sS[kSeg][16];
-    __shared__ __attribute__((aligned(16))) uint16_t sW[kBlock / 64][kMaxDisp + 4];
+    __shared__ __attribute__((aligned(16))) uint16_t sW[kBlock / 64][4][kMaxDisp + 8];
     __shared__ float s_sub[kSeg], s_var[kSeg];
     __shared__ int16_t s_wta[kSeg];
     const int W = a.w, D = a.win.max_disp;
@@ -1879,31 +1879,53 @@ __global__ __launch_bounds__(kBlock) void select_quad_kernel(SgmLaunch a) {
         lds_order();
         if (jq == 0) epilogue(sS[i], B, lo, w, kb & 511, kb >> 9, i);
     }
-    // wide pixels of this wave, one after another
+    // wide pixels of this wave, four at a time: lane group g (16 lanes, one
+    // DPP row) takes the g-th, lane l of the group the 16 slots
+    // B + 16 l .. B + 16 l + 15 (four quads, one 16-byte load per direction;
+    // a group without a pixel loads nothing)
     uint64_t wbits = __builtin_amdgcn_ballot_w64(in_row && !nar && jq == 0);
-    uint16_t* row = sW[wv];
+    const int gw16 = lane >> 4, l16 = lane & 15;
+    uint16_t* row = sW[wv][gw16];
     while (wbits) {
-        const int bit = (int)__builtin_ctzll(wbits);
-        wbits &= wbits - 1;
-        const int lo_g = __builtin_amdgcn_readlane(lo, bit), w_g = __builtin_amdgcn_readlane(w, bit);
-        const uint32_t q_g = (uint32_t)__builtin_amdgcn_readlane((int)q, bit);
+        // the group's pixel: the gw16-th remaining wide pixel of the wave
+        uint64_t m = wbits;
+        for (int k2 = 0; k2 < gw16 && m; ++k2) m &= m - 1;
+        const bool has = m != 0;
+        const int bit = has ? (int)__builtin_ctzll(m) : 0;
+        for (int k2 = 0; k2 < 4 && wbits; ++k2) wbits &= wbits - 1;
+        const int lo_g = __builtin_amdgcn_ds_bpermute(bit << 2, lo), w_g = __builtin_amdgcn_ds_bpermute(bit << 2, w);
+        const uint32_t q_g = (uint32_t)__builtin_amdgcn_ds_bpermute(bit << 2, (int)q);
         const int ig = 16 * wv + (bit >> 2), xg = x0 + ig;
         const int Bg = lo_g & ~3, Eg = (lo_g + w_g + 3) & ~3;
-        const int d = Bg + 4 * lane;
+        const int d0 = Bg + 16 * l16;
+        const bool any = has && d0 < Eg;
+        u32x4 v[NPATH];
+#pragma unroll
+        for (int r = 0; r < NPATH; ++r)
+            v[r] = __builtin_amdgcn_raw_buffer_load_b128(vb[r], any ? q_g + 16u * (uint32_t)l16 : kDropOffset, 0, 0);
         int kb = 0x7fffffff;
-        if (d < Eg) {
-            uint32_t s01, s23;
-            sum_quad(q_g + 4u * (uint32_t)lane, s01, s23);
-            kb = min(min(key_of(s01 & 0xffffu, d, lo_g, w_g), key_of(s01 >> 16, d + 1, lo_g, w_g)),
-                     min(key_of(s23 & 0xffffu, d + 2, lo_g, w_g), key_of(s23 >> 16, d + 3, lo_g, w_g)));
-            *reinterpret_cast<u32x2*>(&row[4 * lane]) = u32x2{s01, s23};
-            offer(s01, s23, d, lo_g, w_g, xg, ig);
-            debug_agg(s01, s23, d, lo_g, w_g, y * W + xg);
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+            const int d = d0 + 4 * qq;
+            if (any && d < Eg) {
+                uint32_t s01 = 0, s23 = 0;
+#pragma unroll
+                for (int r = 0; r < NPATH; ++r) {
+                    const uint32_t vq = qq == 0 ? v[r].x : qq == 1 ? v[r].y : qq == 2 ? v[r].z : v[r].w;
+                    s01 = pk_add(s01, bytes01(vq));
+                    s23 = pk_add(s23, bytes23(vq));
+                }
+                kb = min(kb, min(min(key_of(s01 & 0xffffu, d, lo_g, w_g), key_of(s01 >> 16, d + 1, lo_g, w_g)),
+                                 min(key_of(s23 & 0xffffu, d + 2, lo_g, w_g), key_of(s23 >> 16, d + 3, lo_g, w_g))));
+                *reinterpret_cast<u32x2*>(&row[16 * l16 + 4 * qq]) = u32x2{s01, s23};
+                offer(s01, s23, d, lo_g, w_g, xg, ig);
+                debug_agg(s01, s23, d, lo_g, w_g, y * W + xg);
+            }
         }
-        const int kw = group_min<64>(kb);
+        const int kw = row_min16(kb);
         lds_order();
-        if (lane == 0) epilogue(row, Bg, lo_g, w_g, kw & 511, kw >> 9, ig);
-        lds_order();   // the next wide pixel rewrites the row
+        if (has && l16 == 0) epilogue(row, Bg, lo_g, w_g, kw & 511, kw >> 9, ig);
+        lds_order();   // the next pixels rewrite the rows
     }
     __syncthreads();
     if (threadIdx.x < kSeg && x0 + (int)threadIdx.x < W) {
