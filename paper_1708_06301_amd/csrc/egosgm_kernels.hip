@@ -1685,7 +1685,7 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_regroup_kernel(SgmLaunch a, 
 __global__ __launch_bounds__(kBlock) void cost_frame_kernel(SgmLaunch a) {
     __shared__ uint64_t crs[kSeg + kMaxDisp];
     __shared__ uint64_t cls[kSeg];
-    __shared__ uint32_t s_pre[kSeg + 1];   // quads before each pixel of the segment
+    __shared__ int s_wide[kSeg + 1];   // the segment's wide pixels, then their count
     __shared__ int s_b[kSeg], s_lo[kSeg], s_w[kSeg];
     __shared__ uint32_t s_q[kSeg];
     const int W = a.w, D = a.win.max_disp;
@@ -1711,18 +1711,15 @@ __global__ __launch_bounds__(kBlock) void cost_frame_kernel(SgmLaunch a) {
                                ((uint64_t)(fr.narrow ? 0 : fr.span) << 50);
             s_b[i] = fr.base;
             s_lo[i] = lo;
-            s_w[i] = w;
+            s_w[i] = fr.narrow ? w : -w;   // negative: a wide pixel
             s_q[i] = q;
-            nq = (uint32_t)(fr.span >> 2);
+            nq = fr.narrow ? 0u : (uint32_t)(fr.span >> 2);
+        } else {
+            s_w[i] = 0;   // no pixel: nothing to write
         }
-        uint32_t inc = nq;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t v = __shfl_up(inc, o, 64);
-            if (i >= o) inc += v;
-        }
-        s_pre[i + 1] = inc;
-        if (i == 0) s_pre[0] = 0;
+        const uint64_t wb = __builtin_amdgcn_ballot_w64(nq != 0u);
+        if (nq != 0u) s_wide[__builtin_amdgcn_mbcnt_hi((uint32_t)(wb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)wb, 0u))] = i;
+        if (i == 0) s_wide[kSeg] = __builtin_popcountll(wb);
     }
     for (int i = threadIdx.x; i < kSeg + D - 1; i += kBlock) {
         const int xr = base + i;
@@ -1730,21 +1727,14 @@ __global__ __launch_bounds__(kBlock) void cost_frame_kernel(SgmLaunch a) {
     }
     for (int i = threadIdx.x; i < kSeg; i += kBlock) cls[i] = (x0 + i < W) ? rowl[x0 + i] : 0ull;
     __syncthreads();
-    const uint32_t total = s_pre[kSeg];
     gmem<uint32_t>* cost = reinterpret_cast<gmem<uint32_t>*>(gptr(a.cost));
     // a run of 64 padding markers at the end of the volume, which lanes of
     // a wide pixel outside its span read as their costs
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 16)
         cost[((uint32_t)a.vol_stride - 64u) / 4u + threadIdx.x] = 0xffffffffu;
-    for (uint32_t k = threadIdx.x; k < total; k += kBlock) {
-        int i = 0;
-#pragma unroll
-        for (int st = 32; st > 0; st >>= 1)
-            if (s_pre[i + st] <= k) i += st;
+    // one quad of four costs: C(p, d) inside the window, the padding marker outside
+    auto quad = [&](int i, int d, int lo, int w) {
         const int x = x0 + i;
-        const uint32_t qk = k - s_pre[i];
-        const int d = s_b[i] + 4 * (int)qk;
-        const int lo = s_lo[i], w = s_w[i];
         const uint64_t cl = cls[i];
         uint32_t word = 0;
 #pragma unroll
@@ -1755,7 +1745,24 @@ __global__ __launch_bounds__(kBlock) void cost_frame_kernel(SgmLaunch a) {
                 c = x - dd >= 0 ? (uint32_t)__popcll(cl ^ crs[i + (D - 1) - dd]) : (uint32_t)kCensusBits;
             word |= c << (8 * b);
         }
-        cost[(s_q[i] >> 2) + qk] = word;
+        return word;
+    };
+    // narrow frames (F/4 quads each): four threads per pixel
+    {
+        const int i = (int)threadIdx.x >> 2, j = (int)threadIdx.x & 3;
+        const int w = s_w[i];
+        if (w > 0) {
+            const int lo = s_lo[i], B = s_b[i];
+            for (int qk = j; qk < (int)(F >> 2); qk += 4) cost[(s_q[i] >> 2) + (uint32_t)qk] = quad(i, B + 4 * qk, lo, w);
+        }
+    }
+    // wide spans: one wave per pixel, a quad per lane
+    const int n_wide = s_wide[kSeg];
+    for (int v = (int)threadIdx.x >> 6; v < n_wide; v += kBlock / 64) {
+        const int i = s_wide[v], lo = s_lo[i], w = -s_w[i], B = s_b[i];
+        const int nq = (((lo + w + 15) & ~15) - B) >> 2;
+        for (int qk = (int)threadIdx.x & 63; qk < nq; qk += 64)
+            cost[(s_q[i] >> 2) + (uint32_t)qk] = quad(i, B + 4 * qk, lo, w);
     }
 }
 
