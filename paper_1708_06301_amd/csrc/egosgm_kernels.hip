@@ -1136,14 +1136,6 @@ __device__ inline uint32_t bytes01(uint32_t v) { return __builtin_amdgcn_perm(0u
 __device__ inline uint32_t bytes23(uint32_t v) { return __builtin_amdgcn_perm(0u, v, 0x0C030C02u); }
 // low bytes of the two 16-bit halves of a and b -> a.lo, a.hi, b.lo, b.hi
 __device__ inline uint32_t pack4(uint32_t a, uint32_t b) { return __builtin_amdgcn_perm(b, a, 0x06040200u); }
-__device__ inline uint32_t pk_max(uint32_t a, uint32_t b) {
-    return as_u32(__builtin_elementwise_max(as_pk(a), as_pk(b)));
-}
-// +infinity in the halves of a pair whose slot lies outside [lo, lo+w)
-__device__ inline uint32_t pair_mask(int d, int lo, int w) {
-    return ((uint32_t)(d - lo) < (uint32_t)w ? 0u : (uint32_t)kInf) |
-           ((uint32_t)(d + 1 - lo) < (uint32_t)w ? 0u : (uint32_t)kInf << 16);
-}
 
 // Minimum over each 8-lane half of a 16-lane row, left in all its lanes.
 __device__ inline int min8(int v) {
@@ -1475,7 +1467,7 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_hybrid_kernel(SgmLaunch a, G
 // The first step uses a zero predecessor, so it gives L = C.
 template <int DMAX, int PF>
 __global__ __launch_bounds__(kBlock) void sgm_paths_regroup_kernel(SgmLaunch a, GroupTasks t) {
-    constexpr int G = 16, NG = 4, F = 32;
+    constexpr int G = 16, NG = 4;
     constexpr int NPW = DMAX / 32;   // wide registers per lane
     constexpr int WD = NPW / 2;      // wide cost dwords per lane
     constexpr int RM = 2 * PF;

@@ -134,3 +134,30 @@ def test_pipeline_with_visual_odometry():
         prev_L = L
     torch.cuda.synchronize()
     assert (st.d.cpu().numpy() > 0).mean() > 0.8
+
+
+def test_estimate_edge_cases_pitch_and_empty_map():
+    """Row-padded images give the same estimate bit for bit; a map with no
+    disparity leaves the initial guess unchanged (no level step has 16
+    pixels)."""
+    _say("vo pitch and empty map")
+    seq, L0, L1, gt0 = _pair(640, 192, 1)
+    prm = eg.vo_params(4, (1, 2, 3, 4))
+    calib = _calib(seq.cam)
+    a = eg.estimate_motion(_gpu(L0), _gpu(L1), _gpu(gt0), calib, prm)
+    h, w = L0.shape
+    pitch = w + 13
+    P0 = np.zeros((h, pitch), np.uint8)
+    P1 = np.zeros((h, pitch), np.uint8)
+    P0[:, :w], P1[:, :w] = L0, L1
+    g0, g1 = _gpu(P0), _gpu(P1)
+    ws = eg.vo_workspace(w, h, prm, DEV)
+    pose = torch.tensor(np.concatenate([np.eye(3).ravel(), np.zeros(3)]), dtype=torch.float64, device=DEV)
+    rc = eg.lib().estimate_motion(eg._ptr(g0), eg._ptr(g1), w, h, pitch, eg._ptr(_gpu(gt0)), *[float(v) for v in calib],
+                                  eg.C.byref(prm), eg._ptr(pose), eg._ptr(ws), ws.numel(), eg._stream())
+    assert rc == 0
+    assert torch.equal(a, pose)
+    R0, t0 = vo.se3_exp([0.0, 0.0, -0.5, 0.0, 0.01, 0.0])
+    b = eg.estimate_motion(_gpu(L0), _gpu(L1), _gpu(np.full_like(gt0, -1.0)), calib, prm, R0=R0, t0=t0)
+    R, t = eg.pose_to_host(b)
+    assert np.array_equal(R, R0) and np.array_equal(t, t0)
