@@ -1119,7 +1119,14 @@ __device__ inline Frame frame_of(int lo, int w, int F) {
     const int bw = lo & ~15;
     return Frame{bw, ((lo + w + 15) & ~15) - bw, false};
 }
-__device__ inline uint32_t frame_off(uint32_t off, uint32_t p) { return (off + 35u * p + 3u) & ~3u; }
+// Byte offset of pixel p's frame in a volume of n pixels: narrow frames in a
+// dense first region, 32 bytes per pixel (a frame never shares a line with a
+// pixel it does not neighbour); wide spans after it, from the window offset
+// plus 35 bytes per pixel, so two spans never overlap (consecutive ones are
+// at least w + 32 apart, a span is at most w + 30).
+__device__ inline uint32_t frame_off(bool narrow, uint32_t off, uint32_t p, uint32_t n) {
+    return narrow ? 32u * p : (32u * n + off + 35u * p + 3u) & ~3u;
+}
 constexpr uint32_t kPadCost = 255;
 // Costs of two slots (bytes b0 b1 of v, or b2 b3) as a packed pair, with the
 // padding marker 255 raised to 255 + 0x4000: a slot carrying it stays above
@@ -1694,8 +1701,8 @@ __global__ __launch_bounds__(kBlock) void cost_frame_kernel(SgmLaunch a) {
             const int lo = gptr(a.win.lo)[p], hi = gptr(a.win.hi)[p];
             const uint32_t off = gptr(a.win.off)[p];
             const int w = hi - lo + 1;
-            const uint32_t q = frame_off(off, (uint32_t)p);
             const Frame fr = frame_of(lo, w, (int)F);
+            const uint32_t q = frame_off(fr.narrow, off, (uint32_t)p, (uint32_t)W * (uint32_t)a.h);
             // the window word's offset addresses slot lo (q + d - base for slot
             // d), as in the ragged layout, so every path kernel can read it
             gptr(a.meta)[p] = pack_meta(q + (uint32_t)(lo - fr.base), lo, w);
@@ -2593,9 +2600,10 @@ hipError_t launch_census_pair(const uint8_t* left, const uint8_t* right, int w, 
 }
 
 size_t quad_volume_bytes(int w, int h, int D) {
-    // frames of up to 32 slots: w*h*(D + 35) + 64 bytes, below the drop offset
+    // 32 bytes per pixel of narrow frames, then wide spans in w*h*(D + 35)
+    // bytes, then 64 marker bytes; below the drop offset
     const unsigned long long n = (unsigned long long)w * (unsigned long long)h;
-    const unsigned long long b = (n * (unsigned long long)(D + 35) + 64ull + 255ull) & ~255ull;
+    const unsigned long long b = (n * (unsigned long long)(D + 67) + 64ull + 255ull) & ~255ull;
     return b < (unsigned long long)kDropWide ? (size_t)b : 0;
 }
 
