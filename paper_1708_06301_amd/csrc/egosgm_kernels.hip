@@ -1121,11 +1121,12 @@ __device__ inline Frame frame_of(int lo, int w, int F) {
 }
 // Byte offset of pixel p's frame in a volume of n pixels: narrow frames in a
 // dense first region, 32 bytes per pixel (a frame never shares a line with a
-// pixel it does not neighbour); wide spans after it, from the window offset
-// plus 35 bytes per pixel, so two spans never overlap (consecutive ones are
-// at least w + 32 apart, a span is at most w + 30).
+// pixel it does not neighbour); wide spans after it, each on a 128-byte line
+// boundary at the window offset plus 163 bytes per pixel rounded up, so two
+// spans never overlap (consecutive ones are at least w + 36 apart, a span is
+// at most w + 30) and a span of 256 slots is two whole lines.
 __device__ inline uint32_t frame_off(bool narrow, uint32_t off, uint32_t p, uint32_t n) {
-    return narrow ? 32u * p : (32u * n + off + 35u * p + 3u) & ~3u;
+    return narrow ? 32u * p : ((32u * n + 127u) & ~127u) + ((off + 163u * p + 127u) & ~127u);
 }
 constexpr uint32_t kPadCost = 255;
 // Costs of two slots (bytes b0 b1 of v, or b2 b3) as a packed pair, with the
@@ -2600,10 +2601,11 @@ hipError_t launch_census_pair(const uint8_t* left, const uint8_t* right, int w, 
 }
 
 size_t quad_volume_bytes(int w, int h, int D) {
-    // 32 bytes per pixel of narrow frames, then wide spans in w*h*(D + 35)
-    // bytes, then 64 marker bytes; below the drop offset
+    // 32 bytes per pixel of narrow frames, then the line-aligned wide spans
+    // (below w*h*(D + 163) + 512 bytes), then 64 marker bytes; below the drop offset
     const unsigned long long n = (unsigned long long)w * (unsigned long long)h;
-    const unsigned long long b = (n * (unsigned long long)(D + 67) + 64ull + 255ull) & ~255ull;
+    const unsigned long long a = (32ull * n + 127ull) & ~127ull;
+    const unsigned long long b = (a + n * (unsigned long long)(D + 163) + 512ull + 64ull + 255ull) & ~255ull;
     return b < (unsigned long long)kDropWide ? (size_t)b : 0;
 }
 
