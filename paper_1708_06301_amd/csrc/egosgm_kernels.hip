@@ -2620,17 +2620,6 @@ hipError_t launch_sgm_cost(const SgmLaunch& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Dynamic LDS that lets at most `blocks` blocks of a kernel with `static_bytes`
-// of static LDS share a CU (0 if the device cannot be queried).
-static size_t lds_occupancy_cap(int blocks, size_t static_bytes) {
-    int dev = 0, lds = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess || lds <= 0)
-        return 0;
-    const size_t per_block = (size_t)lds / (size_t)(blocks + 1) + 1024;   // blocks + 1 of them do not fit
-    return per_block > static_bytes ? per_block - static_bytes : 0;
-}
-
 hipError_t launch_sgm_paths(const SgmLaunch& a, hipStream_t s) {
     const int n_tasks = 2 * a.h + 2 * a.w + (a.n_paths == 4 ? 0 : 4 * (a.w + a.h - 1));
     const int D = a.win.max_disp;
@@ -2689,15 +2678,10 @@ hipError_t launch_sgm_paths(const SgmLaunch& a, hipStream_t s) {
         }
         const unsigned nb = (unsigned)((t.wave_start[t.n_dirs] + kBlock / 64 - 1) / (kBlock / 64));
         if (sched == 8) {
-            // at most three blocks per CU (LDS reserved for it): the row
-            // scanlines, which set the kernel's length, then share their SIMD
-            // with at most two other waves (at 2048x1024, D = 256: 1080 us
-            // per reduced frame against 1164 at four waves per SIMD)
-            const int dm = D <= 64 ? 64 : D <= 128 ? 128 : 256;
-            const size_t xl = lds_occupancy_cap(3, sizeof(uint32_t) * (kBlock / 64) * 4 * (dm / 2 + 16));
-            if (D <= 64) sgm_paths_regroup_kernel<64, 4><<<nb, kBlock, xl, s>>>(a, t);
-            else if (D <= 128) sgm_paths_regroup_kernel<128, 4><<<nb, kBlock, xl, s>>>(a, t);
-            else sgm_paths_regroup_kernel<256, 6><<<nb, kBlock, xl, s>>>(a, t);
+            // D = 256: costs six steps ahead (162 VGPRs, three waves per SIMD)
+            if (D <= 64) sgm_paths_regroup_kernel<64, 4><<<nb, kBlock, 0, s>>>(a, t);
+            else if (D <= 128) sgm_paths_regroup_kernel<128, 4><<<nb, kBlock, 0, s>>>(a, t);
+            else sgm_paths_regroup_kernel<256, 6><<<nb, kBlock, 0, s>>>(a, t);
             return hipGetLastError();
         }
         if (hybrid) {
