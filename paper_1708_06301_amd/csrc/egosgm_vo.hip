@@ -11,6 +11,7 @@
 // motion from a feature-based odometry it cites; this front end is the
 // library's own.)
 //
+// The pyramid is one kernel per level (images, disparities and gradients).
 // Per iteration of a large level: one kernel evaluates every pixel's
 // residual and Jacobian and reduces the normal equations (21 + 6 + cost +
 // count terms) per block in float32; one single-block kernel sums the block
@@ -31,36 +32,41 @@ constexpr int kVoPix = 4;       // pixels per thread in the normal-equation pass
 constexpr int kVoTerms = 29;    // 21 (upper triangle of H) + 6 (g) + cost + count
 constexpr int kVoSmallLevel = 1 << 13;   // levels of at most this many pixels run in one block
 
+// Level 0: both images as float, and the central differences of the
+// current one, (I(x+1) - I(x-1)) * 0.5, zero on the border.
 __global__ __launch_bounds__(kVoBlock) void vo_level0_kernel(const uint8_t* prev, const uint8_t* cur, int w, int h,
-                                                              int pitch, float* ref0, float* cur0) {
+                                                              int pitch, float* ref0, float* cur0, float* gx,
+                                                              float* gy) {
     const int i = (int)(blockIdx.x * kVoBlock + threadIdx.x);
     if (i >= w * h) return;
     const int y = i / w, x = i - y * w;
+    const uint8_t* c = cur + (size_t)y * pitch + x;
     ref0[i] = (float)prev[(size_t)y * pitch + x];
-    cur0[i] = (float)cur[(size_t)y * pitch + x];
+    cur0[i] = (float)c[0];
+    gx[i] = (x > 0 && x < w - 1) ? ((float)c[1] - (float)c[-1]) * 0.5f : 0.0f;
+    gy[i] = (y > 0 && y < h - 1) ? ((float)c[pitch] - (float)c[-pitch]) * 0.5f : 0.0f;
 }
 
 // Level l from level l-1 (sizes w x h of level l): images by the 2x2 mean
-// ((a + b) + (c + d)) * 0.25, disparities by the sample at (2x, 2y), halved.
+// ((a + b) + (c + d)) * 0.25, disparities by the sample at (2x, 2y), halved,
+// and the central differences of the current image, zero on the border (its
+// neighbours' means are recomputed the same way, so they equal the stored ones).
 __global__ __launch_bounds__(kVoBlock) void vo_down_kernel(const float* ref_in, const float* cur_in, const float* d_in,
-                                                            int w_in, float* ref, float* cur, float* d, int w, int h) {
+                                                            int w_in, float* ref, float* cur, float* d, float* gx,
+                                                            float* gy, int w, int h) {
     const int i = (int)(blockIdx.x * kVoBlock + threadIdx.x);
     if (i >= w * h) return;
     const int y = i / w, x = i - y * w;
-    const size_t a = (size_t)(2 * y) * w_in + 2 * x, c = a + w_in;
-    ref[i] = ((ref_in[a] + ref_in[a + 1]) + (ref_in[c] + ref_in[c + 1])) * 0.25f;
-    cur[i] = ((cur_in[a] + cur_in[a + 1]) + (cur_in[c] + cur_in[c + 1])) * 0.25f;
-    const float s = d_in[a];
+    auto mean = [&](const float* I, int xx, int yy) {
+        const size_t a = (size_t)(2 * yy) * w_in + 2 * xx, c = a + w_in;
+        return ((I[a] + I[a + 1]) + (I[c] + I[c + 1])) * 0.25f;
+    };
+    ref[i] = mean(ref_in, x, y);
+    cur[i] = mean(cur_in, x, y);
+    const float s = d_in[(size_t)(2 * y) * w_in + 2 * x];
     d[i] = s > 0.0f ? s * 0.5f : -1.0f;
-}
-
-// Central differences of the current image, zero on the border.
-__global__ __launch_bounds__(kVoBlock) void vo_grad_kernel(const float* I, int w, int h, float* gx, float* gy) {
-    const int i = (int)(blockIdx.x * kVoBlock + threadIdx.x);
-    if (i >= w * h) return;
-    const int y = i / w, x = i - y * w;
-    gx[i] = (x > 0 && x < w - 1) ? (I[i + 1] - I[i - 1]) * 0.5f : 0.0f;
-    gy[i] = (y > 0 && y < h - 1) ? (I[i + w] - I[i - w]) * 0.5f : 0.0f;
+    gx[i] = (x > 0 && x < w - 1) ? (mean(cur_in, x + 1, y) - mean(cur_in, x - 1, y)) * 0.5f : 0.0f;
+    gy[i] = (y > 0 && y < h - 1) ? (mean(cur_in, x, y + 1) - mean(cur_in, x, y - 1)) * 0.5f : 0.0f;
 }
 
 struct VoLevel {
@@ -308,7 +314,7 @@ __global__ __launch_bounds__(kVoSmallBlock) void vo_small_level_kernel(VoLevel L
         }
         __syncthreads();
     }
-    if (tid < 12) pose[tid] = pose_s[tid];
+    if (out == nullptr && tid < 12) pose[tid] = pose_s[tid];   // `out`: the pose is read only
 }
 
 unsigned vo_grid(int n) { return (unsigned)((n + kVoBlock - 1) / kVoBlock); }
@@ -357,15 +363,12 @@ hipError_t launch_vo(const VoArgs& v, hipStream_t s) {
     }
     float* part = p;
     // pyramids
-    vo_level0_kernel<<<vo_grid(v.w * v.h), kVoBlock, 0, s>>>(v.prev, v.cur, v.w, v.h, v.pitch, mref[0], mcur[0]);
+    vo_level0_kernel<<<vo_grid(v.w * v.h), kVoBlock, 0, s>>>(v.prev, v.cur, v.w, v.h, v.pitch, mref[0], mcur[0],
+                                                            mgx[0], mgy[0]);
     for (int l = 1; l < v.levels; ++l) {
         const int wl = vo_level_w(v.w, l), hl = vo_level_h(v.h, l);
         vo_down_kernel<<<vo_grid(wl * hl), kVoBlock, 0, s>>>(ref[l - 1], cur[l - 1], dsp[l - 1], vo_level_w(v.w, l - 1),
-                                                              mref[l], mcur[l], mdsp[l], wl, hl);
-    }
-    for (int l = 0; l < v.levels; ++l) {
-        const int wl = vo_level_w(v.w, l), hl = vo_level_h(v.h, l);
-        vo_grad_kernel<<<vo_grid(wl * hl), kVoBlock, 0, s>>>(cur[l], wl, hl, mgx[l], mgy[l]);
+                                                              mref[l], mcur[l], mdsp[l], mgx[l], mgy[l], wl, hl);
     }
     // levels coarse to fine (or the one level asked for)
     for (int l = v.levels - 1; l >= 0; --l) {
