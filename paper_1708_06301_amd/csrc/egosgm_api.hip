@@ -183,10 +183,14 @@ int run_sgm(const uint8_t* left, const uint8_t* right, int w, int h, int pitch, 
     // grouped scanlines (schedules 4, 5) need the quad layout; where its
     // offsets would not fit 32 bits the rows-on-registers schedule runs instead
     a.quad = 0;
+    a.frame_pairs = 0;
     if (win.lo != nullptr && a.ragged_schedule >= 4) {
-        if (L.vol_stride_q != 0)
+        if (L.vol_stride_q != 0) {
             a.quad = (a.ragged_schedule == 5 || a.ragged_schedule == 6 || a.ragged_schedule == 8) ? 16 : 8;
-        else a.ragged_schedule = 1;
+            a.frame_pairs = a.ragged_schedule == 8 ? 1 : 0;
+        } else {
+            a.ragged_schedule = 1;
+        }
     }
     a.vol_stride = a.quad ? L.vol_stride_q : L.vol_stride;
     a.disp_wta = disp_wta;

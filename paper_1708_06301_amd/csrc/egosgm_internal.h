@@ -48,6 +48,8 @@ struct SgmLaunch {
     int wide_offsets;        // 1: LDS scanlines keep 64-bit addresses even where 32-bit offsets fit
     int quad;                // ragged windows in the frame slot layout of the grouped kernels
                              // (schedules 4, 5): lanes per scanline G (frames of 2G slots), or 0
+    int frame_pairs;         // 1: narrow frames of 16 slots on even bases (schedule 8);
+                             // 0: frames of 2G slots on bases that are multiples of 4
     uint8_t* cost;           // matching cost per search slot
     uint32_t* key_r;         // w*h right-map keys (S << 9 | d), cleared by the census pass
     uint64_t* meta;          // w*h packed windows (offset | lo << 32 | width << 48), written by

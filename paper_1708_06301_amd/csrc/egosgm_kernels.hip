@@ -1113,20 +1113,21 @@ struct Frame {
     int base, span;
     bool narrow;
 };
-__device__ inline Frame frame_of(int lo, int w, int F) {
-    const int bn = lo > 0 ? ((lo - 1) & ~3) : 0;
+__device__ inline Frame frame_of(int lo, int w, int F, bool pairs = false) {
+    const int bn = lo > 0 ? ((lo - 1) & (pairs ? ~1 : ~3)) : 0;
     if (lo - bn + w + 1 <= F) return Frame{bn, F, true};
     const int bw = lo & ~15;
     return Frame{bw, ((lo + w + 15) & ~15) - bw, false};
 }
-// Byte offset of pixel p's frame in a volume of n pixels: narrow frames in a
-// dense first region, 32 bytes per pixel (a frame never shares a line with a
-// pixel it does not neighbour); wide spans after it, each on a 128-byte line
-// boundary at the window offset plus 163 bytes per pixel rounded up, so two
-// spans never overlap (consecutive ones are at least w + 36 apart, a span is
-// at most w + 30) and a span of 256 slots is two whole lines.
-__device__ inline uint32_t frame_off(bool narrow, uint32_t off, uint32_t p, uint32_t n) {
-    return narrow ? 32u * p : ((32u * n + 127u) & ~127u) + ((off + 163u * p + 127u) & ~127u);
+// Byte offset of pixel p's frame in a volume of n pixels: narrow frames of F
+// slots (16 or 32) in a dense first region, F bytes per pixel (a frame never
+// shares a line with a pixel it does not neighbour); wide spans after it,
+// each on a 128-byte line boundary at the window offset plus 163 bytes per
+// pixel rounded up, so two spans never overlap (consecutive ones are at least
+// w + 36 apart, a span is at most w + 30) and a span of 256 slots is two
+// whole lines.
+__device__ inline uint32_t frame_off(bool narrow, uint32_t off, uint32_t p, uint32_t n, uint32_t F) {
+    return narrow ? F * p : ((F * n + 127u) & ~127u) + ((off + 163u * p + 127u) & ~127u);
 }
 constexpr uint32_t kPadCost = 255;
 // Costs of two slots (bytes b0 b1 of v, or b2 b3) as a packed pair, with the
@@ -1537,7 +1538,9 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_regroup_kernel(SgmLaunch a, 
         const bool in = (unsigned)(d0 - base) < (hi >> 18);
         f_off[s] = o;
         f_inf[s] = hi | ((uint32_t)in << 31);
-        cst[s] = __builtin_amdgcn_raw_buffer_load_b16(cbuf, o + 2u * (uint32_t)l, 0, 0);
+        // a narrow frame is 16 slots, lanes 0..7; lanes 8..15 take padding markers
+        cst[s] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(cbuf, l < 8 ? o + 2u * (uint32_t)l : kDropWide, 0, 0) |
+                 (l < 8 ? 0u : 0xffffu);
         load_dwords<WD>(cbuf, in ? o + (uint32_t)(d0 - base) : pad_run, wcs[s]);
     };
 #pragma unroll
@@ -1607,7 +1610,7 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_regroup_kernel(SgmLaunch a, 
             m_new = nar ? mn : m;
         }
         __builtin_amdgcn_raw_buffer_store_b16((uint16_t)__builtin_amdgcn_perm(0u, N, 0x0C0C0200u), vbuf,
-                                              nar ? o + 2u * (uint32_t)l : kDropWide, 0, 0);
+                                              nar && l < 8 ? o + 2u * (uint32_t)l : kDropWide, 0, 0);
         if (__builtin_amdgcn_ballot_w64(mc == 2) != 0) {
             if (mc == 2) {
                 const uint32_t prv = __builtin_amdgcn_update_dpp(kInfPk, Wr[NPW - 1], 0x111, 0xF, 0xF, false);
@@ -1689,7 +1692,7 @@ __global__ __launch_bounds__(kBlock) void cost_frame_kernel(SgmLaunch a) {
     __shared__ int s_b[kSeg], s_lo[kSeg], s_w[kSeg];
     __shared__ uint32_t s_q[kSeg];
     const int W = a.w, D = a.win.max_disp;
-    const uint32_t F = 2u * (uint32_t)a.quad;
+    const uint32_t F = a.frame_pairs ? 16u : 2u * (uint32_t)a.quad;
     const int y = blockIdx.y, x0 = blockIdx.x * kSeg;
     const int base = x0 - (D - 1);
     const gmem<const uint64_t>* rowl = gptr(a.census_l + (size_t)y * W);
@@ -1702,8 +1705,8 @@ __global__ __launch_bounds__(kBlock) void cost_frame_kernel(SgmLaunch a) {
             const int lo = gptr(a.win.lo)[p], hi = gptr(a.win.hi)[p];
             const uint32_t off = gptr(a.win.off)[p];
             const int w = hi - lo + 1;
-            const Frame fr = frame_of(lo, w, (int)F);
-            const uint32_t q = frame_off(fr.narrow, off, (uint32_t)p, (uint32_t)W * (uint32_t)a.h);
+            const Frame fr = frame_of(lo, w, (int)F, a.frame_pairs != 0);
+            const uint32_t q = frame_off(fr.narrow, off, (uint32_t)p, (uint32_t)W * (uint32_t)a.h, F);
             // the window word's offset addresses slot lo (q + d - base for slot
             // d), as in the ragged layout, so every path kernel can read it
             gptr(a.meta)[p] = pack_meta(q + (uint32_t)(lo - fr.base), lo, w);
@@ -1865,9 +1868,13 @@ __global__ __launch_bounds__(kBlock) void select_quad_kernel(SgmLaunch a) {
     const int p = y * W + min(x, W - 1);
     const uint64_t mt = gptr(a.meta)[p];
     const int lo = meta_lo(mt), w = meta_w(mt);
-    const uint32_t q = meta_off(mt) - (uint32_t)(lo & 3);   // slot B
-    const int B = lo & ~3;
-    const int span = ((lo + w + 3) & ~3) - B;
+    // B: the last slot at or below lo that is a whole number of quads from
+    // the base of the pixel's frame or span (so its address is dword aligned;
+    // 16-slot frames have even bases, the others multiples of 4)
+    const int fb = frame_of(lo, w, a.frame_pairs ? 16 : 2 * a.quad, a.frame_pairs != 0).base;
+    const int B = fb + ((lo - fb) & ~3);
+    const uint32_t q = meta_off(mt) - (uint32_t)(lo - B);   // slot B
+    const int span = (lo + w - B + 3) & ~3;
     const bool nar = span <= 16;
     if (in_row && nar) {
         const int d = B + 4 * jq;
@@ -1902,8 +1909,9 @@ __global__ __launch_bounds__(kBlock) void select_quad_kernel(SgmLaunch a) {
         for (int k2 = 0; k2 < 4 && wbits; ++k2) wbits &= wbits - 1;
         const int lo_g = __builtin_amdgcn_ds_bpermute(bit << 2, lo), w_g = __builtin_amdgcn_ds_bpermute(bit << 2, w);
         const uint32_t q_g = (uint32_t)__builtin_amdgcn_ds_bpermute(bit << 2, (int)q);
+        const int Bg = __builtin_amdgcn_ds_bpermute(bit << 2, B);
         const int ig = 16 * wv + (bit >> 2), xg = x0 + ig;
-        const int Bg = lo_g & ~3, Eg = (lo_g + w_g + 3) & ~3;
+        const int Eg = Bg + ((lo_g + w_g - Bg + 3) & ~3);
         const int d0 = Bg + 16 * l16;
         const bool any = has && d0 < Eg;
         u32x4 v[NPATH];
@@ -2601,7 +2609,7 @@ hipError_t launch_census_pair(const uint8_t* left, const uint8_t* right, int w, 
 }
 
 size_t quad_volume_bytes(int w, int h, int D) {
-    // 32 bytes per pixel of narrow frames, then the line-aligned wide spans
+    // at most 32 bytes per pixel of narrow frames, then the line-aligned wide spans
     // (below w*h*(D + 163) + 512 bytes), then 64 marker bytes; below the drop offset
     const unsigned long long n = (unsigned long long)w * (unsigned long long)h;
     const unsigned long long a = (32ull * n + 127ull) & ~127ull;
