@@ -1094,21 +1094,22 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_ragged_kernel(SgmLaunch a, i
 }
 
 // ------------------------------------------------------------------ grouped scanlines
-// Frame slot layout (ragged windows on the grouped kernels, frames of F <= 32
-// slots).  Pixel p with window [lo, lo+w) owns the slots of disparities
-// base .. base + span - 1 from byte offset q(p) = (off(p) + 35 p + 3) & ~3 of
-// each volume (costs and path costs):
+// Frame slot layout (ragged windows on the grouped kernels, frames of F = 16
+// or 32 slots).  Pixel p with window [lo, lo+w) owns the slots of
+// disparities base .. base + span - 1 of each volume (costs and path costs):
 //  - narrow (the window and its two neighbours, [lo-1, lo+w], fit F slots
-//    from base = (lo-1) & ~3, or 0 when lo = 0): one frame, span = F;
-//  - wide (otherwise): base = lo & ~15, span = roundup16(lo + w) - base.
-// q(p) is a multiple of 4 and q(p+1) - q(p) >= w + 32 >= span (a wide span is
-// at most w + 30), so a lane reads and writes whole aligned pairs, quads or
-// 16-slot pieces.  Slots of [base, base+span) outside the window are
-// padding: their cost byte is the marker 255 (a real cost is at most 62),
-// which the path kernels turn into +infinity, and their path costs are
-// never read as results.  The window word holds the address of slot lo,
-// q(p) + lo - base, as in the ragged layout.  A volume needs at most
-// w*h*(D+35) + 64 bytes.
+//    from base = (lo-1) rounded down to an even number (16-slot frames of
+//    schedule 8) or to a multiple of 4 (the others), base = 0 when lo = 0):
+//    one frame, span = F, at byte offset q(p) = F p in a dense first region;
+//  - wide (otherwise): base = lo & ~15, span = roundup16(lo + w) - base, on a
+//    128-byte line in a second region (frame_off below).
+// Every frame and span starts on a dword, so a lane reads and writes whole
+// aligned pairs, quads of slots base + 4k, or 16-slot pieces.  Slots of
+// [base, base+span) outside the window are padding: their cost byte is the
+// marker 255 (a real cost is at most 62), which the path kernels turn into
+// +infinity, and their path costs are never read as results.  The window
+// word holds the address of slot lo, q(p) + lo - base, as in the ragged
+// layout.  A volume needs at most w*h*(D+195) + 1 KB (quad_volume_bytes).
 struct Frame {
     int base, span;
     bool narrow;
