@@ -180,7 +180,7 @@ int run_sgm(const uint8_t* left, const uint8_t* right, int w, int h, int pitch, 
     a.meta = reinterpret_cast<uint64_t*>(base + L.meta);
     a.frame = reinterpret_cast<uint64_t*>(base + L.frame);
     a.vol = base + L.vol;
-    // grouped scanlines (schedules 4, 5) need the quad layout; where its
+    // grouped scanlines (schedules 4-8) need the frame layout; where its
     // offsets would not fit 32 bits the rows-on-registers schedule runs instead
     a.quad = 0;
     a.frame_pairs = 0;

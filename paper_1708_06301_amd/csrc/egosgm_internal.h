@@ -47,7 +47,8 @@ struct SgmLaunch {
                              // 3: relative registers, 4/5: grouped scanlines (8/16 lanes, quad layout)
     int wide_offsets;        // 1: LDS scanlines keep 64-bit addresses even where 32-bit offsets fit
     int quad;                // ragged windows in the frame slot layout of the grouped kernels
-                             // (schedules 4, 5): lanes per scanline G (frames of 2G slots), or 0
+                             // (schedules 4-8): lanes per scanline G (frames of 2G slots unless
+                             // frame_pairs), or 0
     int frame_pairs;         // 1: narrow frames of 16 slots on even bases (schedule 8);
                              // 0: frames of 2G slots on bases that are multiples of 4
     uint8_t* cost;           // matching cost per search slot

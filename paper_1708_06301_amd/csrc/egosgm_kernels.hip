@@ -1456,12 +1456,14 @@ __global__ __launch_bounds__(kBlock) void sgm_paths_hybrid_kernel(SgmLaunch a, G
 }
 
 // Register-resident grouped scanlines (ragged windows, frame layout with
-// F = 32; schedule 8).  A wave walks four scanlines of one direction, lane
-// group g (16 lanes, one DPP row) owning scanline g.  The previous pixel's
-// path costs stay in registers, in one of two forms:
+// 16-slot frames on even bases; schedule 8).  A wave walks four scanlines of
+// one direction, lane group g (16 lanes, one DPP row) owning scanline g.  The
+// previous pixel's path costs stay in registers, in one of two forms:
 //  - narrow: one packed pair per lane, slots base + 2l, base + 2l + 1 of the
-//    pixel's frame (the window and its two neighbours lie inside it, so the
-//    frame edges never need a value from outside);
+//    pixel's frame in lanes 0..7 (the window and its two neighbours lie
+//    inside it, so the frame edges never need a value from outside); lanes
+//    8..15 take padding costs, so their values stay above every path cost
+//    + P2 and act as +infinity when a moved frame shifts them in;
 //  - wide: NPW = DMAX/32 packed pairs per lane, the absolute slots
 //    2*NPW*l .. 2*NPW*l + 2*NPW - 1 (the full range, as the full-range
 //    kernel holds it), +infinity outside the window.
@@ -1773,7 +1775,8 @@ __global__ __launch_bounds__(kBlock) void cost_frame_kernel(SgmLaunch a) {
 // Selection in the quad layout (same results as select_segment).  One block
 // per 64-pixel row segment, wave v taking pixels 16v .. 16v+15: a pixel whose
 // window span fits 16 slots is done by a group of 4 lanes (lane j owning the
-// quad B + 4j), the wider ones four at a time by 16-lane groups (lane l
+// quad B + 4j, B the last slot at or below lo a whole number of quads from
+// the frame's base), the wider ones four at a time by 16-lane groups (lane l
 // owning the four quads B + 16l ..).  S is summed from the path volumes a dword (four slots) per
 // direction and lane; the winner key (S << 9 | d) is a minimum over the
 // group; the pixel's S row is staged in LDS for the parabola and the
