@@ -209,29 +209,32 @@ __device__ inline void finish_level_step(const double (&sum)[kVoTerms], double* 
     if (count < 16.0) return;
     const double lam = 1e-9 * (H[0] + H[7] + H[14] + H[21] + H[28] + H[35]) / 6.0;
     for (int u = 0; u < 6; ++u) H[7 * u] += lam;
-    // Cholesky H = L L^T (lower triangle in place), then L L^T xi = -g
+    // Cholesky H = L L^T (lower triangle in place), then L L^T xi = -g; one
+    // division per column (inv[j] = 1 / L_jj), products elsewhere
+    double inv[6];
     for (int j = 0; j < 6; ++j) {
         double s = H[6 * j + j];
         for (int k = 0; k < j; ++k) s -= H[6 * j + k] * H[6 * j + k];
         if (!(s > 0.0)) return;
         const double ljj = sqrt(s);
         H[6 * j + j] = ljj;
+        inv[j] = 1.0 / ljj;
         for (int i = j + 1; i < 6; ++i) {
             double v = H[6 * i + j];
             for (int k = 0; k < j; ++k) v -= H[6 * i + k] * H[6 * j + k];
-            H[6 * i + j] = v / ljj;
+            H[6 * i + j] = v * inv[j];
         }
     }
     double z[6], xi[6];
     for (int i = 0; i < 6; ++i) {
         double v = -g[i];
         for (int k = 0; k < i; ++k) v -= H[6 * i + k] * z[k];
-        z[i] = v / H[7 * i];
+        z[i] = v * inv[i];
     }
     for (int i = 5; i >= 0; --i) {
         double v = z[i];
         for (int k = i + 1; k < 6; ++k) v -= H[6 * k + i] * xi[k];
-        xi[i] = v / H[7 * i];
+        xi[i] = v * inv[i];
     }
     double Rd[9], td[3];
     se3_exp(xi, Rd, td);
